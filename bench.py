@@ -1,0 +1,170 @@
+#!/usr/bin/env python3
+"""Benchmark of the coupled LBM-FVM step on one MI355X.
+
+Workload: the 512 x 512 side-heated cavity, Ra 1e6, Pr 0.71, FP32
+distributions and temperature, seeded T0 perturbation (uniform +-1e-6).
+One benchmark step is one coupled time step (pull-stream, moments, QUICK FV
+energy update, collision with buoyancy) plus, as in the run-to-steady loop,
+a residual check every 1000 steps and the wall Nusselt numbers at the end.
+
+Prints one JSON line: MLUPS (node updates per second / 1e6) over the timed
+steps, the roofline of the fused step kernel (algorithmic bytes over the
+kernel's mean duration, measured with HIP events on the library's stream),
+and the FP64 CPU oracle timed on this host on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "coupled LBM-FVM MLUPS + %HBM peak; time-to-steady (warm vs cold) at Nu 1e-4"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+BYTES_PER_LU_F32 = 80.0        # 9 f read + 9 f write + T read + T write, 4 B each
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_hybrid_step_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1908_08386_amd", "csrc", "k_hybrid.hip")
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(nx, ny):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when it is missing or was taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha256_16") != kernel_hash() or t.get("nx") != nx or t.get("ny") != ny:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(nx, ny, T0, seconds):
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    used = oracle.set_threads(threads)
+    o = oracle.Case(nx, ny).set_physics(1e6, 0.71).set_cavity_walls().init(T0)
+    o.step(5)
+    t0 = time.perf_counter()
+    steps = 0
+    while time.perf_counter() - t0 < seconds:
+        o.step(10)
+        steps += 10
+    dt = time.perf_counter() - t0
+    return {"value": round(nx * ny * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": used,
+            "kind": "oracle",
+            "sample": f"{nx}x{ny} Ra 1e6 cavity, FP64 oracle (3 plain sweeps/step, OpenMP), "
+                      f"{steps} steps in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=2000)
+    ap.add_argument("--n", type=int, default=512, help="cavity size (n x n)")
+    ap.add_argument("--profile-steps", type=int, default=2000)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--hbm-point", type=int, default=4096,
+                    help="also time the kernel on an n x n cavity whose working set is far "
+                         "larger than the on-die caches (0 = skip)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1908_08386_amd as lf
+    from synth_inputs import SEED_C2, perturbation
+
+    n = args.n
+    T0 = perturbation(n, n, SEED_C2)
+    ctx = lf.Context(0)
+    c = lf.Case(ctx, n, n, "f32").set_physics(1e6, 0.71).set_cavity_walls().init(T0)
+
+    def run(k):
+        done = 0
+        while done < k:
+            m = min(1000, k - done)
+            c.step(m)
+            done += m
+            if m == 1000:
+                c.residual()
+
+    run(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(args.steps)
+    nu = c.nusselt()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    mlups = n * n * args.steps / dt / 1e6
+
+    avg_ms, min_ms, max_ms = c.profile_steps(args.profile_steps)
+    bytes_launch = BYTES_PER_LU_F32 * n * n
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(n, n)
+
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": f"synthetic: T0 = 1e-6 (2U - 1), U from splitmix64 seed {SEED_C2}, u0 = 0",
+        "config": {"workload": f"{n}x{n} side-heated cavity, Ra 1e6, Pr 0.71, FP32, "
+                               "coupled D2Q9 BGK + QUICK FV energy (Mode H)",
+                   "nx": n, "ny": n, "Ra": 1e6, "Pr": 0.71, "U_char": c.params()["U_char"],
+                   "residual_every": 1000, "nu_hot_end": round(nu["nu_hot"], 6)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "k_hybrid_step<float>",
+                     "kernel_ms_avg": round(avg_ms, 6), "kernel_ms_min": round(min_ms, 6),
+                     "bytes_per_launch": bytes_launch,
+                     "note": "512^2 FP32 working set (21 MB) is resident in the 256 MB "
+                             "Infinity Cache; see roofline_hbm for an HBM-bound size"},
+    }
+    del c
+
+    if args.hbm_point:
+        m = args.hbm_point
+        big = lf.Case(ctx, m, m, "f32").set_physics(1e6, 0.71).set_cavity_walls()
+        big.init(perturbation(m, m, SEED_C2))
+        big.step(20)
+        a_ms, lo_ms, _ = big.profile_steps(200)
+        b = BYTES_PER_LU_F32 * m * m
+        ach = b / (a_ms * 1e-3) / 1e9
+        out["roofline_hbm"] = {"bound": "hbm", "workload": f"{m}x{m} cavity FP32 Mode H",
+                               "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": round(ach / HBM_PEAK_GBS, 4),
+                               "traffic": measured_traffic(m, m),
+                               "kernel_ms_avg": round(a_ms, 5), "bytes_per_launch": b,
+                               "mlups": round(m * m / (a_ms * 1e-3) / 1e6, 1)}
+        del big
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(n, n, T0, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

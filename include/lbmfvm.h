@@ -1,0 +1,188 @@
+/*
+ * lbmfvm.h -- C ABI of the MI355X (gfx950) hybrid lattice-Boltzmann /
+ * finite-volume natural-convection library.
+ *
+ * Method: Li, Yang & Zhang, "Hybrid LBM-FVM and LBM-MCM methods for fluid
+ * flow and heat transfer simulation" (arXiv:1908.08386).
+ *   - Mode H (LF_MODE_HYBRID), Sec. 5: D2Q9 BGK lattice Boltzmann (Eq 4-9,
+ *     Eq 16-18) gives the velocity on the whole cavity; an explicit
+ *     conservative finite-volume energy balance (Eq 24 / Eq 76, QUICK
+ *     convection) gives the temperature on the same cells; the temperature
+ *     acts back through the Boussinesq buoyancy force (Eq 18, Eq 81).
+ *   - Mode DD (LF_MODE_SPLIT), Sec. 4: LBM (D2Q9 flow + D2Q5 heat, Eq 19-23)
+ *     on the west part, FVM on the east part, three shared columns, coupled
+ *     through non-equilibrium extrapolation (Eq 60, Eq 94-95) or the
+ *     finite-difference velocity-gradient reconstruction (Eq 70-72) with the
+ *     density transfer of Eq 91-93.
+ *
+ * Conventions (all entry points):
+ *   - Every call returns lf_status; LF_OK is 0.  On failure
+ *     lf_last_error() returns a thread-local message.  No exception, abort
+ *     or exit crosses the ABI.
+ *   - Handles are opaque; *_destroy(NULL) is a no-op.  Handles are not
+ *     thread-safe: use one ctx per host thread.
+ *   - The library never allocates device memory.  The caller asks for
+ *     *_workspace_bytes and binds a device buffer of at least that size
+ *     (256-byte aligned) with *_bind_workspace; the buffer stays owned by the
+ *     caller and must outlive the handle's use.  Host arrays passed in are
+ *     copied before the call returns.
+ *   - All device work is enqueued on the HIP stream given to lf_ctx_create.
+ *     init, step and fetch into device memory are asynchronous on that
+ *     stream; calls that return host values (residual, nusselt, mass,
+ *     run_to_steady, fetch into host memory, save) synchronise it.
+ *   - Fields are row-major [ny][nx] (index j*nx + i); j = 0 is the bottom
+ *     wall (gravity points to -y), i = 0 the west wall.  Cell (i, j) has its
+ *     centre at (i + 1/2, j + 1/2) lattice units; walls lie on cell faces.
+ *     u, v are lattice velocities; T is in units of the wall temperature
+ *     difference (hot wall +1/2, cold wall -1/2 in the cavity cases).
+ */
+#ifndef LBMFVM_H
+#define LBMFVM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LF_ABI_VERSION 1
+
+typedef enum {
+  LF_OK = 0,
+  LF_EINVAL = 1,      /* bad argument or combination of settings          */
+  LF_ENOMEM = 2,      /* host allocation failed                            */
+  LF_EWORKSPACE = 3,  /* no workspace bound, or it is too small/misaligned */
+  LF_EDEVICE = 4,     /* a HIP call failed                                 */
+  LF_EUNSTABLE = 5,   /* parameters outside the explicit scheme's limits   */
+  LF_EDIVERGED = 6,   /* NaN or Inf found in the fields                    */
+  LF_ENOTCONV = 7,    /* run_to_steady hit max_steps                       */
+  LF_ESTATE = 8,      /* call out of order (e.g. step before init)         */
+  LF_ENOTIMPL = 9
+} lf_status;
+
+enum { LF_F32 = 0, LF_F64 = 1 };
+enum { LF_MODE_HYBRID = 0, LF_MODE_SPLIT = 1 };
+enum { LF_IFACE_NEQ_EXTRAP = 0, LF_IFACE_FD_GRADIENT = 1 };
+enum { LF_CONV_QUICK = 0, LF_CONV_CENTRAL = 1, LF_CONV_UPWIND = 2 };
+enum { LF_WALL_NOSLIP = 0, LF_WALL_PERIODIC = 1 };
+enum { LF_T_DIRICHLET = 0, LF_T_ADIABATIC = 1, LF_T_PERIODIC = 2 };
+enum { LF_SIDE_W = 0, LF_SIDE_E = 1, LF_SIDE_S = 2, LF_SIDE_N = 3 };
+enum { LF_FIELD_U = 0, LF_FIELD_V = 1, LF_FIELD_T = 2, LF_FIELD_RHO = 3 };
+/* run_to_steady stop rules (r_final[3] of lf_case_run_to_steady)          */
+enum { LF_STOP_TOL = 1, LF_STOP_FLOOR = 2 };
+
+typedef struct lf_ctx lf_ctx;
+typedef struct lf_case lf_case;
+
+/* Case geometry and numerics.  nx, ny >= 8.  Mode DD needs nx even and
+ * split_col / overlap as documented in lf_case_create.                     */
+typedef struct {
+  int nx, ny;
+  int precision; /* LF_F32 or LF_F64                                        */
+  int mode;      /* LF_MODE_HYBRID or LF_MODE_SPLIT                         */
+  int split_col; /* Mode DD: first FV cell is split_col - 1; 0 => nx/2      */
+  int overlap;   /* Mode DD: shared columns; 0 => 3 (the only value)        */
+  int iface;     /* Mode DD: LF_IFACE_NEQ_EXTRAP or LF_IFACE_FD_GRADIENT    */
+} lf_case_desc;
+
+/* Physical groups (Eq 82-89).  Ra > 0, Pr > 0.  U_char is the buoyancy
+ * velocity sqrt(g beta dT H) in lattice units; 0 selects 0.1, lowered where
+ * the explicit updates need it (alpha <= 0.2, U^2 <= 2 alpha; Mode DD also
+ * nu <= 0.2).  T_ref NaN selects 0 (the mid value of walls at +-1/2).
+ * body_gx, body_gy add a constant body acceleration (test hook).           */
+typedef struct {
+  double Ra, Pr, U_char, T_ref;
+  int conv; /* LF_CONV_QUICK (default), LF_CONV_CENTRAL, LF_CONV_UPWIND */
+  double body_gx, body_gy;
+} lf_physics;
+
+/* One side of the box.  vel: LF_WALL_NOSLIP (half-way bounce-back; u_wall
+ * is the tangential wall speed) or LF_WALL_PERIODIC (both opposite sides).
+ * thermal: LF_T_DIRICHLET (T = T_wall), LF_T_ADIABATIC, or LF_T_PERIODIC
+ * (together with vel periodic).                                            */
+typedef struct {
+  int vel;
+  double u_wall;
+  int thermal;
+  double T_wall;
+} lf_wall;
+
+/* Nusselt numbers of the west (hot) and east (cold) walls, Eq 90 with
+ * X = x / ny: nu(j) = 2 ny (T_w - T_edge) / dT (half-cell wall flux);
+ * *_max and their heights y = (j + 1/2) / ny (ties: lowest j); *_o2 the
+ * wall-averaged second-order one-sided gradient through T_w and the first
+ * two cell centres.  dT = T_W - T_E (1 when equal).                        */
+typedef struct {
+  double nu_hot, nu_cold, nu_hot_max, y_hot_max, nu_cold_max, y_cold_max,
+      nu_hot_o2, nu_cold_o2;
+} lf_nusselt;
+
+/* ---- library ---------------------------------------------------------- */
+int lf_abi_version(void);
+const char* lf_last_error(void);
+
+/* Context: a HIP device and a stream (hipStream_t, NULL = default stream),
+ * e.g. torch.cuda.current_stream().cuda_stream.                            */
+lf_status lf_ctx_create(int hip_device, void* hip_stream, lf_ctx** out);
+lf_status lf_ctx_destroy(lf_ctx* ctx);
+/* Rows each wavefront marches through in the fused step (0 = automatic). */
+lf_status lf_ctx_set_band(lf_ctx* ctx, int rows);
+
+/* ---- single cavity ---------------------------------------------------- */
+/* Mode H: the whole cavity is LBM velocity + FV temperature (Sec. 5.1,
+ * grid setting 1).  Defaults after create: side-heated cavity walls (west
+ * T = +1/2, east T = -1/2, south/north adiabatic, all no-slip at rest).    */
+lf_status lf_case_create(lf_ctx* ctx, const lf_case_desc* desc, lf_case** out);
+lf_status lf_case_destroy(lf_case* c);
+lf_status lf_case_workspace_bytes(const lf_case* c, size_t* bytes);
+lf_status lf_case_bind_workspace(lf_case* c, void* dev_ptr, size_t bytes);
+/* Derive the lattice parameters from Ra, Pr (Eq 15, 20, 42, 82-89);
+ * LF_EUNSTABLE if tau <= 0.501 or alpha > 0.25.                            */
+lf_status lf_case_set_physics(lf_case* c, const lf_physics* p);
+/* Lattice parameters directly (Ra = 0 cases, closed-form tests).          */
+lf_status lf_case_set_lattice(lf_case* c, double nu, double alpha,
+                              double gbeta, double T_ref, double body_gx,
+                              double body_gy, int conv);
+lf_status lf_case_set_wall(lf_case* c, int side, const lf_wall* w);
+/* out = {U_char, nu, tau, alpha, tau_T, g beta, T_ref, Ma}               */
+lf_status lf_case_get_params(const lf_case* c, double out[8]);
+/* Initial state from host arrays of ny*nx doubles (NULL = 0): rho = 1,
+ * f = f_eq(1, (u0, v0)), T = T0; the residual snapshot starts here.        */
+lf_status lf_case_init(lf_case* c, const double* T0, const double* u0,
+                       const double* v0);
+/* Advance nsteps time steps (asynchronous).                               */
+lf_status lf_case_step(lf_case* c, int64_t nsteps);
+/* r = ||phi - phi_snap||_2 / ||phi||_2 for phi = u, v, T against the last
+ * snapshot (absolute when ||phi|| < 1e-300), then re-snapshot.
+ * LF_EDIVERGED on NaN/Inf.                                                */
+lf_status lf_case_residual(lf_case* c, double r[3]);
+/* Step in blocks of check_every until max r <= tol (or all r = 0); in FP32
+ * also stop "at the rounding floor" when max r <= 1e-6 and it fell by less
+ * than 10 % over 3 consecutive checks.  r_final receives the last r;
+ * *rule (may be NULL) LF_STOP_TOL or LF_STOP_FLOOR.  LF_ENOTCONV at
+ * max_steps.                                                              */
+lf_status lf_case_run_to_steady(lf_case* c, double tol, int check_every,
+                                int64_t max_steps, int64_t* steps_taken,
+                                double r_final[3], int* rule);
+lf_status lf_case_nusselt(lf_case* c, lf_nusselt* out);
+/* Copy a field (LF_FIELD_*) as ny*nx values into dst (device or host),
+ * as double (as_f64 = 1) or in the case precision.                        */
+lf_status lf_case_fetch(lf_case* c, int field, void* dst, size_t dst_bytes,
+                        int dst_is_device, int as_f64);
+/* Invariants: sum over all nodes and directions of the post-collision
+ * populations, and sum of T.                                              */
+lf_status lf_case_mass(lf_case* c, double* sum_f, double* sum_T);
+/* Steps taken since init.                                                 */
+lf_status lf_case_steps(const lf_case* c, int64_t* steps);
+/* Advance nsteps (1 .. 2^20) steps with a pair of HIP events around every
+ * step kernel on the context stream, synchronising after each; returns the
+ * mean, min and max kernel time in milliseconds (min/max may be NULL).
+ * Same result as lf_case_step; for measurement only.                      */
+lf_status lf_case_profile_steps(lf_case* c, int64_t nsteps, double* avg_ms,
+                                double* min_ms, double* max_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBMFVM_H */

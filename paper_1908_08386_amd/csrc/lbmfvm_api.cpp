@@ -1,0 +1,515 @@
+// lbmfvm_api.cpp -- host runtime behind the C ABI of include/lbmfvm.h.
+//
+// Owns no device memory: every case lays its state out inside the workspace
+// the caller binds.  All device work goes to the context's stream.
+#include <math.h>
+#include <stdio.h>
+#include <stdarg.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "../../include/lbmfvm.h"
+#include "lf_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+lf_status fail(lf_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+#define HIP_TRY(expr)                                                        \
+  do {                                                                       \
+    hipError_t e_ = (expr);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      return fail(LF_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));       \
+  } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct lf_ctx {
+  int device;
+  hipStream_t stream;
+  int band;  // 0: automatic
+};
+
+struct lf_case {
+  lf_ctx* ctx;
+  lf_case_desc desc;
+  size_t es;  // bytes per element
+  lf::Grid g;
+  lf::WallSet w;
+  lf::HybridParams p;
+  double params[8];
+  bool have_params;
+  char* ws;
+  size_t ws_bytes;
+  size_t off_f[2], off_T[2], off_mom, off_snap, off_part, off_out, off_stage, need;
+  int nblk;  // blocks of the reduction passes
+  int cur;   // buffer holding the current state
+  int64_t steps;
+  bool inited;
+};
+
+template <typename real>
+static real* fptr(lf_case* c, size_t off) { return (real*)(c->ws + off); }
+
+extern "C" {
+
+int lf_abi_version(void) { return LF_ABI_VERSION; }
+const char* lf_last_error(void) { return g_err; }
+
+lf_status lf_ctx_create(int hip_device, void* hip_stream, lf_ctx** out) {
+  if (!out) return fail(LF_EINVAL, "out is NULL");
+  int n = 0;
+  HIP_TRY(hipGetDeviceCount(&n));
+  if (hip_device < 0 || hip_device >= n)
+    return fail(LF_EINVAL, "device %d out of range (%d devices)", hip_device, n);
+  HIP_TRY(hipSetDevice(hip_device));
+  lf_ctx* c = new (std::nothrow) lf_ctx;
+  if (!c) return fail(LF_ENOMEM, "ctx allocation");
+  c->device = hip_device;
+  c->stream = (hipStream_t)hip_stream;
+  c->band = 0;
+  *out = c;
+  return LF_OK;
+}
+
+lf_status lf_ctx_destroy(lf_ctx* ctx) {
+  delete ctx;
+  return LF_OK;
+}
+
+lf_status lf_ctx_set_band(lf_ctx* ctx, int rows) {
+  if (!ctx || rows < 0 || rows > 4096) return fail(LF_EINVAL, "band must be in [0, 4096]");
+  ctx->band = rows;
+  return LF_OK;
+}
+
+static void layout(lf_case* c) {
+  const lf::Grid& g = c->g;
+  const size_t pb = align_up((size_t)g.plane * c->es, 256);
+  size_t o = 0;
+  c->off_f[0] = o; o += 9 * pb;
+  c->off_f[1] = o; o += 9 * pb;
+  c->off_T[0] = o; o += pb;
+  c->off_T[1] = o; o += pb;
+  c->off_mom = o; o += 3 * pb;
+  c->off_snap = o; o += 3 * pb;
+  c->off_part = o; o += align_up((size_t)c->nblk * 8 * sizeof(double), 256);
+  c->off_out = o; o += 256 * sizeof(double);
+  c->off_stage = o; o += align_up((size_t)3 * g.nx * g.ny * sizeof(double), 256);
+  c->need = o;
+}
+
+lf_status lf_case_create(lf_ctx* ctx, const lf_case_desc* d, lf_case** out) {
+  if (!ctx || !d || !out) return fail(LF_EINVAL, "NULL argument");
+  if (d->nx < 8 || d->ny < 8) return fail(LF_EINVAL, "nx, ny must be >= 8 (got %d, %d)", d->nx, d->ny);
+  if (d->precision != LF_F32 && d->precision != LF_F64)
+    return fail(LF_EINVAL, "precision must be LF_F32 or LF_F64");
+  if (d->mode != LF_MODE_HYBRID) return fail(LF_ENOTIMPL, "mode %d not available", d->mode);
+  const long long pitch = (d->nx + 63) / 64 * 64;
+  const long long plane = pitch * d->ny;
+  if (9 * plane >= (1LL << 31)) return fail(LF_EINVAL, "grid too large for 32-bit plane indexing");
+  lf_case* c = new (std::nothrow) lf_case;
+  if (!c) return fail(LF_ENOMEM, "case allocation");
+  memset(c, 0, sizeof(*c));
+  c->ctx = ctx;
+  c->desc = *d;
+  c->es = d->precision == LF_F64 ? 8 : 4;
+  c->g.nx = d->nx;
+  c->g.ny = d->ny;
+  c->g.pitch = (int)pitch;
+  c->g.plane = plane;
+  c->nblk = d->ny < 1024 ? d->ny : 1024;
+  // default: side-heated cavity
+  c->w.xper = c->w.yper = 0;
+  c->w.tfix[LF_SIDE_W] = 1; c->w.Tw[LF_SIDE_W] = 0.5;
+  c->w.tfix[LF_SIDE_E] = 1; c->w.Tw[LF_SIDE_E] = -0.5;
+  c->p.omega = 1.0;
+  layout(c);
+  *out = c;
+  return LF_OK;
+}
+
+lf_status lf_case_destroy(lf_case* c) {
+  delete c;
+  return LF_OK;
+}
+
+lf_status lf_case_workspace_bytes(const lf_case* c, size_t* bytes) {
+  if (!c || !bytes) return fail(LF_EINVAL, "NULL argument");
+  *bytes = c->need;
+  return LF_OK;
+}
+
+lf_status lf_case_bind_workspace(lf_case* c, void* dev_ptr, size_t bytes) {
+  if (!c || !dev_ptr) return fail(LF_EINVAL, "NULL argument");
+  if (bytes < c->need) return fail(LF_EWORKSPACE, "workspace %zu bytes < %zu needed", bytes, c->need);
+  if ((uintptr_t)dev_ptr % 256) return fail(LF_EWORKSPACE, "workspace must be 256-byte aligned");
+  c->ws = (char*)dev_ptr;
+  c->ws_bytes = bytes;
+  c->inited = false;
+  return LF_OK;
+}
+
+static lf_status check_stable(double tau, double alpha) {
+  if (!(tau > 0.501)) return fail(LF_EUNSTABLE, "tau = %.6g must exceed 0.501", tau);
+  if (!(alpha >= 0.0 && alpha <= 0.25))
+    return fail(LF_EUNSTABLE, "alpha = %.6g outside [0, 0.25] (explicit 2-D diffusion limit)", alpha);
+  return LF_OK;
+}
+
+static lf_status apply_lattice(lf_case* c, double nu, double alpha, double gbeta, double T_ref,
+                               double gx, double gy, int conv) {
+  if (conv < LF_CONV_QUICK || conv > LF_CONV_UPWIND) return fail(LF_EINVAL, "bad conv %d", conv);
+  if (!(nu > 0.0)) return fail(LF_EINVAL, "nu must be > 0");
+  const double tau = 3.0 * nu + 0.5;  // Eq 15 with c_s^2 = 1/3, Eq 42
+  lf_status st = check_stable(tau, alpha);
+  if (st != LF_OK) return st;
+  c->p.omega = 1.0 / tau;
+  c->p.alpha = alpha;
+  c->p.gbeta = gbeta;
+  c->p.T_ref = T_ref;
+  c->p.gx = gx;
+  c->p.gy = gy;
+  c->p.conv = conv;
+  return LF_OK;
+}
+
+lf_status lf_case_set_lattice(lf_case* c, double nu, double alpha, double gbeta, double T_ref,
+                              double gx, double gy, int conv) {
+  if (!c) return fail(LF_EINVAL, "NULL case");
+  lf_status st = apply_lattice(c, nu, alpha, gbeta, T_ref, gx, gy, conv);
+  if (st != LF_OK) return st;
+  c->params[0] = 0.0;
+  c->params[1] = nu;
+  c->params[2] = 3.0 * nu + 0.5;
+  c->params[3] = alpha;
+  c->params[4] = 3.0 * alpha + 0.5;
+  c->params[5] = gbeta;
+  c->params[6] = T_ref;
+  c->params[7] = 0.0;
+  c->have_params = true;
+  return LF_OK;
+}
+
+lf_status lf_case_set_physics(lf_case* c, const lf_physics* ph) {
+  if (!c || !ph) return fail(LF_EINVAL, "NULL argument");
+  if (!(ph->Ra > 0.0) || !(ph->Pr > 0.0)) return fail(LF_EINVAL, "Ra and Pr must be > 0");
+  const double H = (double)c->g.ny;
+  double U = ph->U_char;
+  if (!(U > 0.0)) {
+    // buoyancy velocity sqrt(g beta dT H) in lattice units: 0.1 unless the
+    // explicit updates need less (alpha <= 0.2, U^2 <= 2 alpha)
+    U = 0.1;
+    const double ua = 0.2 * sqrt(ph->Ra * ph->Pr) / H;
+    if (ua < U) U = ua;
+    if (c->desc.mode == LF_MODE_SPLIT) {
+      const double un = 0.2 * sqrt(ph->Ra / ph->Pr) / H;
+      if (un < U) U = un;
+    }
+    const double ud = 2.0 * H / sqrt(ph->Ra * ph->Pr);
+    if (ud < U) U = ud;
+  }
+  // Eq 87-89 in lattice units: nu = U H sqrt(Pr/Ra), alpha = nu / Pr,
+  // g beta dT = U^2 / H with dT = 1
+  const double nu = U * H * sqrt(ph->Pr / ph->Ra);
+  const double alpha = nu / ph->Pr;
+  const double gbeta = U * U / H;
+  const double T_ref = isnan(ph->T_ref) ? 0.0 : ph->T_ref;
+  lf_status st = apply_lattice(c, nu, alpha, gbeta, T_ref, ph->body_gx, ph->body_gy, ph->conv);
+  if (st != LF_OK) return st;
+  c->params[0] = U;
+  c->params[1] = nu;
+  c->params[2] = 3.0 * nu + 0.5;
+  c->params[3] = alpha;
+  c->params[4] = 3.0 * alpha + 0.5;
+  c->params[5] = gbeta;
+  c->params[6] = T_ref;
+  c->params[7] = U * sqrt(3.0);  // Ma = U / c_s (Eq 84)
+  c->have_params = true;
+  return LF_OK;
+}
+
+lf_status lf_case_set_wall(lf_case* c, int side, const lf_wall* w) {
+  if (!c || !w) return fail(LF_EINVAL, "NULL argument");
+  if (side < LF_SIDE_W || side > LF_SIDE_N) return fail(LF_EINVAL, "bad side %d", side);
+  const bool per = w->vel == LF_WALL_PERIODIC;
+  if (w->vel != LF_WALL_NOSLIP && !per) return fail(LF_EINVAL, "bad vel %d", w->vel);
+  if (per != (w->thermal == LF_T_PERIODIC))
+    return fail(LF_EINVAL, "periodic velocity and periodic temperature go together");
+  if (!per && w->thermal != LF_T_DIRICHLET && w->thermal != LF_T_ADIABATIC)
+    return fail(LF_EINVAL, "bad thermal %d", w->thermal);
+  const int other = side ^ 1;  // W<->E, S<->N
+  const bool axis_per = side < 2 ? c->w.xper : c->w.yper;
+  // periodicity is a property of the axis: it is switched on/off for both sides
+  if (per) {
+    if (side < 2) c->w.xper = 1; else c->w.yper = 1;
+    c->w.uw[side] = c->w.uw[other] = 0.0;
+    c->w.tfix[side] = c->w.tfix[other] = 0;
+  } else {
+    if (axis_per) {
+      if (side < 2) c->w.xper = 0; else c->w.yper = 0;
+    }
+    c->w.uw[side] = w->u_wall;
+    c->w.tfix[side] = w->thermal == LF_T_DIRICHLET;
+    c->w.Tw[side] = w->T_wall;
+  }
+  return LF_OK;
+}
+
+lf_status lf_case_get_params(const lf_case* c, double out[8]) {
+  if (!c || !out) return fail(LF_EINVAL, "NULL argument");
+  if (!c->have_params) return fail(LF_ESTATE, "no parameters set");
+  memcpy(out, c->params, sizeof(c->params));
+  return LF_OK;
+}
+
+lf_status lf_case_init(lf_case* c, const double* T0, const double* u0, const double* v0) {
+  if (!c) return fail(LF_EINVAL, "NULL case");
+  if (!c->ws) return fail(LF_EWORKSPACE, "no workspace bound");
+  hipStream_t s = c->ctx->stream;
+  const size_t n = (size_t)c->g.nx * c->g.ny;
+  double* st = (double*)(c->ws + c->off_stage);
+  const double* dT = nullptr; const double* du = nullptr; const double* dv = nullptr;
+  if (T0) { HIP_TRY(hipMemcpyAsync(st, T0, n * 8, hipMemcpyHostToDevice, s)); dT = st; }
+  if (u0) { HIP_TRY(hipMemcpyAsync(st + n, u0, n * 8, hipMemcpyHostToDevice, s)); du = st + n; }
+  if (v0) { HIP_TRY(hipMemcpyAsync(st + 2 * n, v0, n * 8, hipMemcpyHostToDevice, s)); dv = st + 2 * n; }
+  c->cur = 0;
+  if (c->desc.precision == LF_F32) {
+    HIP_TRY(lf::launch_init<float>(c->g, dT, du, dv, fptr<float>(c, c->off_f[0]),
+                                   fptr<float>(c, c->off_T[0]), fptr<float>(c, c->off_mom),
+                                   fptr<float>(c, c->off_snap), s));
+  } else {
+    HIP_TRY(lf::launch_init<double>(c->g, dT, du, dv, fptr<double>(c, c->off_f[0]),
+                                    fptr<double>(c, c->off_T[0]), fptr<double>(c, c->off_mom),
+                                    fptr<double>(c, c->off_snap), s));
+  }
+  // the host arrays may be freed on return: wait for the uploads
+  HIP_TRY(hipStreamSynchronize(s));
+  c->steps = 0;
+  c->inited = true;
+  return LF_OK;
+}
+
+static int auto_band(const lf_case* c) {
+  if (c->ctx->band > 0) return c->ctx->band;
+  // aim for >= 4096 waves (16 per CU) while keeping the two halo rows of a
+  // band small against its height
+  const long long strips = (c->g.nx + 61) / 62;
+  long long band = 64;
+  while (band > 4 && strips * ((c->g.ny + band - 1) / band) < 4096) band /= 2;
+  return (int)band;
+}
+
+}  // extern "C"
+
+template <typename real>
+static lf_status step_impl(lf_case* c, int64_t n, hipEvent_t* ev = nullptr, float* ms = nullptr) {
+  hipStream_t s = c->ctx->stream;
+  const int band = auto_band(c);
+  for (int64_t k = 0; k < n; ++k) {
+    const int a = c->cur, b = a ^ 1;
+    real* mom = (k == n - 1) ? fptr<real>(c, c->off_mom) : nullptr;
+    if (ev) HIP_TRY(hipEventRecord(ev[0], s));
+    HIP_TRY(lf::launch_hybrid_step<real>(c->g, c->w, c->p, fptr<real>(c, c->off_f[a]),
+                                         fptr<real>(c, c->off_f[b]), fptr<real>(c, c->off_T[a]),
+                                         fptr<real>(c, c->off_T[b]), mom, band, s));
+    if (ev) {
+      HIP_TRY(hipEventRecord(ev[1], s));
+      HIP_TRY(hipEventSynchronize(ev[1]));
+      HIP_TRY(hipEventElapsedTime(&ms[k], ev[0], ev[1]));
+    }
+    c->cur = b;
+  }
+  c->steps += n;
+  return LF_OK;
+}
+
+extern "C" {
+
+lf_status lf_case_step(lf_case* c, int64_t nsteps) {
+  if (!c) return fail(LF_EINVAL, "NULL case");
+  if (nsteps < 0) return fail(LF_EINVAL, "nsteps < 0");
+  if (!c->inited) return fail(LF_ESTATE, "init before step");
+  if (!c->have_params) return fail(LF_ESTATE, "set_physics or set_lattice before step");
+  if (nsteps == 0) return LF_OK;
+  return c->desc.precision == LF_F32 ? step_impl<float>(c, nsteps) : step_impl<double>(c, nsteps);
+}
+
+lf_status lf_case_profile_steps(lf_case* c, int64_t nsteps, double* avg_ms, double* min_ms,
+                                double* max_ms) {
+  if (!c || !avg_ms) return fail(LF_EINVAL, "NULL argument");
+  if (nsteps < 1 || nsteps > (1 << 20)) return fail(LF_EINVAL, "nsteps must be in [1, 2^20]");
+  if (!c->inited) return fail(LF_ESTATE, "init before step");
+  if (!c->have_params) return fail(LF_ESTATE, "set_physics or set_lattice before step");
+  std::vector<float> ms((size_t)nsteps, 0.0f);
+  hipEvent_t ev[2];
+  HIP_TRY(hipEventCreate(&ev[0]));
+  if (hipEventCreate(&ev[1]) != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return fail(LF_EDEVICE, "hipEventCreate");
+  }
+  lf_status st = c->desc.precision == LF_F32 ? step_impl<float>(c, nsteps, ev, ms.data())
+                                              : step_impl<double>(c, nsteps, ev, ms.data());
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (st != LF_OK) return st;
+  double sum = 0.0, lo = 1e300, hi = 0.0;
+  for (float v : ms) {
+    sum += v;
+    lo = v < lo ? v : lo;
+    hi = v > hi ? v : hi;
+  }
+  *avg_ms = sum / (double)nsteps;
+  if (min_ms) *min_ms = lo;
+  if (max_ms) *max_ms = hi;
+  return LF_OK;
+}
+
+lf_status lf_case_steps(const lf_case* c, int64_t* steps) {
+  if (!c || !steps) return fail(LF_EINVAL, "NULL argument");
+  *steps = c->steps;
+  return LF_OK;
+}
+
+lf_status lf_case_residual(lf_case* c, double r[3]) {
+  if (!c || !r) return fail(LF_EINVAL, "NULL argument");
+  if (!c->inited) return fail(LF_ESTATE, "init first");
+  hipStream_t s = c->ctx->stream;
+  double* out = (double*)(c->ws + c->off_out);
+  double* part = (double*)(c->ws + c->off_part);
+  if (c->desc.precision == LF_F32) {
+    HIP_TRY(lf::launch_residual<float>(c->g, fptr<float>(c, c->off_mom),
+                                       fptr<float>(c, c->off_T[c->cur]),
+                                       fptr<float>(c, c->off_snap), part, c->nblk, out, s));
+  } else {
+    HIP_TRY(lf::launch_residual<double>(c->g, fptr<double>(c, c->off_mom),
+                                        fptr<double>(c, c->off_T[c->cur]),
+                                        fptr<double>(c, c->off_snap), part, c->nblk, out, s));
+  }
+  double h[7];
+  HIP_TRY(hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int k = 0; k < 3; ++k) {
+    const double num = sqrt(h[2 * k]), den = sqrt(h[2 * k + 1]);
+    r[k] = den < 1e-300 ? num : num / den;
+  }
+  if (h[6] != 0.0) return fail(LF_EDIVERGED, "%.0f non-finite values after %lld steps", h[6],
+                               (long long)c->steps);
+  return LF_OK;
+}
+
+lf_status lf_case_run_to_steady(lf_case* c, double tol, int check_every, int64_t max_steps,
+                                int64_t* steps_taken, double r_final[3], int* rule) {
+  if (!c) return fail(LF_EINVAL, "NULL case");
+  if (!(tol > 0.0) || check_every < 1 || max_steps < 0) return fail(LF_EINVAL, "bad stop settings");
+  double r[3] = {0, 0, 0};
+  lf_status st = lf_case_residual(c, r);  // snapshot the current state
+  if (st != LF_OK) return st;
+  std::vector<double> hist;
+  int64_t done = 0;
+  int fired = 0;
+  while (done < max_steps) {
+    const int64_t k = (max_steps - done) < check_every ? (max_steps - done) : check_every;
+    st = lf_case_step(c, k);
+    if (st != LF_OK) return st;
+    done += k;
+    st = lf_case_residual(c, r);
+    if (st != LF_OK) break;
+    const double m = fmax(r[0], fmax(r[1], r[2]));
+    hist.push_back(m);
+    if (m <= tol || (r[0] == 0.0 && r[1] == 0.0 && r[2] == 0.0)) { fired = LF_STOP_TOL; break; }
+    if (c->desc.precision == LF_F32 && m <= 1e-6 && hist.size() >= 4) {
+      // FP32 rounding floor: no 10 % drop over the last three checks
+      const double before = hist[hist.size() - 4];
+      if (m > 0.9 * before) { fired = LF_STOP_FLOOR; break; }
+    }
+  }
+  if (steps_taken) *steps_taken = done;
+  if (r_final) memcpy(r_final, r, sizeof(r));
+  if (rule) *rule = fired;
+  if (st != LF_OK) return st;
+  if (!fired) return fail(LF_ENOTCONV, "max residual %.3g after %lld steps", fmax(r[0], fmax(r[1], r[2])),
+                          (long long)done);
+  return LF_OK;
+}
+
+lf_status lf_case_nusselt(lf_case* c, lf_nusselt* out) {
+  if (!c || !out) return fail(LF_EINVAL, "NULL argument");
+  if (!c->inited) return fail(LF_ESTATE, "init first");
+  hipStream_t s = c->ctx->stream;
+  double* dout = (double*)(c->ws + c->off_out) + 16;
+  if (c->desc.precision == LF_F32)
+    HIP_TRY(lf::launch_nusselt<float>(c->g, c->w, fptr<float>(c, c->off_T[c->cur]), dout, s));
+  else
+    HIP_TRY(lf::launch_nusselt<double>(c->g, c->w, fptr<double>(c, c->off_T[c->cur]), dout, s));
+  double h[8];
+  HIP_TRY(hipMemcpyAsync(h, dout, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  out->nu_hot = h[0]; out->nu_cold = h[1]; out->nu_hot_max = h[2]; out->y_hot_max = h[3];
+  out->nu_cold_max = h[4]; out->y_cold_max = h[5]; out->nu_hot_o2 = h[6]; out->nu_cold_o2 = h[7];
+  return LF_OK;
+}
+
+lf_status lf_case_fetch(lf_case* c, int field, void* dst, size_t dst_bytes, int dst_is_device,
+                        int as_f64) {
+  if (!c || !dst) return fail(LF_EINVAL, "NULL argument");
+  if (!c->inited) return fail(LF_ESTATE, "init first");
+  const size_t n = (size_t)c->g.nx * c->g.ny;
+  const size_t need = n * (as_f64 ? 8 : c->es);
+  if (dst_bytes < need) return fail(LF_EINVAL, "dst holds %zu bytes, %zu needed", dst_bytes, need);
+  const size_t pb = align_up((size_t)c->g.plane * c->es, 256);
+  size_t off;
+  switch (field) {
+    case LF_FIELD_RHO: off = c->off_mom; break;
+    case LF_FIELD_U: off = c->off_mom + pb; break;
+    case LF_FIELD_V: off = c->off_mom + 2 * pb; break;
+    case LF_FIELD_T: off = c->off_T[c->cur]; break;
+    default: return fail(LF_EINVAL, "bad field %d", field);
+  }
+  hipStream_t s = c->ctx->stream;
+  void* target = dst_is_device ? dst : (void*)(c->ws + c->off_stage);
+  if (c->desc.precision == LF_F32)
+    HIP_TRY(lf::launch_unpack<float>(c->g, fptr<float>(c, off), target, as_f64, s));
+  else
+    HIP_TRY(lf::launch_unpack<double>(c->g, fptr<double>(c, off), target, as_f64, s));
+  if (!dst_is_device) {
+    HIP_TRY(hipMemcpyAsync(dst, target, need, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  return LF_OK;
+}
+
+lf_status lf_case_mass(lf_case* c, double* sum_f, double* sum_T) {
+  if (!c || !sum_f || !sum_T) return fail(LF_EINVAL, "NULL argument");
+  if (!c->inited) return fail(LF_ESTATE, "init first");
+  hipStream_t s = c->ctx->stream;
+  double* out = (double*)(c->ws + c->off_out) + 32;
+  double* part = (double*)(c->ws + c->off_part);
+  if (c->desc.precision == LF_F32)
+    HIP_TRY(lf::launch_mass<float>(c->g, fptr<float>(c, c->off_f[c->cur]),
+                                   fptr<float>(c, c->off_T[c->cur]), part, c->nblk, out, s));
+  else
+    HIP_TRY(lf::launch_mass<double>(c->g, fptr<double>(c, c->off_f[c->cur]),
+                                    fptr<double>(c, c->off_T[c->cur]), part, c->nblk, out, s));
+  double h[2];
+  HIP_TRY(hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  // populations are stored as f - w_q; the weights of a node sum to one
+  *sum_f = h[0] + (double)c->g.nx * c->g.ny;
+  *sum_T = h[1];
+  return LF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,76 @@
+// Internal interface between the host runtime (lbmfvm_api.cpp) and the HIP
+// kernels (*.hip).  Not installed; the public ABI is include/lbmfvm.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lf {
+
+// Wall description as the kernels see it (sides W, E, S, N).
+struct WallSet {
+  int xper, yper;     // periodic along x / y
+  double uw[4];       // tangential wall speed per side
+  int tfix[4];        // 1: fixed-temperature wall, 0: adiabatic
+  double Tw[4];       // wall temperature of fixed-temperature walls
+};
+
+// Scalar parameters of the Mode H step.
+struct HybridParams {
+  double omega;       // 1 / tau
+  double alpha;       // thermal diffusivity (lattice units)
+  double gbeta;       // g * beta
+  double T_ref;       // reference temperature of the buoyancy term
+  double gx, gy;      // extra body acceleration
+  int conv;           // 0 QUICK, 1 central, 2 upwind
+};
+
+// Geometry of one cavity's planes inside the workspace.
+struct Grid {
+  int nx, ny, pitch;  // pitch: row stride in elements (multiple of 64)
+  long long plane;    // elements per plane = ny * pitch
+};
+
+// One fused Mode H step: pull-stream + bounce-back + moments + explicit FV
+// energy update + BGK collision with buoyancy.  f planes are stored shifted
+// (f - w_q).  mom (rho, u, v planes) is written only when non-null.
+template <typename real>
+hipError_t launch_hybrid_step(const Grid& g, const WallSet& w,
+                              const HybridParams& p, const real* fin,
+                              real* fout, const real* Tin, real* Tout,
+                              real* mom, int band, hipStream_t s);
+
+// f = f_eq(1, u0) - w, T = T0, mom = (1, u0, v0), snapshots = (u0, v0, T0)
+// from dense double staging arrays (u0 / v0 may be null for zero).
+template <typename real>
+hipError_t launch_init(const Grid& g, const double* T0, const double* u0,
+                       const double* v0, real* f, real* T, real* mom,
+                       real* snap, hipStream_t s);
+
+// Residual partial sums: per block six FP64 sums
+// {sum (u-us)^2, sum u^2, sum (v-vs)^2, sum v^2, sum (T-Ts)^2, sum T^2}
+// plus a non-finite flag; then a single-block pass in fixed order writes
+// out[0..5] and out[6] = count of non-finite values.  Snapshot updated.
+template <typename real>
+hipError_t launch_residual(const Grid& g, const real* mom, const real* T,
+                           real* snap, double* partials, int nblocks,
+                           double* out, hipStream_t s);
+
+// Nusselt numbers of the west and east walls into out[0..7] (lf_nusselt
+// order).
+template <typename real>
+hipError_t launch_nusselt(const Grid& g, const WallSet& w, const real* T,
+                          double* out, hipStream_t s);
+
+// out[0] = sum of the post-collision populations (unshifted), out[1] = sum T
+template <typename real>
+hipError_t launch_mass(const Grid& g, const real* f, const real* T,
+                       double* partials, int nblocks, double* out,
+                       hipStream_t s);
+
+// Dense copy of one plane into dst ([ny][nx]) as double or as real.
+template <typename real>
+hipError_t launch_unpack(const Grid& g, const real* plane, void* dst,
+                         int as_f64, hipStream_t s);
+
+}  // namespace lf
