@@ -175,10 +175,12 @@ lf_status lf_case_fetch(lf_case* c, int field, void* dst, size_t dst_bytes,
 lf_status lf_case_mass(lf_case* c, double* sum_f, double* sum_T);
 /* Steps taken since init.                                                 */
 lf_status lf_case_steps(const lf_case* c, int64_t* steps);
-/* Advance nsteps (1 .. 2^20) steps with a pair of HIP events around every
- * step kernel on the context stream, synchronising after each; returns the
- * mean, min and max kernel time in milliseconds (min/max may be NULL).
- * Same result as lf_case_step; for measurement only.                      */
+/* Advance nsteps (1 .. 2^20) steps, launched back to back on the context
+ * stream with a HIP event after every 64 launches; synchronises at the end
+ * and returns the mean time per step kernel in milliseconds and the min /
+ * max of the 64-launch means (min/max may be NULL).  The state advances
+ * exactly as with lf_case_step (moments written on the last step of every
+ * 64).  For measurement.                                                   */
 lf_status lf_case_profile_steps(lf_case* c, int64_t nsteps, double* avg_ms,
                                 double* min_ms, double* max_ms);
 

@@ -22,7 +22,7 @@ import numpy as np
 import torch  # noqa: F401  (loads the HIP runtime the library binds to)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liblbmfvm.so")
+LIB_PATH = os.environ.get("LBMFVM_LIB") or os.path.join(_HERE, "liblbmfvm.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(

@@ -24,10 +24,37 @@
 // to w_q, which keeps FP32 results within 1e-4 of FP64 over long runs.
 #include "lf_internal.h"
 
+// Floating-point contraction is off in this file and every fused
+// multiply-add is written out (fma_): the interior and the general march
+// then execute the same operations in the same order for a node, so results
+// do not depend on how the grid is cut into strips and bands.
+#pragma clang fp contract(off)
+
 namespace lf {
 namespace {
 
+template <typename real>
+__device__ __forceinline__ real fma_(real a, real b, real c) {
+  return __builtin_fma(a, b, c);
+}
+template <>
+__device__ __forceinline__ float fma_<float>(float a, float b, float c) {
+  return __builtin_fmaf(a, b, c);
+}
+
 constexpr int kOut = 62;  // output columns per wave (lanes 1..62)
+
+// Minimum waves per SIMD the step kernel is compiled for (register budget):
+// 5 for FP32 (up to 96 VGPRs, room for two rows in flight without spills);
+// FP64 is left its full register file.
+#ifndef LF_STEP_WAVES_F32
+#define LF_STEP_WAVES_F32 5
+#endif
+#define LF_STEP_WAVES(real) (sizeof(real) == 4 ? LF_STEP_WAVES_F32 : 2)
+// Rows of populations requested ahead of the row being computed (1 or 2).
+#ifndef LF_PREFETCH_ROWS
+#define LF_PREFETCH_ROWS 2
+#endif
 
 // D2Q9 (Eq 4, Eq 9): 0 rest, 1 E, 2 N, 3 W, 4 S, 5 NE, 6 NW, 7 SW, 8 SE.
 __host__ __device__ constexpr int ex(int q) {
@@ -71,6 +98,27 @@ __device__ __forceinline__ int wrap_one(int c, int n) {
 }
 __device__ __forceinline__ int clampi(int c, int lo, int hi) {
   return c < lo ? lo : (c > hi ? hi : c);
+}
+
+template <typename real>
+__device__ __forceinline__ real recip(real x) {
+  return real(1) / x;
+}
+template <>
+__device__ __forceinline__ float recip<float>(float x) {
+  return __builtin_amdgcn_rcpf(x);  // v_rcp_f32, 1 ulp
+}
+
+// Moments of 9 streamed (shifted) populations.
+template <typename real>
+__device__ __forceinline__ void moments(const real f[9], real& drho, real& ux, real& uy) {
+  const real s = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+  const real jx = (f[1] - f[3]) + ((f[5] - f[6]) + (f[8] - f[7]));
+  const real jy = (f[2] - f[4]) + ((f[5] - f[7]) + (f[6] - f[8]));
+  drho = s;
+  const real inv = recip<real>(real(1) + s);
+  ux = jx * inv;
+  uy = jy * inv;
 }
 
 // Temperature of cell (c, r) of the previous step, extended one cell past
@@ -122,31 +170,20 @@ __device__ __forceinline__ void pull_row(const StepArgs<real>& a, int ic, int r,
     }
     f[q] = v;
   }
-  real s = real(0), jx = real(0), jy = real(0);
-#pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    s += f[q];
-    if (ex(q) > 0) jx += f[q];
-    if (ex(q) < 0) jx -= f[q];
-    if (ey(q) > 0) jy += f[q];
-    if (ey(q) < 0) jy -= f[q];
-  }
-  drho = s;
-  const real inv = real(1) / (real(1) + s);
-  ux = jx * inv;
-  uy = jy * inv;
+  moments(f, drho, ux, uy);
 }
 
 // Face value of the convected temperature between cells L and R; tll is
 // upstream of L, trr downstream of R.  QUICK: quadratic through the two
 // neighbours and the next upstream cell.
 template <typename real>
-__device__ __forceinline__ real face_value(int conv, real uf, real tll, real tl,
+__device__ __forceinline__ real face_value(const int conv, real uf, real tll, real tl,
                                            real tr, real trr) {
   if (conv == 1) return real(0.5) * (tl + tr);
   if (conv == 2) return uf >= real(0) ? tl : tr;
-  return uf >= real(0) ? (real(6) * tl + real(3) * tr - tll) * real(0.125)
-                       : (real(6) * tr + real(3) * tl - trr) * real(0.125);
+  // (6 t_near + 3 t_far - t_up) / 8
+  return uf >= real(0) ? fma_(real(0.75), tl, fma_(real(0.375), tr, real(-0.125) * tll))
+                       : fma_(real(0.75), tr, fma_(real(0.375), tl, real(-0.125) * trr));
 }
 
 // BGK collision with the buoyancy force, on shifted populations.
@@ -154,39 +191,69 @@ __device__ __forceinline__ real face_value(int conv, real uf, real tll, real tl,
 //   F    = 3 w (G.(e - u)) (1 + P)  = G.(e - u) f_eq / (rho c_s^2) (Eq 18)
 //   f*   = f + (f_eq - f) / tau + F                           (Eq 5 / 19)
 // with G = (gx, g beta (T - T_ref) + gy) (Eq 81).  In shifted form
-// f~_eq = w (drho + rho P).
+// f~_eq = w (drho + rho P).  Opposite directions share e.u up to sign, so
+// they are evaluated in pairs.
 template <typename real>
 __device__ __forceinline__ void collide(const StepArgs<real>& a, const real f[9],
                                         real drho, real ux, real uy, real T,
                                         real out[9]) {
   const real rho = real(1) + drho;
   const real Gx = a.gx;
-  const real Gy = a.gbeta * (T - a.Tref) + a.gy;
-  const real usq = real(1.5) * (ux * ux + uy * uy);
-  const real Gu = Gx * ux + Gy * uy;
-#pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    const real eu = real(ex(q)) * ux + real(ey(q)) * uy;
-    const real P = real(3) * eu + real(4.5) * eu * eu - usq;
-    const real feq = wq<real>(q) * (drho + rho * P);
-    const real Ge = real(ex(q)) * Gx + real(ey(q)) * Gy;
-    const real F = real(3) * wq<real>(q) * (Ge - Gu) * (real(1) + P);
-    out[q] = f[q] + a.omega * (feq - f[q]) + F;
+  const real Gy = fma_(a.gbeta, T - a.Tref, a.gy);
+  const real usq = real(1.5) * fma_(ux, ux, uy * uy);
+  const real Gu = fma_(Gx, ux, Gy * uy);
+  const real om = a.omega;
+  {
+    const real w = wq<real>(0);
+    const real P = -usq;
+    const real feq = w * fma_(rho, P, drho);
+    const real F = (real(3) * w) * (-Gu) * (real(1) + P);
+    out[0] = fma_(om, feq - f[0], f[0]) + F;
   }
+  auto pair = [&](int q, int qb, real eu, real Ge, real w) {
+    const real A = fma_(real(4.5) * eu, eu, -usq);
+    const real B = real(3) * eu;
+    const real Pq = A + B, Pb = A - B;
+    const real fq = w * fma_(rho, Pq, drho), fb = w * fma_(rho, Pb, drho);
+    const real cq = (real(3) * w) * (Ge - Gu), cb = (real(3) * w) * (-Ge - Gu);
+    out[q] = fma_(om, fq - f[q], f[q]) + fma_(cq, Pq, cq);
+    out[qb] = fma_(om, fb - f[qb], f[qb]) + fma_(cb, Pb, cb);
+  };
+  pair(1, 3, ux, Gx, wq<real>(1));
+  pair(2, 4, uy, Gy, wq<real>(2));
+  pair(5, 7, ux + uy, Gx + Gy, wq<real>(5));
+  pair(6, 8, uy - ux, Gy - Gx, wq<real>(6));
+}
+
+// Flux through the face between cells L and R (positive from L to R):
+// u_f T_f - alpha (T_R - T_L) with u_f the mean of the two cell velocities.
+// tll is upstream of L, trr downstream of R.
+template <typename real, int CONV>
+__device__ __forceinline__ real face_flux(real al, real uL, real uR, real tll, real tl, real tr,
+                                          real trr) {
+  const real uf = real(0.5) * (uL + uR);
+  return fma_(uf, face_value<real>(CONV, uf, tll, tl, tr, trr), -al * (tr - tl));
 }
 
 template <typename real>
-__global__ __launch_bounds__(256) void k_hybrid_step(StepArgs<real> a) {
-  const int lane = threadIdx.x & 63;
-  const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (wave >= a.nwaves) return;  // uniform per wave
-  const int strip = wave % a.nstrips;
-  const int bnd = wave / a.nstrips;
-  const int i = strip * kOut + lane - 1;  // this lane's column
+__device__ __forceinline__ void store_node(const StepArgs<real>& a, int o, const real fo[9],
+                                           real Tnew, real drho, real ux, real uy) {
+#pragma unroll
+  for (int q = 0; q < 9; ++q) a.fout[q * a.plane + o] = fo[q];
+  a.Tout[o] = Tnew;
+  if (a.mom) {
+    a.mom[o] = real(1) + drho;
+    a.mom[a.plane + o] = ux;
+    a.mom[2 * a.plane + o] = uy;
+  }
+}
+
+// General march: any wave, including those touching walls or periodic seams.
+// Each cell evaluates its four face fluxes (wall faces by the wall rule).
+template <typename real, int CONV>
+__device__ void march_general(const StepArgs<real>& a, int lane, int i, int j0, int j1) {
   const int ic = a.xper ? wrap_any(i, a.nx) : clampi(i, 0, a.nx - 1);
   const bool act = lane >= 1 && lane <= kOut && i < a.nx;
-  const int j0 = bnd * a.band;
-  const int j1 = min(j0 + a.band, a.ny);
   const int ix2 = lane < 32 ? i - 2 : i + 2;  // second T column (lanes 1, 62)
   const real al = a.alpha;
 
@@ -203,7 +270,6 @@ __global__ __launch_bounds__(256) void k_hybrid_step(StepArgs<real> a) {
   for (int j = j0; j < j1; ++j) {
     pull_row(a, ic, j + 1, fn, dr_n, ux_n, uy_n);
     const real tx2 = T_at(a, ix2, j);
-    // x-neighbours from the adjacent lanes (all lanes take part)
     const real tW1 = __shfl_up(t2, 1, 64);
     const real tE1 = __shfl_down(t2, 1, 64);
     real tW2 = __shfl_up(t2, 2, 64);
@@ -212,49 +278,21 @@ __global__ __launch_bounds__(256) void k_hybrid_step(StepArgs<real> a) {
     const real uE = __shfl_down(ux_c, 1, 64);
     if (lane == 1) tW2 = tx2;
     if (lane == kOut) tE2 = tx2;
-
-    // fluxes through the four faces, positive towards +x / +y
     real Fw, Fe, Fs, Fn;
-    if (!a.xper && i == 0) {
-      Fw = a.tfix[0] ? real(-2) * al * (t2 - a.Tw[0]) : real(0);
-    } else {
-      const real uf = real(0.5) * (uW + ux_c);
-      Fw = uf * face_value(a.conv, uf, tW2, tW1, t2, tE1) - al * (t2 - tW1);
-    }
-    if (!a.xper && i == a.nx - 1) {
-      Fe = a.tfix[1] ? real(-2) * al * (a.Tw[1] - t2) : real(0);
-    } else {
-      const real uf = real(0.5) * (ux_c + uE);
-      Fe = uf * face_value(a.conv, uf, tW1, t2, tE1, tE2) - al * (tE1 - t2);
-    }
-    if (!a.yper && j == 0) {
-      Fs = a.tfix[2] ? real(-2) * al * (t2 - a.Tw[2]) : real(0);
-    } else {
-      const real vf = real(0.5) * (uy_p + uy_c);
-      Fs = vf * face_value(a.conv, vf, t0, t1, t2, t3) - al * (t2 - t1);
-    }
-    if (!a.yper && j == a.ny - 1) {
-      Fn = a.tfix[3] ? real(-2) * al * (a.Tw[3] - t2) : real(0);
-    } else {
-      const real vf = real(0.5) * (uy_c + uy_n);
-      Fn = vf * face_value(a.conv, vf, t1, t2, t3, t4) - al * (t3 - t2);
-    }
+    if (!a.xper && i == 0) Fw = a.tfix[0] ? real(-2) * al * (t2 - a.Tw[0]) : real(0);
+    else Fw = face_flux<real, CONV>(al, uW, ux_c, tW2, tW1, t2, tE1);
+    if (!a.xper && i == a.nx - 1) Fe = a.tfix[1] ? real(-2) * al * (a.Tw[1] - t2) : real(0);
+    else Fe = face_flux<real, CONV>(al, ux_c, uE, tW1, t2, tE1, tE2);
+    if (!a.yper && j == 0) Fs = a.tfix[2] ? real(-2) * al * (t2 - a.Tw[2]) : real(0);
+    else Fs = face_flux<real, CONV>(al, uy_p, uy_c, t0, t1, t2, t3);
+    if (!a.yper && j == a.ny - 1) Fn = a.tfix[3] ? real(-2) * al * (a.Tw[3] - t2) : real(0);
+    else Fn = face_flux<real, CONV>(al, uy_c, uy_n, t1, t2, t3, t4);
     const real Tnew = t2 - (Fe - Fw) - (Fn - Fs);
-
     if (act) {
       real fo[9];
       collide(a, fc, dr_c, ux_c, uy_c, Tnew, fo);
-      const int o = j * a.pitch + i;
-#pragma unroll
-      for (int q = 0; q < 9; ++q) a.fout[q * a.plane + o] = fo[q];
-      a.Tout[o] = Tnew;
-      if (a.mom) {
-        a.mom[o] = real(1) + dr_c;
-        a.mom[a.plane + o] = ux_c;
-        a.mom[2 * a.plane + o] = uy_c;
-      }
+      store_node(a, j * a.pitch + i, fo, Tnew, dr_c, ux_c, uy_c);
     }
-
     uy_p = uy_c;
 #pragma unroll
     for (int q = 0; q < 9; ++q) fc[q] = fn[q];
@@ -267,6 +305,193 @@ __global__ __launch_bounds__(256) void k_hybrid_step(StepArgs<real> a) {
     t3 = t4;
     t4 = T_at(a, i, j + 3);
   }
+}
+
+// Buffer-resource access: one descriptor per array, a per-lane byte offset
+// (row * pitch + column) and a wave-uniform byte offset in an SGPR (the
+// direction's plane and upstream shift), so an access costs no VALU work.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
+                                           0x00020000);
+}
+template <typename real>
+__device__ __forceinline__ real bload(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <>
+__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+  const u2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+  return __builtin_bit_cast(double, v);
+}
+template <typename real>
+__device__ __forceinline__ void bstore(real v, __amdgpu_buffer_rsrc_t r, int voff, int soff);
+// cache policy of the step's output stores (2 = non-temporal)
+#ifndef LF_STORE_AUX
+#define LF_STORE_AUX 0
+#endif
+template <>
+__device__ __forceinline__ void bstore<float>(float v, __amdgpu_buffer_rsrc_t r, int voff,
+                                              int soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, LF_STORE_AUX);
+}
+template <>
+__device__ __forceinline__ void bstore<double>(double v, __amdgpu_buffer_rsrc_t r, int voff,
+                                               int soff) {
+  typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, LF_STORE_AUX);
+}
+
+// Interior march: every pulled node, its upstream nodes and the T stencil
+// lie inside the grid and no face is a wall.  Each lane evaluates only the
+// east face of its cell (the west face is the east face of the lane to the
+// left) and the north face (the south face is the previous row's north
+// face), and the next row's populations are requested one row ahead.
+template <typename real, int CONV>
+__device__ void march_interior(const StepArgs<real>& a, int lane, int i, int j0, int j1) {
+  constexpr int es = sizeof(real);
+  const int P = a.pitch;
+  const bool act = lane >= 1 && lane <= kOut;
+  const unsigned fbytes = 9u * (unsigned)a.plane * es, pbytes = (unsigned)a.plane * es;
+  const __amdgpu_buffer_rsrc_t rf = make_rsrc(a.fin, fbytes);
+  const __amdgpu_buffer_rsrc_t rT = make_rsrc(a.Tin, pbytes);
+  const __amdgpu_buffer_rsrc_t wf = make_rsrc(a.fout, fbytes);
+  const __amdgpu_buffer_rsrc_t wT = make_rsrc(a.Tout, pbytes);
+  int sq[9];  // uniform byte offset of direction q's upstream node
+#pragma unroll
+  for (int q = 0; q < 9; ++q) sq[q] = (q * a.plane - ey(q) * P - ex(q)) * es;
+  // lane 0 needs T one column further west, lane 62 one further east
+  const int xoff = (lane < 32 ? -1 : 2) * es;
+  const real al = a.alpha;
+
+  auto load_row = [&](int r, real f[9]) {
+    const int vo = (r * P + i) * es;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) f[q] = bload<real>(rf, vo, sq[q]);
+  };
+  auto T_row = [&](int r) { return bload<real>(rT, (r * P + i) * es, 0); };
+
+#if LF_PREFETCH_ROWS == 2
+  // rows j0-1 .. j0+2 requested up front; row j+3 is requested while row j
+  // is computed (two rows ahead).  Four arrays rotate by unrolling.
+  real A[9], B[9], C[9], D[9];
+  real dr_c, ux_c, uy_c, uy_p, d_unused, u_unused;
+  load_row(j0 - 1, D);
+  load_row(j0, A);
+  load_row(j0 + 1, B);
+  if (j0 + 2 <= j1) load_row(j0 + 2, C);
+  const real tm2 = T_row(j0 - 2);
+  real t1 = T_row(j0 - 1), t2 = T_row(j0), t3 = T_row(j0 + 1), t4 = T_row(j0 + 2);
+  real t5 = T_row(j0 + 3 < a.ny ? j0 + 3 : j0 + 2);
+  moments(D, d_unused, u_unused, uy_p);
+  moments(A, dr_c, ux_c, uy_c);
+  real Fs = face_flux<real, CONV>(al, uy_p, uy_c, tm2, t1, t2, t3);
+
+  auto row = [&](int j, const real (&fc)[9], const real (&fn)[9], real (&fl)[9]) {
+    if (j + 3 <= j1) load_row(j + 3, fl);  // prefetch two rows ahead
+#else
+  real A[9], B[9], C[9];
+  real dr_c, ux_c, uy_c, uy_p, d_unused, u_unused;
+  load_row(j0 - 1, C);
+  load_row(j0, A);
+  load_row(j0 + 1, B);
+  const real tm2 = T_row(j0 - 2);
+  real t1 = T_row(j0 - 1), t2 = T_row(j0), t3 = T_row(j0 + 1), t4 = T_row(j0 + 2);
+  moments(C, d_unused, u_unused, uy_p);
+  moments(A, dr_c, ux_c, uy_c);
+  // south face of the first row: the north face of row j0 - 1
+  real Fs = face_flux<real, CONV>(al, uy_p, uy_c, tm2, t1, t2, t3);
+
+  // one row: fc holds row j's streamed populations, fn row j + 1's; fl
+  // receives row j + 2's.  The three arrays rotate by unrolling (no copies).
+  auto row = [&](int j, const real (&fc)[9], const real (&fn)[9], real (&fl)[9]) {
+    if (j + 2 <= j1) load_row(j + 2, fl);  // prefetch
+#endif
+    real dr_n, ux_n, uy_n;
+    moments(fn, dr_n, ux_n, uy_n);
+    const real tx = bload<real>(rT, (j * P + i) * es + xoff, 0);
+    real tW1 = __shfl_up(t2, 1, 64);
+    const real tE1 = __shfl_down(t2, 1, 64);
+    real tE2 = __shfl_down(t2, 2, 64);
+    const real uE = __shfl_down(ux_c, 1, 64);
+    if (lane == 0) tW1 = tx;
+    if (lane == kOut) tE2 = tx;
+    const real Fe = face_flux<real, CONV>(al, ux_c, uE, tW1, t2, tE1, tE2);
+    const real Fw = __shfl_up(Fe, 1, 64);
+    const real Fn = face_flux<real, CONV>(al, uy_c, uy_n, t1, t2, t3, t4);
+    const real Tnew = t2 - (Fe - Fw) - (Fn - Fs);
+    if (act) {
+      real fo[9];
+      collide(a, fc, dr_c, ux_c, uy_c, Tnew, fo);
+      const int vo = (j * P + i) * es;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) bstore<real>(fo[q], wf, vo, q * a.plane * es);
+      bstore<real>(Tnew, wT, vo, 0);
+      if (a.mom) {
+        const int o = j * P + i;
+        a.mom[o] = real(1) + dr_c;
+        a.mom[a.plane + o] = ux_c;
+        a.mom[2 * a.plane + o] = uy_c;
+      }
+    }
+    Fs = Fn;
+    uy_p = uy_c;
+    dr_c = dr_n;
+    ux_c = ux_n;
+    uy_c = uy_n;
+    t1 = t2;
+    t2 = t3;
+    t3 = t4;
+#if LF_PREFETCH_ROWS == 2
+    t4 = t5;
+    if (j + 4 < a.ny) t5 = T_row(j + 4);
+  };
+  for (int j = j0; j < j1; j += 4) {
+    row(j, A, B, D);
+    if (j + 1 >= j1) break;
+    row(j + 1, B, C, A);
+    if (j + 2 >= j1) break;
+    row(j + 2, C, D, B);
+    if (j + 3 >= j1) break;
+    row(j + 3, D, A, C);
+  }
+}
+#else
+    if (j + 3 < a.ny) t4 = T_row(j + 3);
+  };
+  for (int j = j0; j < j1; j += 3) {
+    row(j, A, B, C);
+    if (j + 1 >= j1) break;
+    row(j + 1, B, C, A);
+    if (j + 2 >= j1) break;
+    row(j + 2, C, A, B);
+  }
+}
+#endif
+
+template <typename real, int CONV>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LF_STEP_WAVES(real))))
+void k_hybrid_step(StepArgs<real> a) {
+  // Blocks are dealt round-robin to the 8 XCDs; renumber them so that each
+  // XCD works on a contiguous range of strips and bands, which keeps the
+  // halo lines shared by neighbouring waves inside one L2.
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int per = nb / 8, rem = nb % 8, x = b % 8;
+  const int lb = x * per + (x < rem ? x : rem) + b / 8;
+  const int wave = lb * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (wave >= a.nwaves) return;  // uniform per wave
+  const int lane = threadIdx.x & 63;
+  const int strip = wave % a.nstrips;
+  const int bnd = wave / a.nstrips;
+  const int c0 = strip * kOut;   // first output column
+  const int i = c0 + lane - 1;   // this lane's column
+  const int j0 = bnd * a.band;
+  const int j1 = min(j0 + a.band, a.ny);
+  const bool interior = c0 - 1 >= 1 && c0 + kOut <= a.nx - 2 && j0 - 1 >= 2 && j1 <= a.ny - 2;
+  if (interior) march_interior<real, CONV>(a, lane, i, j0, j1);
+  else march_general<real, CONV>(a, lane, i, j0, j1);
 }
 
 // ---------------------------------------------------------------------------
@@ -334,7 +559,12 @@ hipError_t launch_hybrid_step(const Grid& g, const WallSet& w, const HybridParam
   a.gx = real(p.gx);
   a.gy = real(p.gy);
   const int blocks = (a.nwaves + 3) / 4;
-  hipLaunchKernelGGL(k_hybrid_step<real>, dim3(blocks), dim3(256), 0, s, a);
+  if (p.conv == 1)
+    hipLaunchKernelGGL((k_hybrid_step<real, 1>), dim3(blocks), dim3(256), 0, s, a);
+  else if (p.conv == 2)
+    hipLaunchKernelGGL((k_hybrid_step<real, 2>), dim3(blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_hybrid_step<real, 0>), dim3(blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

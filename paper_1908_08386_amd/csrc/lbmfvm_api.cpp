@@ -304,32 +304,28 @@ lf_status lf_case_init(lf_case* c, const double* T0, const double* u0, const dou
 
 static int auto_band(const lf_case* c) {
   if (c->ctx->band > 0) return c->ctx->band;
-  // aim for >= 4096 waves (16 per CU) while keeping the two halo rows of a
-  // band small against its height
+  // Rows per wave: short marches keep many waves in flight, long ones
+  // re-pull fewer halo rows.  Measured on MI355X: 4 rows is best once the
+  // grid yields >= 8192 waves (e.g. 2048^2 and up), otherwise 2, then 1
+  // (512^2 is latency-bound and wants the most waves).
   const long long strips = (c->g.nx + 61) / 62;
-  long long band = 64;
-  while (band > 4 && strips * ((c->g.ny + band - 1) / band) < 4096) band /= 2;
-  return (int)band;
+  for (int band = 4; band > 1; band /= 2)
+    if (strips * ((c->g.ny + band - 1) / band) >= 8192) return band;
+  return 1;
 }
 
 }  // extern "C"
 
 template <typename real>
-static lf_status step_impl(lf_case* c, int64_t n, hipEvent_t* ev = nullptr, float* ms = nullptr) {
+static lf_status step_impl(lf_case* c, int64_t n) {
   hipStream_t s = c->ctx->stream;
   const int band = auto_band(c);
   for (int64_t k = 0; k < n; ++k) {
     const int a = c->cur, b = a ^ 1;
     real* mom = (k == n - 1) ? fptr<real>(c, c->off_mom) : nullptr;
-    if (ev) HIP_TRY(hipEventRecord(ev[0], s));
     HIP_TRY(lf::launch_hybrid_step<real>(c->g, c->w, c->p, fptr<real>(c, c->off_f[a]),
                                          fptr<real>(c, c->off_f[b]), fptr<real>(c, c->off_T[a]),
                                          fptr<real>(c, c->off_T[b]), mom, band, s));
-    if (ev) {
-      HIP_TRY(hipEventRecord(ev[1], s));
-      HIP_TRY(hipEventSynchronize(ev[1]));
-      HIP_TRY(hipEventElapsedTime(&ms[k], ev[0], ev[1]));
-    }
     c->cur = b;
   }
   c->steps += n;
@@ -353,25 +349,44 @@ lf_status lf_case_profile_steps(lf_case* c, int64_t nsteps, double* avg_ms, doub
   if (nsteps < 1 || nsteps > (1 << 20)) return fail(LF_EINVAL, "nsteps must be in [1, 2^20]");
   if (!c->inited) return fail(LF_ESTATE, "init before step");
   if (!c->have_params) return fail(LF_ESTATE, "set_physics or set_lattice before step");
-  std::vector<float> ms((size_t)nsteps, 0.0f);
-  hipEvent_t ev[2];
-  HIP_TRY(hipEventCreate(&ev[0]));
-  if (hipEventCreate(&ev[1]) != hipSuccess) {
-    (void)hipEventDestroy(ev[0]);
-    return fail(LF_EDEVICE, "hipEventCreate");
+  // launches run back to back; an event is recorded every `chunk` launches
+  // and read after the last one, so the timing adds no synchronisation
+  const int64_t chunk = nsteps < 64 ? nsteps : 64;
+  const int64_t nchunks = (nsteps + chunk - 1) / chunk;
+  std::vector<hipEvent_t> ev((size_t)nchunks + 1, nullptr);
+  lf_status st = LF_OK;
+  for (auto& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) { st = fail(LF_EDEVICE, "hipEventCreate"); break; }
+  hipStream_t s = c->ctx->stream;
+  std::vector<double> per;
+  if (st == LF_OK && hipEventRecord(ev[0], s) != hipSuccess) st = fail(LF_EDEVICE, "hipEventRecord");
+  int64_t done = 0;
+  for (int64_t k = 0; st == LF_OK && k < nchunks; ++k) {
+    const int64_t m = (nsteps - done) < chunk ? (nsteps - done) : chunk;
+    st = c->desc.precision == LF_F32 ? step_impl<float>(c, m) : step_impl<double>(c, m);
+    if (st == LF_OK && hipEventRecord(ev[(size_t)k + 1], s) != hipSuccess)
+      st = fail(LF_EDEVICE, "hipEventRecord");
+    done += m;
+    per.push_back((double)m);
   }
-  lf_status st = c->desc.precision == LF_F32 ? step_impl<float>(c, nsteps, ev, ms.data())
-                                              : step_impl<double>(c, nsteps, ev, ms.data());
-  (void)hipEventDestroy(ev[0]);
-  (void)hipEventDestroy(ev[1]);
+  double total = 0.0, lo = 1e300, hi = 0.0;
+  if (st == LF_OK && hipEventSynchronize(ev[(size_t)nchunks]) != hipSuccess)
+    st = fail(LF_EDEVICE, "hipEventSynchronize");
+  for (int64_t k = 0; st == LF_OK && k < nchunks; ++k) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, ev[(size_t)k], ev[(size_t)k + 1]) != hipSuccess) {
+      st = fail(LF_EDEVICE, "hipEventElapsedTime");
+      break;
+    }
+    total += ms;
+    const double a = ms / per[(size_t)k];
+    lo = a < lo ? a : lo;
+    hi = a > hi ? a : hi;
+  }
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
   if (st != LF_OK) return st;
-  double sum = 0.0, lo = 1e300, hi = 0.0;
-  for (float v : ms) {
-    sum += v;
-    lo = v < lo ? v : lo;
-    hi = v > hi ? v : hi;
-  }
-  *avg_ms = sum / (double)nsteps;
+  *avg_ms = total / (double)nsteps;
   if (min_ms) *min_ms = lo;
   if (max_ms) *max_ms = hi;
   return LF_OK;
