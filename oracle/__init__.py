@@ -80,9 +80,9 @@ def lib() -> ctypes.CDLL:
             L.dd_create.restype = vp
             L.dd_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
             L.dd_destroy.argtypes = [vp]
-            L.dd_set_lattice.argtypes = [vp] + [ctypes.c_double] * 4 + [ctypes.c_int]
             L.dd_set_wall.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                       ctypes.c_double]
+            L.dd_set_lattice.argtypes = [vp] + [ctypes.c_double] * 5 + [ctypes.c_int]
             L.dd_init.argtypes = [vp, dp]
             L.dd_step.argtypes = [vp, ctypes.c_long]
             L.dd_fetch.argtypes = [vp, ctypes.c_int, dp]
@@ -94,6 +94,11 @@ def lib() -> ctypes.CDLL:
                                               ctypes.c_double, ctypes.c_double, dp]
             L.dd_boundary_density.restype = ctypes.c_double
             L.dd_boundary_density.argtypes = [ctypes.c_double] * 3
+            L.dd_set_iface.argtypes = [vp, ctypes.c_int]
+            L.dd_steps.restype = ctypes.c_long
+            L.dd_steps.argtypes = [vp]
+            L.dd_init_uniform_flow.argtypes = [vp, dp, ctypes.c_double, ctypes.c_double]
+            L.dd_set_fv.argtypes = [vp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -240,4 +245,118 @@ class Case:
             r = self.residual()
             if r[sel].max() <= tol or not np.any(r[sel]):
                 return self.steps, r
+        return self.steps, r
+
+
+SPLIT, PURE_FV, PURE_LBM = 0, 1, 2
+
+
+def reconstruct_node(kind, f_f, rho_b, ub, vb, tau, dudx=0.0, dudy=0.0, dvdx=0.0):
+    """Populations of the LBM artificial-boundary node (Eq 60 or Eq 70)."""
+    ff = np.ascontiguousarray(f_f, dtype=np.float64)
+    out = np.zeros(9)
+    lib().dd_reconstruct_node(int(kind), _dp(ff), rho_b, ub, vb, tau, dudx, dudy, dvdx, _dp(out))
+    return out
+
+
+def boundary_density(rho0, pS, pbar):
+    """Eq 93."""
+    return lib().dd_boundary_density(float(rho0), float(pS), float(pbar))
+
+
+class DDCase:
+    """Domain-decomposed cavity (mode SPLIT: LBM west half, FV east half),
+    or one of the single-method cavities (PURE_FV, PURE_LBM)."""
+
+    def __init__(self, nx: int, ny: int, mode: int = SPLIT, iface: int = IFACE_NEQ):
+        self.nx, self.ny, self.mode = int(nx), int(ny), int(mode)
+        self._h = lib().dd_create(self.nx, self.ny, self.mode)
+        if not self._h:
+            raise ValueError("dd_create: bad size or mode")
+        lib().dd_set_iface(self._h, int(iface))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().dd_destroy(h)
+            self._h = None
+
+    def set_lattice(self, nu, alpha, gbeta=0.0, T_ref=0.0, gx=0.0, conv=CONV_QUICK):
+        if lib().dd_set_lattice(self._h, nu, alpha, gbeta, T_ref, gx, int(conv)) != 0:
+            raise ValueError("bad lattice parameters")
+        return self
+
+    def set_physics(self, Ra, Pr, U_char=0.0, T_ref=0.0):
+        p = physics_params(Ra, Pr, self.ny, U_char, split=True)
+        self.params = p
+        return self.set_lattice(p["nu"], p["alpha"], p["gbeta"], T_ref)
+
+    def set_thermal(self, side, fixed: bool, T_wall=0.0):
+        lib().dd_set_wall(self._h, int(side), 0.0, 1 if fixed else 0, float(T_wall))
+        return self
+
+    def set_periodic(self, axis: str):
+        side = W if axis == "x" else S
+        if lib().dd_set_wall(self._h, side, 0.0, 1 << 4, 0.0) != 0:
+            raise ValueError("periodic sides only in the single-method modes")
+        return self
+
+    def set_cavity_walls(self, T_hot=0.5, T_cold=-0.5):
+        self.set_thermal(W, True, T_hot).set_thermal(E, True, T_cold)
+        return self.set_thermal(S, False).set_thermal(N, False)
+
+    def init(self, T0=None, uniform_flow=None):
+        T = None if T0 is None else np.ascontiguousarray(
+            np.broadcast_to(np.asarray(T0, np.float64), (self.ny, self.nx)))
+        self._keep = T
+        if uniform_flow is None:
+            lib().dd_init(self._h, _dp(T) if T is not None else None)
+        else:
+            lib().dd_init_uniform_flow(self._h, _dp(T) if T is not None else None,
+                                       float(uniform_flow[0]), float(uniform_flow[1]))
+        return self
+
+    def set_fv(self, p=None, u=None, v=None):
+        arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in (p, u, v)]
+        self._keep_fv = arrs
+        lib().dd_set_fv(self._h, *[(_dp(a) if a is not None else None) for a in arrs])
+        return self
+
+    def step(self, n: int):
+        lib().dd_step(self._h, int(n))
+        return self
+
+    @property
+    def steps(self) -> int:
+        return lib().dd_steps(self._h)
+
+    def fetch(self, field) -> np.ndarray:
+        idx = {"u": 0, "v": 1, "T": 2, "rho": 3, "p": 4, "u_faces": 5, "v_faces": 6}[field]
+        shape = {5: (self.ny, self.nx + 1), 6: (self.ny + 1, self.nx)}.get(idx, (self.ny, self.nx))
+        out = np.empty(shape)
+        if lib().dd_fetch(self._h, idx, _dp(out)) != 0:
+            raise ValueError(field)
+        return out
+
+    def residual(self) -> np.ndarray:
+        r = np.zeros(3)
+        lib().dd_residual(self._h, _dp(r))
+        return r
+
+    def nusselt(self) -> dict:
+        out = np.zeros(8)
+        lib().dd_nusselt(self._h, _dp(out))
+        keys = ["nu_hot", "nu_cold", "nu_hot_max", "y_hot_max", "nu_cold_max",
+                "y_cold_max", "nu_hot_o2", "nu_cold_o2"]
+        return dict(zip(keys, out.tolist()))
+
+    def run_to_steady(self, tol=1e-8, check_every=1000, max_steps=10**7, fields=(0, 1, 2)):
+        self.residual()
+        sel = list(fields)
+        r = np.zeros(3)
+        while self.steps < max_steps:
+            self.step(check_every)
+            r = self.residual()
+            if r[sel].max() <= tol or not np.any(r[sel]):
+                break
         return self.steps, r

@@ -547,8 +547,10 @@ int oc_mass(const oc_case* c, double* sum_f, double* sum_T) {
  *   tau_T = 3 alpha + 1/2 (Eq 20), g beta = U_c^2 / (H Delta T), Ma = U_c/c_s.
  * U_char <= 0 selects the default: 0.1, lowered where the explicit
  * temperature update needs it (alpha <= 0.2, U_c^2 <= 2 alpha) and, when
- * split != 0 (the domain-decomposed mode), where the explicit momentum
- * update needs nu <= 0.2.
+ * split != 0 (the domain-decomposed mode), where the explicit
+ * artificial-compressibility momentum update needs it: its linear
+ * amplification stays <= 1 only for nu <= 1/12 (with beta = c_s^2), so
+ * nu <= 0.08 is used.
  * out = {U_c, nu, tau, alpha, tau_T, g beta, T_ref, Ma}                      */
 int oc_physics_params(double Ra, double Pr, int H, double U_char, int split,
                       double out[8]) {
@@ -559,7 +561,7 @@ int oc_physics_params(double Ra, double Pr, int H, double U_char, int split,
     double a = 0.2 * sqrt(Ra * Pr) / H;
     if (a < U) U = a;
     if (split) {
-      double b = 0.2 * sqrt(Ra / Pr) / H;
+      double b = 0.08 * sqrt(Ra / Pr) / H;
       if (b < U) U = b;
     }
     double d = 2.0 * H / sqrt(Ra * Pr);

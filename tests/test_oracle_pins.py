@@ -303,7 +303,11 @@ def test_physics_params_match_eq82_89():
     assert abs(p["tau_T"] - (3 * p["alpha"] + 0.5)) < 1e-15  # Eq 20
     # the Mach number of Eq 84 with u_c = sqrt(g beta dT H)
     assert abs(p["Ma"] - np.sqrt(p["gbeta"] * 64) * np.sqrt(3)) < 1e-15
-    # explicit-stability default lowers U_c for a 4096^2 split cavity at Ra 1e6
+    # explicit-stability default lowers U_c for a 4096^2 cavity at Ra 1e6:
+    # alpha <= 0.2 for the temperature update; in the split mode also
+    # nu <= 0.08 for the artificial-compressibility FV zone
+    q = oracle.physics_params(1e6, 0.71, 4096, 0.0)
+    assert abs(q["alpha"] - 0.2) < 1e-12
     q = oracle.physics_params(1e6, 0.71, 4096, 0.0, split=True)
-    assert abs(q["alpha"] - 0.2) < 1e-12 and q["nu"] < 0.2
-    assert abs(q["U_char"] - 0.2 * np.sqrt(1e6 * 0.71) / 4096) < 1e-15
+    assert abs(q["nu"] - 0.08) < 1e-12 and q["alpha"] < 0.2
+    assert abs(q["U_char"] - 0.08 * np.sqrt(1e6 / 0.71) / 4096) < 1e-15
