@@ -1,0 +1,642 @@
+// k_split.hip -- domain-decomposed LBM|FVM step (Sec. 4 of Li, Yang & Zhang,
+// arXiv:1908.08386) for gfx950.
+//
+// Layout (one cavity, nx even, s = nx / 2):
+//   LBM zone   nodes  0 .. ib (ib = s + 1, the artificial boundary x_b),
+//              D2Q9 populations f (stored shifted, f - w_q) and D2Q5 g,
+//              [q][ny][pitch_L] planes, ping-pong buffers;
+//   FV zone    cells  c0 .. nx-1 (c0 = s - 1) on a staggered grid, stored
+//              for columns c0-2 .. nx (two ghost columns in the LBM zone
+//              and the east wall face): u on x-faces [ny][pitch_F], v on
+//              y-faces [ny+1][pitch_F], p and T at centres [ny][pitch_F];
+//   shared columns c0, c0+1, c0+2 = ib.
+// One step is six launches on one stream:
+//   k_dd_ghost    ghost columns of the FV zone from the LBM moments of the
+//                 previous step (two-point averages; the mean of the inflow
+//                 face is removed: global continuity of the FV zone) and
+//                 rho0 = mean LBM density over the shared columns (Eq 91-93);
+//   k_dd_momentum u*, v* (QUICK convection, central diffusion, pressure
+//                 gradient, buoyancy on v faces; Eq 74-75 explicit);
+//   k_dd_press_energy  p <- p - c_s^2 div u*, and the conservative QUICK
+//                 energy balance on u* (Eq 76);
+//   k_dd_pbar     mean FV pressure over the shared columns;
+//   k_dd_lbm      pull-stream + bounce-back / anti-bounce-back walls,
+//                 moments, BGK collision with buoyancy from T = sum g
+//                 (Eq 5, 18, 19-23) for nodes 0 .. ib-1; the streamed state
+//                 of x_f = ib-1 is kept for the boundary node;
+//   k_dd_xb       x_b from the FV zone: rho_b by Eq 93, u_b, v_b, T_b by
+//                 face averages, populations by non-equilibrium
+//                 extrapolation (Eq 60 / Eq 94-95) or by the
+//                 finite-difference velocity-gradient closure (Eq 70-72);
+//                 then its collision.
+// The LBM zone is 112 B per node (FP32) and the FV zone streams u, v, p, T
+// twice; the interface work is O(ny).
+#include "lf_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace lf {
+namespace {
+
+__host__ __device__ constexpr int ex9(int q) {
+  return (q == 1 || q == 5 || q == 8) ? 1 : (q == 3 || q == 6 || q == 7) ? -1 : 0;
+}
+__host__ __device__ constexpr int ey9(int q) {
+  return (q == 2 || q == 5 || q == 6) ? 1 : (q == 4 || q == 7 || q == 8) ? -1 : 0;
+}
+__host__ __device__ constexpr int opp9(int q) {
+  return q == 0 ? 0 : q < 5 ? ((q + 1) % 4) + 1 : ((q - 3) % 4) + 5;
+}
+template <typename real>
+__host__ __device__ constexpr real w9(int q) {
+  return q == 0 ? real(4) / real(9) : q < 5 ? real(1) / real(9) : real(1) / real(36);
+}
+// D2Q5 (Eq 22): 0 rest, 1 E, 2 N, 3 W, 4 S
+__host__ __device__ constexpr int ex5(int q) { return q == 1 ? 1 : q == 3 ? -1 : 0; }
+__host__ __device__ constexpr int ey5(int q) { return q == 2 ? 1 : q == 4 ? -1 : 0; }
+__host__ __device__ constexpr int opp5(int q) { return q == 0 ? 0 : ((q + 1) % 4) + 1; }
+template <typename real>
+__host__ __device__ constexpr real w5(int q) {
+  return q == 0 ? real(1) / real(3) : real(1) / real(6);
+}
+
+template <typename real>
+__device__ __forceinline__ real fmad(real a, real b, real c) {
+  return __builtin_fma(a, b, c);
+}
+template <>
+__device__ __forceinline__ float fmad<float>(float a, float b, float c) {
+  return __builtin_fmaf(a, b, c);
+}
+
+template <typename real>
+__device__ __forceinline__ real quick(int conv, real uf, real ll, real l, real r, real rr) {
+  if (conv == 1) return real(0.5) * (l + r);
+  if (conv == 2) return uf >= real(0) ? l : r;
+  return uf >= real(0) ? fmad(real(0.75), l, fmad(real(0.375), r, real(-0.125) * ll))
+                       : fmad(real(0.75), r, fmad(real(0.375), l, real(-0.125) * rr));
+}
+
+// shifted f_eq: f_eq - w = w (drho + rho P), P = 3 e.u + 9/2 (e.u)^2 - 3/2 u.u
+template <typename real>
+__device__ __forceinline__ real feq_s(int q, real drho, real ux, real uy) {
+  const real rho = real(1) + drho;
+  const real eu = real(ex9(q)) * ux + real(ey9(q)) * uy;
+  const real P = fmad(real(4.5) * eu, eu, real(3) * eu) - real(1.5) * fmad(ux, ux, uy * uy);
+  return w9<real>(q) * fmad(rho, P, drho);
+}
+
+template <typename real>
+struct SplitArgs {
+  // LBM zone
+  const real* __restrict__ fin;
+  real* __restrict__ fout;
+  const real* __restrict__ gin;
+  real* __restrict__ gout;
+  real* __restrict__ mom;  // rho, u, v, T planes of the LBM zone
+  real* __restrict__ xf;   // streamed state of column ib-1: 9 f + 5 g + rho u v T per row
+  int pL, planeL, nl;      // pitch, plane size, LBM columns (ib + 1)
+  // FV zone (stored columns c0-2 .. nx)
+  const real* __restrict__ u;
+  const real* __restrict__ v;
+  const real* __restrict__ T;
+  real* __restrict__ us;  // u*
+  real* __restrict__ vs;  // v*
+  real* __restrict__ Tn;
+  real* __restrict__ p;
+  int pF;
+  // interface scalars (double): [0] rho0, [1] p_bar
+  double* __restrict__ iface;
+  int nx, ny, s, c0, ib;
+  int conv, kind, mom_all;
+  real omega, omegaT, tau, nu, alpha, gbeta, Tref;
+  int tfix[4];
+  real Tw[4];
+};
+
+// ---- FV-zone accessors (real column x, ghost rules of the walls) -------
+template <typename real>
+__device__ __forceinline__ int fidx(const SplitArgs<real>& a, int x) {
+  return x - (a.c0 - 2);
+}
+template <typename real>
+__device__ __forceinline__ real U_at(const SplitArgs<real>& a, const real* u, int x, int j) {
+  real sg = real(1);
+  if (j < 0) { j = -1 - j; sg = -sg; }
+  else if (j >= a.ny) { j = 2 * a.ny - 1 - j; sg = -sg; }
+  if (x > a.nx) { x = 2 * a.nx - x; sg = -sg; }
+  return sg * u[j * a.pF + fidx(a, x)];
+}
+template <typename real>
+__device__ __forceinline__ real V_at(const SplitArgs<real>& a, const real* v, int x, int jf) {
+  real sg = real(1);
+  if (jf < 0) { jf = -jf; sg = -sg; }
+  else if (jf > a.ny) { jf = 2 * a.ny - jf; sg = -sg; }
+  if (x >= a.nx) { x = 2 * a.nx - 1 - x; sg = -sg; }
+  return sg * v[jf * a.pF + fidx(a, x)];
+}
+template <typename real>
+__device__ __forceinline__ real T_at(const SplitArgs<real>& a, const real* T, int x, int j) {
+  const int jj = j < 0 ? 0 : (j >= a.ny ? a.ny - 1 : j);
+  real t;
+  if (x >= a.nx) {
+    t = T[jj * a.pF + fidx(a, a.nx - 1)];
+    if (a.tfix[1]) t = real(2) * a.Tw[1] - t;
+  } else {
+    t = T[jj * a.pF + fidx(a, x)];
+  }
+  if (j < 0 && a.tfix[2]) t = real(2) * a.Tw[2] - t;
+  if (j >= a.ny && a.tfix[3]) t = real(2) * a.Tw[3] - t;
+  return t;
+}
+template <typename real>
+__device__ __forceinline__ real P_at(const SplitArgs<real>& a, int x, int j) {
+  return a.p[j * a.pF + fidx(a, x)];
+}
+
+// ---- block reduction helpers (one block of 1024 threads) ----------------
+__device__ __forceinline__ double block_sum1024(double v, double* sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += sh[k];
+    sh[16] = s;
+  }
+  __syncthreads();
+  const double r = sh[16];
+  __syncthreads();
+  return r;
+}
+
+// 1. ghost columns from the LBM moments of the previous step; rho0
+template <typename real>
+__global__ __launch_bounds__(1024) void k_dd_ghost(SplitArgs<real> a) {
+  __shared__ double sh[17];
+  real* u = const_cast<real*>(a.u);
+  real* v = const_cast<real*>(a.v);
+  real* T = const_cast<real*>(a.T);
+  const real* rho = a.mom;
+  const real* ux = a.mom + a.planeL;
+  const real* uy = a.mom + 2 * a.planeL;
+  const real* TL = a.mom + 3 * a.planeL;
+  const int c0 = a.c0, ny = a.ny;
+  double su = 0.0, sr = 0.0;
+  for (int j = threadIdx.x; j < ny; j += blockDim.x) {
+    const int o = j * a.pL;
+    const real uf0 = real(0.5) * (ux[o + c0 - 2] + ux[o + c0 - 1]);
+    const real uf1 = real(0.5) * (ux[o + c0 - 1] + ux[o + c0]);
+    u[j * a.pF + fidx(a, c0 - 1)] = uf0;
+    u[j * a.pF + fidx(a, c0)] = uf1;
+    su += (double)uf1;
+    T[j * a.pF + fidx(a, c0 - 2)] = TL[o + c0 - 2];
+    T[j * a.pF + fidx(a, c0 - 1)] = TL[o + c0 - 1];
+    sr += (double)rho[o + c0] + (double)rho[o + c0 + 1] + (double)rho[o + c0 + 2];
+  }
+  for (int jf = threadIdx.x; jf <= ny; jf += blockDim.x) {
+    for (int x = c0 - 2; x <= c0 - 1; ++x) {
+      real vv = real(0);
+      if (jf > 0 && jf < ny) vv = real(0.5) * (uy[(jf - 1) * a.pL + x] + uy[jf * a.pL + x]);
+      v[jf * a.pF + fidx(a, x)] = vv;
+    }
+  }
+  const double tot_u = block_sum1024(su, sh);
+  const double tot_r = block_sum1024(sr, sh);
+  const real mean_u = (real)(tot_u / ny);
+  for (int j = threadIdx.x; j < ny; j += blockDim.x) u[j * a.pF + fidx(a, c0)] -= mean_u;
+  if (threadIdx.x == 0) a.iface[0] = tot_r / (3.0 * ny);
+}
+
+// 2. momentum: u* on x-faces c0+1 .. nx-1, v* on y-faces 1 .. ny-1 of the
+//    FV cells; wall and prescribed faces copied.
+template <typename real>
+__global__ __launch_bounds__(256) void k_dd_momentum(SplitArgs<real> a) {
+  const int x = a.c0 + blockIdx.x * blockDim.x + threadIdx.x;  // c0 .. nx
+  const int j = blockIdx.y;                                    // 0 .. ny
+  if (x > a.nx) return;
+  const int conv = a.conv;
+  const real nu = a.nu;
+  // ---- u* at face (x, j)
+  if (j < a.ny) {
+    real out;
+    if (x == a.c0) {
+      out = a.u[j * a.pF + fidx(a, x)];  // prescribed inflow face
+    } else if (x == a.nx) {
+      out = real(0);                     // east wall
+    } else {
+      real Fc[2], Gc[2];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int m = x - 1 + k;
+        const real ub = real(0.5) * (U_at(a, a.u, m, j) + U_at(a, a.u, m + 1, j));
+        const real uh = quick(conv, ub, U_at(a, a.u, m - 1, j), U_at(a, a.u, m, j),
+                              U_at(a, a.u, m + 1, j), U_at(a, a.u, m + 2, j));
+        Fc[k] = ub * uh;
+        const int jf = j + k;
+        const real vb = real(0.5) * (V_at(a, a.v, x - 1, jf) + V_at(a, a.v, x, jf));
+        const real uh2 = quick(conv, vb, U_at(a, a.u, x, jf - 2), U_at(a, a.u, x, jf - 1),
+                               U_at(a, a.u, x, jf), U_at(a, a.u, x, jf + 1));
+        Gc[k] = vb * uh2;
+      }
+      const real uc = U_at(a, a.u, x, j);
+      const real lap = U_at(a, a.u, x + 1, j) + U_at(a, a.u, x - 1, j) + U_at(a, a.u, x, j + 1) +
+                       U_at(a, a.u, x, j - 1) - real(4) * uc;
+      const real dp = P_at(a, x, j) - P_at(a, x - 1, j);
+      out = uc - (Fc[1] - Fc[0]) - (Gc[1] - Gc[0]) + nu * lap - dp;
+    }
+    a.us[j * a.pF + fidx(a, x)] = out;
+  }
+  // ---- v* at face (x, jf = j) for cells x < nx
+  if (x < a.nx) {
+    const int jf = j;
+    real out = real(0);
+    if (jf > 0 && jf < a.ny) {
+      real Fc[2], Gc[2];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int m = jf - 1 + k;
+        const real vb = real(0.5) * (V_at(a, a.v, x, m) + V_at(a, a.v, x, m + 1));
+        const real vh = quick(conv, vb, V_at(a, a.v, x, m - 1), V_at(a, a.v, x, m),
+                              V_at(a, a.v, x, m + 1), V_at(a, a.v, x, m + 2));
+        Fc[k] = vb * vh;
+        const int xc = x + k;
+        const real ub = real(0.5) * (U_at(a, a.u, xc, jf - 1) + U_at(a, a.u, xc, jf));
+        const real vh2 = quick(conv, ub, V_at(a, a.v, xc - 2, jf), V_at(a, a.v, xc - 1, jf),
+                               V_at(a, a.v, xc, jf), V_at(a, a.v, xc + 1, jf));
+        Gc[k] = ub * vh2;
+      }
+      const real vc = V_at(a, a.v, x, jf);
+      const real lap = V_at(a, a.v, x + 1, jf) + V_at(a, a.v, x - 1, jf) +
+                       V_at(a, a.v, x, jf + 1) + V_at(a, a.v, x, jf - 1) - real(4) * vc;
+      const real dp = P_at(a, x, jf) - P_at(a, x, jf - 1);
+      const real Tf = real(0.5) * (T_at(a, a.T, x, jf - 1) + T_at(a, a.T, x, jf));
+      out = vc - (Gc[1] - Gc[0]) - (Fc[1] - Fc[0]) + nu * lap - dp + a.gbeta * (Tf - a.Tref);
+    }
+    a.vs[jf * a.pF + fidx(a, x)] = out;
+  }
+}
+
+// 3. pressure (artificial compressibility, beta = c_s^2) and energy on u*
+template <typename real>
+__global__ __launch_bounds__(256) void k_dd_press_energy(SplitArgs<real> a) {
+  const int x = a.c0 + blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (x >= a.nx) return;
+  const int conv = a.conv;
+  const real al = a.alpha;
+  const real ue = x == a.nx - 1 ? real(0) : U_at(a, a.us, x + 1, j);
+  const real uw = U_at(a, a.us, x, j);
+  const real vn = V_at(a, a.vs, x, j + 1), vsd = V_at(a, a.vs, x, j);
+  const int o = j * a.pF + fidx(a, x);
+  a.p[o] = a.p[o] - real(1) / real(3) * ((ue - uw) + (vn - vsd));
+  real F[2], G[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int xf = x + k;
+    if (xf == a.nx) {
+      F[k] = a.tfix[1] ? real(-2) * al * (a.Tw[1] - a.T[o]) : real(0);
+    } else {
+      const real uf = U_at(a, a.us, xf, j);
+      const real th = quick(conv, uf, T_at(a, a.T, xf - 2, j), T_at(a, a.T, xf - 1, j),
+                            T_at(a, a.T, xf, j), T_at(a, a.T, xf + 1, j));
+      F[k] = fmad(uf, th, -al * (T_at(a, a.T, xf, j) - T_at(a, a.T, xf - 1, j)));
+    }
+    const int jf = j + k;
+    if (jf == 0) {
+      G[k] = a.tfix[2] ? real(-2) * al * (a.T[o] - a.Tw[2]) : real(0);
+    } else if (jf == a.ny) {
+      G[k] = a.tfix[3] ? real(-2) * al * (a.Tw[3] - a.T[o]) : real(0);
+    } else {
+      const real vf = V_at(a, a.vs, x, jf);
+      const real th = quick(conv, vf, T_at(a, a.T, x, jf - 2), T_at(a, a.T, x, jf - 1),
+                            T_at(a, a.T, x, jf), T_at(a, a.T, x, jf + 1));
+      G[k] = fmad(vf, th, -al * (T_at(a, a.T, x, jf) - T_at(a, a.T, x, jf - 1)));
+    }
+  }
+  a.Tn[o] = a.T[o] - (F[1] - F[0]) - (G[1] - G[0]);
+}
+
+// 4. p_bar: mean new FV pressure over the shared columns
+template <typename real>
+__global__ __launch_bounds__(1024) void k_dd_pbar(SplitArgs<real> a) {
+  __shared__ double sh[17];
+  double s = 0.0;
+  for (int j = threadIdx.x; j < a.ny; j += blockDim.x)
+    for (int x = a.c0; x <= a.ib; ++x) s += (double)a.p[j * a.pF + fidx(a, x)];
+  const double tot = block_sum1024(s, sh);
+  if (threadIdx.x == 0) a.iface[1] = tot / (3.0 * a.ny);
+}
+
+// 5. LBM zone, nodes 0 .. ib-1: stream, moments, collide
+template <typename real>
+__device__ __forceinline__ void collide_fg(const SplitArgs<real>& a, real f[9], real g[5],
+                                           real drho, real ux, real uy, real T) {
+  const real rho = real(1) + drho;
+  const real Gy = a.gbeta * (T - a.Tref);
+  const real Gu = Gy * uy;
+  const real usq = real(1.5) * fmad(ux, ux, uy * uy);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const real eu = real(ex9(q)) * ux + real(ey9(q)) * uy;
+    const real P = fmad(real(4.5) * eu, eu, real(3) * eu) - usq;
+    const real fe = w9<real>(q) * fmad(rho, P, drho);
+    const real c = (real(3) * w9<real>(q)) * (real(ey9(q)) * Gy - Gu);
+    f[q] = fmad(a.omega, fe - f[q], f[q]) + fmad(c, P, c);
+  }
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    const real ge = T * w5<real>(q) * (real(1) + real(3) * (real(ex5(q)) * ux + real(ey5(q)) * uy));
+    g[q] = fmad(a.omegaT, ge - g[q], g[q]);
+  }
+}
+
+template <typename real>
+__device__ __forceinline__ void moments9(const real f[9], real& drho, real& ux, real& uy) {
+  const real s = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+  const real jx = (f[1] - f[3]) + ((f[5] - f[6]) + (f[8] - f[7]));
+  const real jy = (f[2] - f[4]) + ((f[5] - f[7]) + (f[6] - f[8]));
+  drho = s;
+  const real inv = real(1) / (real(1) + s);
+  ux = jx * inv;
+  uy = jy * inv;
+}
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_dd_lbm(SplitArgs<real> a) {
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (i >= a.ib || j >= a.ny) return;
+  const int pL = a.pL, PL = a.planeL;
+  real f[9], g[5];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const int sx = i - ex9(q), sy = j - ey9(q);
+    if (sx >= 0 && sy >= 0 && sy < a.ny) f[q] = a.fin[q * PL + sy * pL + sx];
+    else f[q] = a.fin[opp9(q) * PL + j * pL + i];  // walls at rest: bounce-back
+  }
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    const int sx = i - ex5(q), sy = j - ey5(q);
+    const int side = sy < 0 ? 2 : sy >= a.ny ? 3 : sx < 0 ? 0 : -1;
+    if (side < 0) g[q] = a.gin[q * PL + sy * pL + sx];
+    else if (a.tfix[side])  // anti-bounce-back: fixed temperature
+      g[q] = -a.gin[opp5(q) * PL + j * pL + i] + real(2) * w5<real>(q) * a.Tw[side];
+    else  // bounce-back: adiabatic
+      g[q] = a.gin[opp5(q) * PL + j * pL + i];
+  }
+  real drho, ux, uy;
+  moments9(f, drho, ux, uy);
+  const real T = ((g[0] + g[1]) + (g[2] + g[3])) + g[4];
+  const int o = j * pL + i;
+  if (i == a.ib - 1) {  // keep x_f's streamed state for the boundary node
+    real* xf = a.xf + j * 18;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) xf[q] = f[q];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) xf[9 + q] = g[q];
+    xf[14] = drho;
+    xf[15] = ux;
+    xf[16] = uy;
+    xf[17] = T;
+  }
+  if (a.mom_all || i >= a.c0 - 2) {
+    a.mom[o] = real(1) + drho;
+    a.mom[PL + o] = ux;
+    a.mom[2 * PL + o] = uy;
+    a.mom[3 * PL + o] = T;
+  }
+  collide_fg(a, f, g, drho, ux, uy, T);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) a.fout[q * PL + o] = f[q];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) a.gout[q * PL + o] = g[q];
+}
+
+// 6. the artificial boundary node x_b = ib, one thread per row
+template <typename real>
+__global__ __launch_bounds__(256) void k_dd_xb(SplitArgs<real> a) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.ny) return;
+  const int ib = a.ib, ny = a.ny;
+  // FV state at the new time level (u*, v*, p, T_new)
+  const real ub = real(0.5) * (a.us[j * a.pF + fidx(a, ib)] + a.us[j * a.pF + fidx(a, ib + 1)]);
+  const real vb = real(0.5) * (a.vs[j * a.pF + fidx(a, ib)] + a.vs[(j + 1) * a.pF + fidx(a, ib)]);
+  const real Tb = a.Tn[j * a.pF + fidx(a, ib)];
+  const double rho0 = a.iface[0], pbar = a.iface[1];
+  // Eq 93: rho_b = rho0 ((p_S - p_bar) / (rho0 c_s^2) + 1)
+  const double rb = rho0 * (((double)a.p[j * a.pF + fidx(a, ib)] - pbar) / (rho0 / 3.0) + 1.0);
+  const real drb = (real)(rb - 1.0);
+  const real* xf = a.xf + j * 18;
+  real f[9], g[5];
+  if (a.kind == 0) {
+    // non-equilibrium extrapolation: f_b = f_eq(b) + f_f - f_eq(f)
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+      f[q] = feq_s<real>(q, drb, ub, vb) + (xf[q] - feq_s<real>(q, xf[14], xf[15], xf[16]));
+  } else {
+    // f_b = f_eq(b) - (tau w rho_b / c_s^2) Q : S, S from the FV velocities
+    const real dudx = a.us[j * a.pF + fidx(a, ib + 1)] - a.us[j * a.pF + fidx(a, ib)];
+    auto ucell = [&](int jj) {
+      return real(0.5) * (a.us[jj * a.pF + fidx(a, ib)] + a.us[jj * a.pF + fidx(a, ib + 1)]);
+    };
+    const real um = j > 0 ? ucell(j - 1) : -ub;
+    const real up = j < ny - 1 ? ucell(j + 1) : -ub;
+    const real vw = real(0.5) * (a.vs[j * a.pF + fidx(a, ib - 1)] + a.vs[(j + 1) * a.pF + fidx(a, ib - 1)]);
+    const real ve = real(0.5) * (a.vs[j * a.pF + fidx(a, ib + 1)] + a.vs[(j + 1) * a.pF + fidx(a, ib + 1)]);
+    const real Sxx = dudx, Syy = -dudx;
+    const real Sxy = real(0.5) * (real(0.5) * (up - um) + real(0.5) * (ve - vw));
+    const real rbr = (real)rb;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const real cx = real(ex9(q)), cy = real(ey9(q));
+      const real QS = (cx * cx - real(1) / real(3)) * Sxx + real(2) * cx * cy * Sxy +
+                      (cy * cy - real(1) / real(3)) * Syy;
+      f[q] = feq_s<real>(q, drb, ub, vb) - a.tau * w9<real>(q) * rbr * real(3) * QS;
+    }
+  }
+  // g by non-equilibrium extrapolation (Eq 95)
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    const real gb = Tb * w5<real>(q) * (real(1) + real(3) * (real(ex5(q)) * ub + real(ey5(q)) * vb));
+    const real gf = xf[17] * w5<real>(q) *
+                    (real(1) + real(3) * (real(ex5(q)) * xf[15] + real(ey5(q)) * xf[16]));
+    g[q] = gb + (xf[9 + q] - gf);
+  }
+  real drho, ux, uy;
+  moments9(f, drho, ux, uy);
+  const real T = ((g[0] + g[1]) + (g[2] + g[3])) + g[4];
+  const int o = j * a.pL + ib;
+  a.mom[o] = real(1) + drho;
+  a.mom[a.planeL + o] = ux;
+  a.mom[2 * a.planeL + o] = uy;
+  a.mom[3 * a.planeL + o] = T;
+  collide_fg(a, f, g, drho, ux, uy, T);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) a.fout[q * a.planeL + o] = f[q];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) a.gout[q * a.planeL + o] = g[q];
+}
+
+// dense output: LBM values for columns < s, FV (face-averaged) for >= s
+template <typename real>
+__global__ __launch_bounds__(256) void k_dd_output(SplitArgs<real> a, real* __restrict__ out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (x >= a.nx) return;
+  const int n = a.nx * a.ny, d = j * a.nx + x;
+  real r, u, v, t;
+  if (x < a.s) {
+    const int o = j * a.pL + x;
+    r = a.mom[o];
+    u = a.mom[a.planeL + o];
+    v = a.mom[2 * a.planeL + o];
+    t = a.mom[3 * a.planeL + o];
+  } else {
+    const int o = j * a.pF + fidx(a, x);
+    const real ue = x == a.nx - 1 ? real(0) : a.u[j * a.pF + fidx(a, x + 1)];
+    u = real(0.5) * (a.u[o] + ue);
+    v = real(0.5) * (a.v[o] + a.v[(j + 1) * a.pF + fidx(a, x)]);
+    t = a.T[o];
+    r = real(1) + real(3) * a.p[o];
+  }
+  out[d] = r;
+  out[n + d] = u;
+  out[2 * n + d] = v;
+  out[3 * n + d] = t;
+}
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_dd_init(SplitArgs<real> a, const double* __restrict__ T0) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (j >= a.ny) return;
+  const double t0 = (x < a.nx && T0) ? T0[j * a.nx + x] : 0.0;
+  if (x < a.nl) {
+    const int o = j * a.pL + x;
+    real* f = const_cast<real*>(a.fin);
+    real* g = const_cast<real*>(a.gin);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) f[q * a.planeL + o] = real(0);  // f = w at rest
+#pragma unroll
+    for (int q = 0; q < 5; ++q) g[q * a.planeL + o] = real(w5<double>(q) * t0);
+    a.mom[o] = real(1);
+    a.mom[a.planeL + o] = real(0);
+    a.mom[2 * a.planeL + o] = real(0);
+    a.mom[3 * a.planeL + o] = real(t0);
+  }
+  const int xf = x + a.c0 - 2;  // stored FV column
+  if (xf <= a.nx) {
+    const int o = j * a.pF + (xf - (a.c0 - 2));
+    real* u = const_cast<real*>(a.u);
+    real* v = const_cast<real*>(a.v);
+    real* T = const_cast<real*>(a.T);
+    u[o] = real(0);
+    a.us[o] = real(0);
+    a.p[o] = real(0);
+    T[o] = real((xf < a.nx && xf >= 0 && T0) ? T0[j * a.nx + xf] : 0.0);
+    a.Tn[o] = T[o];
+    v[o] = real(0);
+    a.vs[o] = real(0);
+    if (j == a.ny - 1) {
+      v[(j + 1) * a.pF + (xf - (a.c0 - 2))] = real(0);
+      a.vs[(j + 1) * a.pF + (xf - (a.c0 - 2))] = real(0);
+    }
+  }
+}
+
+}  // namespace
+
+template <typename real>
+static SplitArgs<real> make_args(const SplitGeom& G, const SplitPtrs<real>& P, const SplitParams& S,
+                                 int cur, int mom_all) {
+  SplitArgs<real> a;
+  const int nxt = cur ^ 1;
+  a.fin = P.f[cur];
+  a.fout = P.f[nxt];
+  a.gin = P.g[cur];
+  a.gout = P.g[nxt];
+  a.mom = P.mom;
+  a.xf = P.xf;
+  a.pL = G.pL;
+  a.planeL = G.pL * G.ny;
+  a.nl = G.ib + 1;
+  a.u = P.u[cur];
+  a.v = P.v[cur];
+  a.T = P.T[cur];
+  a.us = P.u[nxt];
+  a.vs = P.v[nxt];
+  a.Tn = P.T[nxt];
+  a.p = P.p;
+  a.pF = G.pF;
+  a.iface = P.iface;
+  a.nx = G.nx;
+  a.ny = G.ny;
+  a.s = G.s;
+  a.c0 = G.c0;
+  a.ib = G.ib;
+  a.conv = S.conv;
+  a.kind = S.kind;
+  a.mom_all = mom_all;
+  a.omega = real(1.0 / S.tau);
+  a.omegaT = real(1.0 / S.tauT);
+  a.tau = real(S.tau);
+  a.nu = real(S.nu);
+  a.alpha = real(S.alpha);
+  a.gbeta = real(S.gbeta);
+  a.Tref = real(S.T_ref);
+  for (int k = 0; k < 4; ++k) {
+    a.tfix[k] = S.tfix[k];
+    a.Tw[k] = real(S.Tw[k]);
+  }
+  return a;
+}
+
+template <typename real>
+hipError_t launch_split_step(const SplitGeom& G, const SplitPtrs<real>& P, const SplitParams& S,
+                             int cur, int mom_all, hipStream_t s) {
+  const SplitArgs<real> a = make_args<real>(G, P, S, cur, mom_all);
+  const int nfc = G.nx - G.c0 + 1;  // FV columns c0 .. nx
+  hipLaunchKernelGGL(k_dd_ghost<real>, dim3(1), dim3(1024), 0, s, a);
+  hipLaunchKernelGGL(k_dd_momentum<real>, dim3((nfc + 255) / 256, G.ny + 1), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_dd_press_energy<real>, dim3((nfc + 255) / 256, G.ny), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_dd_pbar<real>, dim3(1), dim3(1024), 0, s, a);
+  hipLaunchKernelGGL(k_dd_lbm<real>, dim3((G.ib + 63) / 64, (G.ny + 3) / 4), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_dd_xb<real>, dim3((G.ny + 255) / 256), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_split_init(const SplitGeom& G, const SplitPtrs<real>& P, const SplitParams& S,
+                             const double* T0, hipStream_t s) {
+  const SplitArgs<real> a = make_args<real>(G, P, S, 0, 1);
+  const int w = G.nx + 2 > G.ib + 1 ? G.nx + 2 : G.ib + 1;
+  hipLaunchKernelGGL(k_dd_init<real>, dim3((w + 255) / 256, G.ny), dim3(256), 0, s, a, T0);
+  // the second FV buffers start equal to the first (prescribed/wall faces)
+  const SplitArgs<real> b = make_args<real>(G, P, S, 1, 1);
+  hipLaunchKernelGGL(k_dd_init<real>, dim3((w + 255) / 256, G.ny), dim3(256), 0, s, b, T0);
+  return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_split_output(const SplitGeom& G, const SplitPtrs<real>& P, const SplitParams& S,
+                               int cur, real* out, hipStream_t s) {
+  const SplitArgs<real> a = make_args<real>(G, P, S, cur, 1);
+  hipLaunchKernelGGL(k_dd_output<real>, dim3((G.nx + 255) / 256, G.ny), dim3(256), 0, s, a, out);
+  return hipGetLastError();
+}
+
+#define LF_SPLIT_INST(real)                                                                   \
+  template hipError_t launch_split_step<real>(const SplitGeom&, const SplitPtrs<real>&,        \
+                                              const SplitParams&, int, int, hipStream_t);      \
+  template hipError_t launch_split_init<real>(const SplitGeom&, const SplitPtrs<real>&,        \
+                                              const SplitParams&, const double*, hipStream_t); \
+  template hipError_t launch_split_output<real>(const SplitGeom&, const SplitPtrs<real>&,      \
+                                                const SplitParams&, int, real*, hipStream_t);
+LF_SPLIT_INST(float)
+LF_SPLIT_INST(double)
+#undef LF_SPLIT_INST
+
+}  // namespace lf

@@ -58,10 +58,108 @@ struct lf_case {
   int cur;   // buffer holding the current state
   int64_t steps;
   bool inited;
+  // domain-decomposed mode
+  bool split;
+  lf::SplitGeom sg;
+  lf::SplitParams sp;
+  size_t off_sf[2], off_sg[2], off_smom, off_sxf, off_su[2], off_sv[2], off_sT[2], off_sp,
+      off_siface, off_dense, off_dsnap;
 };
 
 template <typename real>
 static real* fptr(lf_case* c, size_t off) { return (real*)(c->ws + off); }
+
+// Domain-decomposed layout: LBM zone (f, g ping-pong, moments, x_f rows),
+// FV zone (u, v, T ping-pong, p), interface scalars, dense output and
+// snapshot planes for residual / Nusselt / fetch.
+static void layout_split(lf_case* c) {
+  const lf::SplitGeom& G = c->sg;
+  const size_t pbL = align_up((size_t)G.pL * G.ny * c->es, 256);
+  const size_t pbF = align_up((size_t)G.pF * (G.ny + 1) * c->es, 256);
+  const size_t n = (size_t)G.nx * G.ny;
+  const size_t pbD = align_up(n * c->es, 256);
+  size_t o = 0;
+  for (int k = 0; k < 2; ++k) { c->off_sf[k] = o; o += 9 * pbL; }
+  for (int k = 0; k < 2; ++k) { c->off_sg[k] = o; o += 5 * pbL; }
+  c->off_smom = o; o += 4 * pbL;
+  c->off_sxf = o; o += align_up((size_t)18 * G.ny * c->es, 256);
+  for (int k = 0; k < 2; ++k) { c->off_su[k] = o; o += pbF; }
+  for (int k = 0; k < 2; ++k) { c->off_sv[k] = o; o += pbF; }
+  for (int k = 0; k < 2; ++k) { c->off_sT[k] = o; o += pbF; }
+  c->off_sp = o; o += pbF;
+  c->off_siface = o; o += 256;
+  c->off_dense = o; o += 4 * pbD;
+  c->off_dsnap = o; o += 3 * pbD;
+  c->off_part = o; o += align_up((size_t)c->nblk * 8 * sizeof(double), 256);
+  c->off_out = o; o += 256 * sizeof(double);
+  c->off_stage = o; o += align_up((size_t)3 * n * sizeof(double), 256);
+  c->need = o;
+}
+
+template <typename real>
+static lf::SplitPtrs<real> split_ptrs(lf_case* c) {
+  lf::SplitPtrs<real> P;
+  const lf::SplitGeom& G = c->sg;
+  const size_t pbL = align_up((size_t)G.pL * G.ny * c->es, 256);
+  for (int k = 0; k < 2; ++k) {
+    P.f[k] = (real*)(c->ws + c->off_sf[k]);
+    P.g[k] = (real*)(c->ws + c->off_sg[k]);
+    P.u[k] = (real*)(c->ws + c->off_su[k]);
+    P.v[k] = (real*)(c->ws + c->off_sv[k]);
+    P.T[k] = (real*)(c->ws + c->off_sT[k]);
+  }
+  (void)pbL;
+  P.mom = (real*)(c->ws + c->off_smom);
+  P.xf = (real*)(c->ws + c->off_sxf);
+  P.p = (real*)(c->ws + c->off_sp);
+  P.iface = (double*)(c->ws + c->off_siface);
+  return P;
+}
+
+// dense [ny][nx] planes used by the reductions in the split mode
+static lf::Grid dense_grid(const lf_case* c) {
+  lf::Grid g;
+  g.nx = c->sg.nx;
+  g.ny = c->sg.ny;
+  g.pitch = c->sg.nx;
+  g.plane = (long long)c->sg.nx * c->sg.ny;
+  return g;
+}
+
+template <typename real>
+static lf_status split_init(lf_case* c, const double* dT) {
+  hipStream_t s = c->ctx->stream;
+  const lf::SplitPtrs<real> P = split_ptrs<real>(c);
+  HIP_TRY(lf::launch_split_init<real>(c->sg, P, c->sp, dT, s));
+  real* dense = (real*)(c->ws + c->off_dense);
+  HIP_TRY(lf::launch_split_output<real>(c->sg, P, c->sp, 0, dense, s));
+  const size_t n = (size_t)c->sg.nx * c->sg.ny;
+  // residual snapshot: the u, v, T planes (contiguous after rho)
+  HIP_TRY(hipMemcpyAsync(c->ws + c->off_dsnap, dense + n, 3 * n * sizeof(real),
+                         hipMemcpyDeviceToDevice, s));
+  return LF_OK;
+}
+
+template <typename real>
+static lf_status split_steps(lf_case* c, int64_t n) {
+  hipStream_t s = c->ctx->stream;
+  const lf::SplitPtrs<real> P = split_ptrs<real>(c);
+  for (int64_t k = 0; k < n; ++k) {
+    HIP_TRY(lf::launch_split_step<real>(c->sg, P, c->sp, c->cur, k == n - 1 ? 1 : 0, s));
+    c->cur ^= 1;
+  }
+  c->steps += n;
+  return LF_OK;
+}
+
+// dense rho, u, v, T planes of the current split-mode state
+template <typename real>
+static lf_status split_dense(lf_case* c) {
+  const lf::SplitPtrs<real> P = split_ptrs<real>(c);
+  HIP_TRY(lf::launch_split_output<real>(c->sg, P, c->sp, c->cur, (real*)(c->ws + c->off_dense),
+                                        c->ctx->stream));
+  return LF_OK;
+}
 
 extern "C" {
 
@@ -116,7 +214,17 @@ lf_status lf_case_create(lf_ctx* ctx, const lf_case_desc* d, lf_case** out) {
   if (d->nx < 8 || d->ny < 8) return fail(LF_EINVAL, "nx, ny must be >= 8 (got %d, %d)", d->nx, d->ny);
   if (d->precision != LF_F32 && d->precision != LF_F64)
     return fail(LF_EINVAL, "precision must be LF_F32 or LF_F64");
-  if (d->mode != LF_MODE_HYBRID) return fail(LF_ENOTIMPL, "mode %d not available", d->mode);
+  if (d->mode != LF_MODE_HYBRID && d->mode != LF_MODE_SPLIT)
+    return fail(LF_EINVAL, "mode %d unknown", d->mode);
+  if (d->mode == LF_MODE_SPLIT) {
+    if (d->nx % 2 || d->nx < 12)
+      return fail(LF_EINVAL, "split mode needs an even nx >= 12 (got %d)", d->nx);
+    if (d->split_col != 0 && d->split_col != d->nx / 2)
+      return fail(LF_ENOTIMPL, "split_col must be nx/2 (0 selects it)");
+    if (d->overlap != 0 && d->overlap != 3) return fail(LF_ENOTIMPL, "overlap must be 3");
+    if (d->iface != LF_IFACE_NEQ_EXTRAP && d->iface != LF_IFACE_FD_GRADIENT)
+      return fail(LF_EINVAL, "bad iface %d", d->iface);
+  }
   const long long pitch = (d->nx + 63) / 64 * 64;
   const long long plane = pitch * d->ny;
   if (9 * plane >= (1LL << 31)) return fail(LF_EINVAL, "grid too large for 32-bit plane indexing");
@@ -136,7 +244,24 @@ lf_status lf_case_create(lf_ctx* ctx, const lf_case_desc* d, lf_case** out) {
   c->w.tfix[LF_SIDE_W] = 1; c->w.Tw[LF_SIDE_W] = 0.5;
   c->w.tfix[LF_SIDE_E] = 1; c->w.Tw[LF_SIDE_E] = -0.5;
   c->p.omega = 1.0;
-  layout(c);
+  if (d->mode == LF_MODE_SPLIT) {
+    c->split = true;
+    lf::SplitGeom& G = c->sg;
+    G.nx = d->nx;
+    G.ny = d->ny;
+    G.s = d->nx / 2;
+    G.c0 = G.s - 1;
+    G.ib = G.s + 1;
+    G.pL = (G.ib + 1 + 63) / 64 * 64;
+    G.pF = (G.nx - G.c0 + 3 + 63) / 64 * 64;
+    c->sp.kind = d->iface;
+    c->sp.tau = c->sp.tauT = 1.0;
+    c->sp.tfix[LF_SIDE_W] = 1; c->sp.Tw[LF_SIDE_W] = 0.5;
+    c->sp.tfix[LF_SIDE_E] = 1; c->sp.Tw[LF_SIDE_E] = -0.5;
+    layout_split(c);
+  } else {
+    layout(c);
+  }
   *out = c;
   return LF_OK;
 }
@@ -176,6 +301,20 @@ static lf_status apply_lattice(lf_case* c, double nu, double alpha, double gbeta
   const double tau = 3.0 * nu + 0.5;  // Eq 15 with c_s^2 = 1/3, Eq 42
   lf_status st = check_stable(tau, alpha);
   if (st != LF_OK) return st;
+  if (c->split && nu > 1.0 / 12.0)
+    return fail(LF_EUNSTABLE, "nu = %.6g: the explicit artificial-compressibility FV zone is "
+                "linearly stable only for nu <= 1/12", nu);
+  if (c->split && (gx != 0.0 || gy != 0.0))
+    return fail(LF_ENOTIMPL, "body forces are not available in the split mode");
+  c->sp.tau = tau;
+  c->sp.tauT = 3.0 * alpha + 0.5;
+  c->sp.nu = nu;
+  c->sp.alpha = alpha;
+  c->sp.gbeta = gbeta;
+  c->sp.T_ref = T_ref;
+  c->sp.conv = conv;
+  if (c->split && !(c->sp.tauT > 0.501))
+    return fail(LF_EUNSTABLE, "tau_T = %.6g must exceed 0.501", c->sp.tauT);
   c->p.omega = 1.0 / tau;
   c->p.alpha = alpha;
   c->p.gbeta = gbeta;
@@ -210,12 +349,14 @@ lf_status lf_case_set_physics(lf_case* c, const lf_physics* ph) {
   double U = ph->U_char;
   if (!(U > 0.0)) {
     // buoyancy velocity sqrt(g beta dT H) in lattice units: 0.1 unless the
-    // explicit updates need less (alpha <= 0.2, U^2 <= 2 alpha)
+    // explicit updates need less (alpha <= 0.2, U^2 <= 2 alpha; split mode
+    // also nu <= 0.08)
     U = 0.1;
     const double ua = 0.2 * sqrt(ph->Ra * ph->Pr) / H;
     if (ua < U) U = ua;
     if (c->desc.mode == LF_MODE_SPLIT) {
-      const double un = 0.2 * sqrt(ph->Ra / ph->Pr) / H;
+      // the artificial-compressibility FV zone needs nu <= 1/12
+      const double un = 0.08 * sqrt(ph->Ra / ph->Pr) / H;
       if (un < U) U = un;
     }
     const double ud = 2.0 * H / sqrt(ph->Ra * ph->Pr);
@@ -250,6 +391,12 @@ lf_status lf_case_set_wall(lf_case* c, int side, const lf_wall* w) {
     return fail(LF_EINVAL, "periodic velocity and periodic temperature go together");
   if (!per && w->thermal != LF_T_DIRICHLET && w->thermal != LF_T_ADIABATIC)
     return fail(LF_EINVAL, "bad thermal %d", w->thermal);
+  if (c->split) {
+    if (per) return fail(LF_ENOTIMPL, "periodic sides are not available in the split mode");
+    if (w->u_wall != 0.0) return fail(LF_ENOTIMPL, "moving walls are not available in the split mode");
+    c->sp.tfix[side] = w->thermal == LF_T_DIRICHLET;
+    c->sp.Tw[side] = w->T_wall;
+  }
   const int other = side ^ 1;  // W<->E, S<->N
   const bool axis_per = side < 2 ? c->w.xper : c->w.yper;
   // periodicity is a property of the axis: it is switched on/off for both sides
@@ -286,7 +433,11 @@ lf_status lf_case_init(lf_case* c, const double* T0, const double* u0, const dou
   if (u0) { HIP_TRY(hipMemcpyAsync(st + n, u0, n * 8, hipMemcpyHostToDevice, s)); du = st + n; }
   if (v0) { HIP_TRY(hipMemcpyAsync(st + 2 * n, v0, n * 8, hipMemcpyHostToDevice, s)); dv = st + 2 * n; }
   c->cur = 0;
-  if (c->desc.precision == LF_F32) {
+  if (c->split) {
+    if (u0 || v0) return fail(LF_ENOTIMPL, "the split mode starts from rest (u0 = v0 = NULL)");
+    lf_status st = c->desc.precision == LF_F32 ? split_init<float>(c, dT) : split_init<double>(c, dT);
+    if (st != LF_OK) return st;
+  } else if (c->desc.precision == LF_F32) {
     HIP_TRY(lf::launch_init<float>(c->g, dT, du, dv, fptr<float>(c, c->off_f[0]),
                                    fptr<float>(c, c->off_T[0]), fptr<float>(c, c->off_mom),
                                    fptr<float>(c, c->off_snap), s));
@@ -340,6 +491,8 @@ lf_status lf_case_step(lf_case* c, int64_t nsteps) {
   if (!c->inited) return fail(LF_ESTATE, "init before step");
   if (!c->have_params) return fail(LF_ESTATE, "set_physics or set_lattice before step");
   if (nsteps == 0) return LF_OK;
+  if (c->split)
+    return c->desc.precision == LF_F32 ? split_steps<float>(c, nsteps) : split_steps<double>(c, nsteps);
   return c->desc.precision == LF_F32 ? step_impl<float>(c, nsteps) : step_impl<double>(c, nsteps);
 }
 
@@ -363,7 +516,10 @@ lf_status lf_case_profile_steps(lf_case* c, int64_t nsteps, double* avg_ms, doub
   int64_t done = 0;
   for (int64_t k = 0; st == LF_OK && k < nchunks; ++k) {
     const int64_t m = (nsteps - done) < chunk ? (nsteps - done) : chunk;
-    st = c->desc.precision == LF_F32 ? step_impl<float>(c, m) : step_impl<double>(c, m);
+    if (c->split)
+      st = c->desc.precision == LF_F32 ? split_steps<float>(c, m) : split_steps<double>(c, m);
+    else
+      st = c->desc.precision == LF_F32 ? step_impl<float>(c, m) : step_impl<double>(c, m);
     if (st == LF_OK && hipEventRecord(ev[(size_t)k + 1], s) != hipSuccess)
       st = fail(LF_EDEVICE, "hipEventRecord");
     done += m;
@@ -404,7 +560,23 @@ lf_status lf_case_residual(lf_case* c, double r[3]) {
   hipStream_t s = c->ctx->stream;
   double* out = (double*)(c->ws + c->off_out);
   double* part = (double*)(c->ws + c->off_part);
-  if (c->desc.precision == LF_F32) {
+  if (c->split) {
+    const lf::Grid dg = dense_grid(c);
+    const size_t n = (size_t)dg.plane;
+    if (c->desc.precision == LF_F32) {
+      lf_status st = split_dense<float>(c);
+      if (st != LF_OK) return st;
+      float* d = fptr<float>(c, c->off_dense);
+      HIP_TRY(lf::launch_residual<float>(dg, d, d + 3 * n, fptr<float>(c, c->off_dsnap), part,
+                                         c->nblk, out, s));
+    } else {
+      lf_status st = split_dense<double>(c);
+      if (st != LF_OK) return st;
+      double* d = fptr<double>(c, c->off_dense);
+      HIP_TRY(lf::launch_residual<double>(dg, d, d + 3 * n, fptr<double>(c, c->off_dsnap), part,
+                                          c->nblk, out, s));
+    }
+  } else if (c->desc.precision == LF_F32) {
     HIP_TRY(lf::launch_residual<float>(c->g, fptr<float>(c, c->off_mom),
                                        fptr<float>(c, c->off_T[c->cur]),
                                        fptr<float>(c, c->off_snap), part, c->nblk, out, s));
@@ -465,7 +637,16 @@ lf_status lf_case_nusselt(lf_case* c, lf_nusselt* out) {
   if (!c->inited) return fail(LF_ESTATE, "init first");
   hipStream_t s = c->ctx->stream;
   double* dout = (double*)(c->ws + c->off_out) + 16;
-  if (c->desc.precision == LF_F32)
+  if (c->split) {
+    const lf::Grid dg = dense_grid(c);
+    const size_t n = (size_t)dg.plane;
+    lf_status st = c->desc.precision == LF_F32 ? split_dense<float>(c) : split_dense<double>(c);
+    if (st != LF_OK) return st;
+    if (c->desc.precision == LF_F32)
+      HIP_TRY(lf::launch_nusselt<float>(dg, c->w, fptr<float>(c, c->off_dense) + 3 * n, dout, s));
+    else
+      HIP_TRY(lf::launch_nusselt<double>(dg, c->w, fptr<double>(c, c->off_dense) + 3 * n, dout, s));
+  } else if (c->desc.precision == LF_F32)
     HIP_TRY(lf::launch_nusselt<float>(c->g, c->w, fptr<float>(c, c->off_T[c->cur]), dout, s));
   else
     HIP_TRY(lf::launch_nusselt<double>(c->g, c->w, fptr<double>(c, c->off_T[c->cur]), dout, s));
@@ -495,10 +676,18 @@ lf_status lf_case_fetch(lf_case* c, int field, void* dst, size_t dst_bytes, int 
   }
   hipStream_t s = c->ctx->stream;
   void* target = dst_is_device ? dst : (void*)(c->ws + c->off_stage);
+  lf::Grid g = c->g;
+  if (c->split) {
+    g = dense_grid(c);
+    lf_status st = c->desc.precision == LF_F32 ? split_dense<float>(c) : split_dense<double>(c);
+    if (st != LF_OK) return st;
+    const int plane_of[4] = {1, 2, 3, 0};  // U, V, T, RHO -> dense planes rho, u, v, T
+    off = c->off_dense + (size_t)plane_of[field] * (size_t)g.plane * c->es;
+  }
   if (c->desc.precision == LF_F32)
-    HIP_TRY(lf::launch_unpack<float>(c->g, fptr<float>(c, off), target, as_f64, s));
+    HIP_TRY(lf::launch_unpack<float>(g, fptr<float>(c, off), target, as_f64, s));
   else
-    HIP_TRY(lf::launch_unpack<double>(c->g, fptr<double>(c, off), target, as_f64, s));
+    HIP_TRY(lf::launch_unpack<double>(g, fptr<double>(c, off), target, as_f64, s));
   if (!dst_is_device) {
     HIP_TRY(hipMemcpyAsync(dst, target, need, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -512,6 +701,33 @@ lf_status lf_case_mass(lf_case* c, double* sum_f, double* sum_T) {
   hipStream_t s = c->ctx->stream;
   double* out = (double*)(c->ws + c->off_out) + 32;
   double* part = (double*)(c->ws + c->off_part);
+  if (c->split) {
+    // populations of the LBM zone (nodes 0 .. ib); T summed over the whole
+    // cavity from the output field
+    lf::Grid gl;
+    gl.nx = c->sg.ib + 1;
+    gl.ny = c->sg.ny;
+    gl.pitch = c->sg.pL;
+    gl.plane = (long long)c->sg.pL * c->sg.ny;
+    const size_t n = (size_t)c->sg.nx * c->sg.ny;
+    std::vector<double> T(n);
+    lf_status st = lf_case_fetch(c, LF_FIELD_T, T.data(), n * sizeof(double), 0, 1);
+    if (st != LF_OK) return st;
+    if (c->desc.precision == LF_F32)
+      HIP_TRY(lf::launch_mass<float>(gl, fptr<float>(c, c->off_sf[c->cur]),
+                                     fptr<float>(c, c->off_smom), part, c->nblk, out, s));
+    else
+      HIP_TRY(lf::launch_mass<double>(gl, fptr<double>(c, c->off_sf[c->cur]),
+                                      fptr<double>(c, c->off_smom), part, c->nblk, out, s));
+    double h[2];
+    HIP_TRY(hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double sT = 0.0;
+    for (double t : T) sT += t;
+    *sum_f = h[0] + (double)gl.nx * gl.ny;
+    *sum_T = sT;
+    return LF_OK;
+  }
   if (c->desc.precision == LF_F32)
     HIP_TRY(lf::launch_mass<float>(c->g, fptr<float>(c, c->off_f[c->cur]),
                                    fptr<float>(c, c->off_T[c->cur]), part, c->nblk, out, s));

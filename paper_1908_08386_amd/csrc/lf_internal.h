@@ -74,3 +74,50 @@ hipError_t launch_unpack(const Grid& g, const real* plane, void* dst,
                          int as_f64, hipStream_t s);
 
 }  // namespace lf
+
+namespace lf {
+
+// ---- domain-decomposed mode ---------------------------------------------
+// Geometry: nx even, s = nx / 2, FV cells from c0 = s - 1, LBM nodes up to
+// ib = s + 1; pL / pF are the row pitches of the LBM and FV arrays.
+struct SplitGeom {
+  int nx, ny, s, c0, ib, pL, pF;
+};
+
+template <typename real>
+struct SplitPtrs {
+  real* f[2];   // 9 planes of ny * pL each (shifted populations)
+  real* g[2];   // 5 planes
+  real* mom;    // rho, u, v, T planes of the LBM zone
+  real* xf;     // 18 values per row: streamed state of column ib - 1
+  real* u[2];   // x-faces, ny rows * pF
+  real* v[2];   // y-faces, (ny + 1) rows * pF
+  real* T[2];   // centres
+  real* p;      // centres
+  double* iface;  // [0] rho0, [1] p_bar
+};
+
+struct SplitParams {
+  double tau, tauT, nu, alpha, gbeta, T_ref;
+  int conv;   // 0 QUICK, 1 central, 2 upwind
+  int kind;   // 0 non-equilibrium extrapolation, 1 finite-difference gradient
+  int tfix[4];
+  double Tw[4];
+};
+
+// One step; the state is read from buffers [cur] and written to [cur ^ 1].
+// mom_all: write the moments of every LBM node (else only the shared and
+// ghost columns the next step needs).
+template <typename real>
+hipError_t launch_split_step(const SplitGeom& G, const SplitPtrs<real>& P, const SplitParams& S,
+                             int cur, int mom_all, hipStream_t s);
+// Rest state, T = T0 (dense [ny][nx] doubles in device memory, or null).
+template <typename real>
+hipError_t launch_split_init(const SplitGeom& G, const SplitPtrs<real>& P, const SplitParams& S,
+                             const double* T0, hipStream_t s);
+// Dense rho, u, v, T planes ([4][ny][nx]) of the current state.
+template <typename real>
+hipError_t launch_split_output(const SplitGeom& G, const SplitPtrs<real>& P, const SplitParams& S,
+                               int cur, real* out, hipStream_t s);
+
+}  // namespace lf

@@ -1,0 +1,119 @@
+"""GPU parity of the domain-decomposed mode (LBM west half, FV east half)
+against the FP64 oracle, through the C-ABI library."""
+import numpy as np
+import pytest
+
+import oracle
+from synth_inputs import perturbation
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lf():
+    import paper_1908_08386_amd as lf
+    return lf
+
+
+@pytest.fixture(scope="module")
+def ctx(lf):
+    return lf.Context(0)
+
+
+def rel_linf(a, b):
+    s = np.abs(b).max()
+    return np.abs(a - b).max() / (s if s > 0 else 1.0)
+
+
+def pair(lf, ctx, nx, ny, prec, iface, Ra=1e5, Pr=0.71, T0=None):
+    g = lf.Case(ctx, nx, ny, prec, mode=lf.MODE_SPLIT, iface=iface)
+    g.set_physics(Ra, Pr).set_cavity_walls().init(T0)
+    o = oracle.DDCase(nx, ny, oracle.SPLIT, iface).set_physics(Ra, Pr).set_cavity_walls()
+    o.init(T0)
+    assert abs(g.params()["nu"] - o.params["nu"]) < 1e-15
+    return g, o
+
+
+def check(g, o, tol, fields=("u", "v", "T", "rho")):
+    errs = {}
+    for f in fields:
+        a, b = g.fetch(f), o.fetch(f)
+        errs[f] = rel_linf(a - (1 if f == "rho" else 0), b - (1 if f == "rho" else 0))
+    for f, e in errs.items():
+        assert e <= tol, (f, e, errs)
+    return errs
+
+
+@pytest.mark.parametrize("iface", [0, 1])
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_split_parity_small(lf, ctx, iface, prec, tol):
+    oracle.set_threads(8)
+    nx, ny = 64, 48
+    T0 = perturbation(nx, ny, 31, amp=0.1)
+    g, o = pair(lf, ctx, nx, ny, prec, iface, T0=T0)
+    g.step(600)
+    o.step(600)
+    check(g, o, tol)
+    ng, no = g.nusselt(), o.nusselt()
+    for k in ("nu_hot", "nu_cold", "nu_hot_max"):
+        assert abs(ng[k] - no[k]) <= tol * abs(no[k]), k
+
+
+def test_split_parity_ragged_fp64(lf, ctx):
+    oracle.set_threads(8)
+    nx, ny = 138, 77  # split column 69: the LBM and FV zones span ragged tiles
+    T0 = perturbation(nx, ny, 32, amp=0.05)
+    g, o = pair(lf, ctx, nx, ny, "f64", 0, Ra=1e6, T0=T0)
+    for _ in range(3):
+        g.step(300)
+        o.step(300)
+        np.testing.assert_allclose(g.residual(), o.residual(), rtol=1e-8)
+    check(g, o, 1e-10)
+
+
+def test_split_128_fp32_2000_steps(lf, ctx):
+    oracle.set_threads(8)
+    n = 128
+    g, o = pair(lf, ctx, n, n, "f32", 0, Ra=1e6, T0=perturbation(n, n, 1908083860))
+    g.step(2000)
+    o.step(2000)
+    check(g, o, 1e-4, ("u", "v", "T"))
+
+
+def test_split_conduction_limit(lf, ctx):
+    nx, ny = 40, 16
+    g = lf.Case(ctx, nx, ny, "f64", mode=lf.MODE_SPLIT).set_lattice(0.05, 0.15, 0.0)
+    g.set_cavity_walls().init()
+    g.step(30000)
+    lin = np.tile(0.5 - (np.arange(nx) + 0.5) / nx, (ny, 1))
+    assert np.abs(g.fetch("T") - lin).max() < 1e-9
+    assert np.abs(g.fetch("u")).max() < 1e-12
+    assert abs(g.nusselt()["nu_hot"] - ny / nx) < 1e-8
+
+
+def test_split_errors(lf, ctx):
+    with pytest.raises(lf.LFError) as e:
+        lf.Case(ctx, 65, 32, mode=lf.MODE_SPLIT)
+    assert e.value.status == lf.LF_EINVAL
+    g = lf.Case(ctx, 64, 32, mode=lf.MODE_SPLIT)
+    with pytest.raises(lf.LFError) as e:
+        g.set_lattice(0.09, 0.05)  # above the FV zone's nu <= 1/12 bound
+    assert e.value.status == lf.LF_EUNSTABLE
+    with pytest.raises(lf.LFError) as e:
+        g.set_wall(lf.S, lf.WALL_PERIODIC, 0.0, lf.T_PERIODIC, 0.0)
+    assert e.value.status == lf.LF_ENOTIMPL
+
+
+def test_split_full_size_first_steps(lf, ctx):
+    """4096 x 4096 split cavity, Ra 1e6, FP32, in the benchmark's launch
+    configuration: element-wise parity with the oracle over the first steps."""
+    oracle.set_threads(16)
+    n = 4096
+    g, o = pair(lf, ctx, n, n, "f32", 0, Ra=1e6, T0=perturbation(n, n, 1908083860))
+    g.step(4)
+    o.step(4)
+    check(g, o, 1e-4, ("T",))
+    # velocities start from rest: compare against the field scale of T-driven flow
+    for f in ("u", "v"):
+        a, b = g.fetch(f), o.fetch(f)
+        assert np.abs(a - b).max() <= 1e-4 * max(np.abs(b).max(), 1e-12) + 1e-12, f
