@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run a few steps at 512^2 and 4096^2 and a 1 GiB device copy "
                          "(the calibration kernel), for rocprofv3 counter collection")
+    ap.add_argument("--split-point", type=int, default=4096,
+                    help="also time the domain-decomposed mode on an n x n cavity (0 = skip)")
     ap.add_argument("--hbm-point", type=int, default=4096,
                     help="also time the kernel on an n x n cavity whose working set is far "
                          "larger than the on-die caches (0 = skip)")
@@ -185,6 +187,25 @@ def main():
                                "kernel_ms_avg": round(a_ms, 5), "bytes_per_launch": b,
                                "mlups": round(m * m / (a_ms * 1e-3) / 1e6, 1)}
         del big
+
+    if args.split_point:
+        m = args.split_point
+        sp = lf.Case(ctx, m, m, "f32", mode=lf.MODE_SPLIT).set_physics(1e6, 0.71)
+        sp.set_cavity_walls().init(perturbation(m, m, SEED_C2))
+        sp.step(10)
+        a_ms, _, _ = sp.profile_steps(200)
+        # algorithmic bytes: LBM half 112 B/node (9 f + 5 g, read + write),
+        # FV half 32 B/cell (u, v, p, T read + write): 72 B per node on average
+        b = 72.0 * m * m
+        ach = b / (a_ms * 1e-3) / 1e9
+        out["split_point"] = {"workload": f"{m}x{m} split cavity (LBM west half, FV east half), "
+                                          "Ra 1e6, Pr 0.71, FP32, NEE interface",
+                              "ms_per_step": round(a_ms, 5),
+                              "mlups": round(m * m / (a_ms * 1e-3) / 1e6, 1),
+                              "achieved_GBs_at_72B": round(ach, 1),
+                              "frac_of_8TBs": round(ach / HBM_PEAK_GBS, 4),
+                              "U_char": sp.params()["U_char"]}
+        del sp
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, n, T0, args.cpu_seconds)
