@@ -126,7 +126,7 @@ def main():
                 c.residual()
 
     run(args.warmup)
-    stream = torch.cuda.current_stream()  # the stream the library launches on
+    stream = ctx.stream  # the stream the library launches on
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

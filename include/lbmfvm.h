@@ -84,6 +84,9 @@ typedef struct {
   int split_col; /* Mode DD: first FV cell is split_col - 1; 0 => nx/2      */
   int overlap;   /* Mode DD: shared columns; 0 => 3 (the only value)        */
   int iface;     /* Mode DD: LF_IFACE_NEQ_EXTRAP or LF_IFACE_FD_GRADIENT    */
+  int tcomp;     /* Mode H, FP32: 1 = temperature kept as a compensated
+                    pair hi + lo (FP32 words; increments below ulp(T) are
+                    not lost near steady state; +8 B per node), 0 = plain  */
 } lf_case_desc;
 
 /* Physical groups (Eq 82-89).  Ra > 0, Pr > 0.  U_char is the buoyancy
@@ -158,8 +161,8 @@ lf_status lf_case_step(lf_case* c, int64_t nsteps);
  * LF_EDIVERGED on NaN/Inf.                                                */
 lf_status lf_case_residual(lf_case* c, double r[3]);
 /* Step in blocks of check_every until max r <= tol (or all r = 0); in FP32
- * also stop "at the rounding floor" when max r <= 1e-6 and it fell by less
- * than 10 % over 3 consecutive checks.  r_final receives the last r;
+ * also stop "at the rounding floor" when max r <= 1e-6 and the last four
+ * checks set no new minimum of max r (noise, not slow decay).  r_final receives the last r;
  * *rule (may be NULL) LF_STOP_TOL or LF_STOP_FLOOR.  LF_ENOTCONV at
  * max_steps.                                                              */
 lf_status lf_case_run_to_steady(lf_case* c, double tol, int check_every,
@@ -183,6 +186,62 @@ lf_status lf_case_steps(const lf_case* c, int64_t* steps);
  * 64).  For measurement.                                                   */
 lf_status lf_case_profile_steps(lf_case* c, int64_t nsteps, double* avg_ms,
                                 double* min_ms, double* max_ms);
+
+/* ---- batches of Mode H cavities ---------------------------------------- */
+/* Many cavities of uneven size, aspect, Ra and Pr stepped together: every
+ * launch processes a table of wave tiles (62 columns x band rows) of all
+ * live cavities; run_to_steady replays a captured hipGraph of check_every
+ * steps plus the batched residual and retires converged cavities between
+ * replays.  Each cavity is exactly a Mode H case (same kernel code), so a
+ * batch member equals the same cavity run alone, bit for bit.  All cavities
+ * share one precision; QUICK convection; no periodic sides, no body force.
+ * The context stream must not be the legacy default stream (graph capture).
+ * walls: 4 per cavity (W, E, S, N) or NULL for the side-heated default.    */
+typedef struct lf_batch lf_batch;
+lf_status lf_batch_create(lf_ctx* ctx, int n, const lf_case_desc* descs,
+                          const lf_physics* phys, const lf_wall* walls,
+                          lf_batch** out);
+lf_status lf_batch_destroy(lf_batch* b);
+lf_status lf_batch_workspace_bytes(const lf_batch* b, size_t* bytes);
+lf_status lf_batch_bind_workspace(lf_batch* b, void* dev_ptr, size_t bytes);
+/* Rows per wave tile for cavity idx (-1: all cavities).                   */
+lf_status lf_batch_set_band(lf_batch* b, int idx, int rows);
+/* Initial state per cavity from n host pointers each (NULL array or NULL
+ * entry = 0), as lf_case_init.  All cavities become live.                 */
+lf_status lf_batch_init(lf_batch* b, const double* const* T0,
+                        const double* const* u0, const double* const* v0);
+/* Advance every live cavity nsteps steps (asynchronous).                  */
+lf_status lf_batch_step(lf_batch* b, int64_t nsteps);
+/* Residuals of the live cavities into r3n[3 idx .. 3 idx + 2] (others
+ * untouched), then re-snapshot; synchronises.                             */
+lf_status lf_batch_residual(lf_batch* b, double* r3n);
+/* Per-cavity stop rule of lf_case_run_to_steady with an even check_every;
+ * converged cavities stop stepping.  steps_each / rule_each / r_each (3 per
+ * cavity) may be NULL.  LF_ENOTCONV if a cavity hit max_steps.            */
+lf_status lf_batch_run_to_steady(lf_batch* b, double tol, int check_every,
+                                 int64_t max_steps, int64_t* steps_each,
+                                 int* rule_each, double* r_each);
+/* Make every cavity live again (after run_to_steady).                     */
+lf_status lf_batch_reactivate(lf_batch* b);
+lf_status lf_batch_get_params(const lf_batch* b, int idx, double out[8]);
+lf_status lf_batch_steps(const lf_batch* b, int idx, int64_t* steps);
+lf_status lf_batch_nusselt(lf_batch* b, int idx, lf_nusselt* out);
+lf_status lf_batch_fetch(lf_batch* b, int idx, int field, void* dst,
+                         size_t dst_bytes, int dst_is_device, int as_f64);
+/* Advance the live cavities nsteps (even) steps back to back between two
+ * HIP events; mean milliseconds per batched step.                         */
+lf_status lf_batch_profile_steps(lf_batch* b, int64_t nsteps, double* avg_ms);
+
+/* Autotuner: load the band table for batches from cache_path if it holds
+ * one for gfx950 / FP32; otherwise time band heights 1..16 per cavity-height
+ * class (64 .. 512 rows, aspect 2) on copies that fill dev_scratch (the
+ * library still allocates nothing), keep the fastest, write the cache, and
+ * use the table for batches created afterwards in this context.           */
+lf_status lf_autotune(lf_ctx* ctx, const char* cache_path, int budget_ms,
+                      void* dev_scratch, size_t scratch_bytes);
+/* The context's band table (nclass = 0 when none).                        */
+lf_status lf_ctx_get_tuning(const lf_ctx* ctx, int* nclass, int ny_class[16],
+                            int band[16]);
 
 #ifdef __cplusplus
 }

@@ -52,7 +52,7 @@ _STATUS = {0: "LF_OK", 1: "LF_EINVAL", 2: "LF_ENOMEM", 3: "LF_EWORKSPACE", 4: "L
 class lf_case_desc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("precision", ctypes.c_int),
                 ("mode", ctypes.c_int), ("split_col", ctypes.c_int), ("overlap", ctypes.c_int),
-                ("iface", ctypes.c_int)]
+                ("iface", ctypes.c_int), ("tcomp", ctypes.c_int)]
 
 
 class lf_physics(ctypes.Structure):
@@ -102,6 +102,31 @@ _SIGS = {
     "lf_case_mass": (ctypes.c_int, [_vp, _dp, _dp]),
     "lf_case_steps": (ctypes.c_int, [_vp, ctypes.POINTER(_i64)]),
     "lf_case_profile_steps": (ctypes.c_int, [_vp, _i64, _dp, _dp, _dp]),
+    "lf_batch_create": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(lf_case_desc),
+                                       ctypes.POINTER(lf_physics), ctypes.POINTER(lf_wall),
+                                       ctypes.POINTER(_vp)]),
+    "lf_batch_destroy": (ctypes.c_int, [_vp]),
+    "lf_batch_workspace_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "lf_batch_bind_workspace": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
+    "lf_batch_set_band": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    "lf_batch_init": (ctypes.c_int, [_vp, ctypes.POINTER(_dp), ctypes.POINTER(_dp),
+                                     ctypes.POINTER(_dp)]),
+    "lf_batch_step": (ctypes.c_int, [_vp, _i64]),
+    "lf_batch_residual": (ctypes.c_int, [_vp, _dp]),
+    "lf_batch_run_to_steady": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_int, _i64,
+                                              ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_int),
+                                              _dp]),
+    "lf_batch_reactivate": (ctypes.c_int, [_vp]),
+    "lf_batch_get_params": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
+    "lf_batch_steps": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(_i64)]),
+    "lf_batch_nusselt": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(lf_nusselt)]),
+    "lf_batch_fetch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_size_t,
+                                      ctypes.c_int, ctypes.c_int]),
+    "lf_batch_profile_steps": (ctypes.c_int, [_vp, _i64, _dp]),
+    "lf_autotune": (ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_int, _vp, ctypes.c_size_t]),
+    "lf_ctx_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(ctypes.c_int)]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -134,16 +159,36 @@ def _torch_stream_ptr(device: int):
 
 
 class Context:
-    """A HIP device and stream (torch's current stream on that device)."""
+    """A HIP device and the stream the library enqueues on.  By default a
+    dedicated torch stream (default priority) is created, so that batches can
+    capture graphs on it; ``ctx.stream`` is that torch.cuda.Stream."""
 
     def __init__(self, device: int = 0, stream=None):
         if not torch.cuda.is_available():
             raise RuntimeError("no ROCm GPU visible: the library runs on MI355X only")
         self.device = int(device)
-        s = _torch_stream_ptr(self.device) if stream is None else ctypes.c_void_p(int(stream))
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        s = ctypes.c_void_p(self.stream.cuda_stream)
         h = _vp()
         _check(_lib.lf_ctx_create(self.device, s, ctypes.byref(h)), "lf_ctx_create")
         self._h = h
+
+    def autotune(self, cache_path: str, budget_ms: int = 3000, scratch_bytes: int = 1 << 30):
+        """Load or measure the batch band table (see lf_autotune)."""
+        scratch = torch.empty(int(scratch_bytes), dtype=torch.uint8, device=f"cuda:{self.device}")
+        _check(_lib.lf_autotune(self._h, cache_path.encode(), int(budget_ms),
+                                ctypes.c_void_p(scratch.data_ptr()), scratch.numel()),
+               "lf_autotune")
+        torch.cuda.synchronize(self.device)
+        del scratch
+        return self.tuning()
+
+    def tuning(self) -> dict:
+        n = ctypes.c_int()
+        ny = (ctypes.c_int * 16)()
+        bd = (ctypes.c_int * 16)()
+        _check(_lib.lf_ctx_get_tuning(self._h, ctypes.byref(n), ny, bd), "lf_ctx_get_tuning")
+        return {int(ny[k]): int(bd[k]) for k in range(n.value)}
 
     def set_band(self, rows: int):
         _check(_lib.lf_ctx_set_band(self._h, int(rows)), "lf_ctx_set_band")
@@ -161,11 +206,14 @@ class Case:
     """One cavity (Mode H).  Fields are numpy arrays of shape (ny, nx)."""
 
     def __init__(self, ctx: Context, nx: int, ny: int, precision: str = "f32",
-                 mode: int = MODE_HYBRID, split_col: int = 0, iface: int = IFACE_NEQ_EXTRAP):
+                 mode: int = MODE_HYBRID, split_col: int = 0, iface: int = IFACE_NEQ_EXTRAP,
+                 tcomp: bool = True):
+        """tcomp: FP32 Mode H keeps T as a compensated hi + lo pair."""
         self.ctx = ctx
         self.nx, self.ny = int(nx), int(ny)
         self.precision = F64 if precision in ("f64", F64, "fp64", "double") else F32
-        d = lf_case_desc(self.nx, self.ny, self.precision, int(mode), int(split_col), 0, int(iface))
+        d = lf_case_desc(self.nx, self.ny, self.precision, int(mode), int(split_col), 0, int(iface),
+                         int(bool(tcomp)))
         h = _vp()
         _check(_lib.lf_case_create(ctx._h, ctypes.byref(d), ctypes.byref(h)), "lf_case_create")
         self._h = h
@@ -281,3 +329,127 @@ class Case:
         a, b = ctypes.c_double(), ctypes.c_double()
         _check(_lib.lf_case_mass(self._h, ctypes.byref(a), ctypes.byref(b)), "lf_case_mass")
         return a.value, b.value
+
+
+class Batch:
+    """Many Mode H cavities stepped together (see lf_batch_* in lbmfvm.h).
+
+    ``cases`` is a list of dicts with keys nx, ny and Ra, Pr (optional:
+    U_char, T_ref, walls = list of four (vel, u_wall, thermal, T_wall))."""
+
+    def __init__(self, ctx: Context, cases, precision: str = "f32", tcomp: bool = True):
+        self.ctx = ctx
+        self.n = len(cases)
+        prec = F64 if precision in ("f64", F64) else F32
+        D = (lf_case_desc * self.n)()
+        Ph = (lf_physics * self.n)()
+        Wl = (lf_wall * (4 * self.n))()
+        any_walls = False
+        self.shapes = []
+        for k, c in enumerate(cases):
+            D[k] = lf_case_desc(int(c["nx"]), int(c["ny"]), prec, MODE_HYBRID, 0, 0, 0,
+                                int(bool(tcomp)))
+            Ph[k] = lf_physics(float(c["Ra"]), float(c["Pr"]), float(c.get("U_char", 0.0)),
+                               float(c.get("T_ref", float("nan"))), CONV_QUICK, 0.0, 0.0)
+            walls = c.get("walls")
+            if walls is None:
+                walls = [(WALL_NOSLIP, 0.0, T_DIRICHLET, 0.5), (WALL_NOSLIP, 0.0, T_DIRICHLET, -0.5),
+                         (WALL_NOSLIP, 0.0, T_ADIABATIC, 0.0), (WALL_NOSLIP, 0.0, T_ADIABATIC, 0.0)]
+            else:
+                any_walls = True
+            for sd in range(4):
+                vel, uw, th, tw = walls[sd]
+                Wl[4 * k + sd] = lf_wall(int(vel), float(uw), int(th), float(tw))
+            self.shapes.append((int(c["ny"]), int(c["nx"])))
+        h = _vp()
+        _check(_lib.lf_batch_create(ctx._h, self.n, D, Ph, Wl if any_walls else None,
+                                    ctypes.byref(h)), "lf_batch_create")
+        self._h = h
+        nb = ctypes.c_size_t()
+        _check(_lib.lf_batch_workspace_bytes(h, ctypes.byref(nb)), "lf_batch_workspace_bytes")
+        self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=f"cuda:{ctx.device}")
+        _check(_lib.lf_batch_bind_workspace(h, ctypes.c_void_p(self.workspace.data_ptr()),
+                                            nb.value), "lf_batch_bind_workspace")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lf_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def set_band(self, rows: int, idx: int = -1):
+        _check(_lib.lf_batch_set_band(self._h, int(idx), int(rows)), "lf_batch_set_band")
+        return self
+
+    def init(self, T0=None, u0=None, v0=None):
+        keep = []
+
+        def arr(lst):
+            if lst is None:
+                return None
+            P = (_dp * self.n)()
+            for k in range(self.n):
+                a = lst[k]
+                if a is None:
+                    P[k] = None
+                else:
+                    a = np.ascontiguousarray(np.broadcast_to(np.asarray(a, np.float64),
+                                                             self.shapes[k]))
+                    keep.append(a)
+                    P[k] = a.ctypes.data_as(_dp)
+            return P
+        _check(_lib.lf_batch_init(self._h, arr(T0), arr(u0), arr(v0)), "lf_batch_init")
+        return self
+
+    def step(self, n: int):
+        _check(_lib.lf_batch_step(self._h, int(n)), "lf_batch_step")
+        return self
+
+    def residual(self) -> np.ndarray:
+        r = np.zeros(3 * self.n)
+        _check(_lib.lf_batch_residual(self._h, _dptr(r)), "lf_batch_residual")
+        return r.reshape(self.n, 3)
+
+    def run_to_steady(self, tol=1e-8, check_every=1000, max_steps=10**7, raise_on_notconv=True):
+        steps = (_i64 * self.n)()
+        rules = (ctypes.c_int * self.n)()
+        r = np.zeros(3 * self.n)
+        st = _lib.lf_batch_run_to_steady(self._h, float(tol), int(check_every), int(max_steps),
+                                         steps, rules, _dptr(r))
+        if st != LF_OK and not (st == LF_ENOTCONV and not raise_on_notconv):
+            raise LFError(st, "lf_batch_run_to_steady")
+        return np.array(steps[:]), np.array(rules[:]), r.reshape(self.n, 3)
+
+    def reactivate(self):
+        _check(_lib.lf_batch_reactivate(self._h), "lf_batch_reactivate")
+        return self
+
+    def params(self, idx: int) -> dict:
+        out = np.zeros(8)
+        _check(_lib.lf_batch_get_params(self._h, int(idx), _dptr(out)), "lf_batch_get_params")
+        return dict(zip(["U_char", "nu", "tau", "alpha", "tau_T", "gbeta", "T_ref", "Ma"],
+                        out.tolist()))
+
+    def steps(self, idx: int) -> int:
+        v = _i64()
+        _check(_lib.lf_batch_steps(self._h, int(idx), ctypes.byref(v)), "lf_batch_steps")
+        return v.value
+
+    def nusselt(self, idx: int) -> dict:
+        o = lf_nusselt()
+        _check(_lib.lf_batch_nusselt(self._h, int(idx), ctypes.byref(o)), "lf_batch_nusselt")
+        return {k: getattr(o, k) for k, _ in lf_nusselt._fields_}
+
+    def fetch(self, idx: int, field) -> np.ndarray:
+        out = np.empty(self.shapes[idx], dtype=np.float64)
+        _check(_lib.lf_batch_fetch(self._h, int(idx), _FIELDS.get(field, field),
+                                   out.ctypes.data_as(_vp), out.nbytes, 0, 1), "lf_batch_fetch")
+        return out
+
+    def profile_steps(self, n: int) -> float:
+        a = ctypes.c_double()
+        _check(_lib.lf_batch_profile_steps(self._h, int(n), ctypes.byref(a)),
+               "lf_batch_profile_steps")
+        return a.value

@@ -79,6 +79,9 @@ struct StepArgs {
   real* __restrict__ fout;
   const real* __restrict__ Tin;
   real* __restrict__ Tout;
+  // low words of a compensated (hi + lo) temperature, or null
+  const real* __restrict__ Tlo_in;
+  real* __restrict__ Tlo_out;
   real* __restrict__ mom;
   int plane;  // elements per plane
   int nx, ny, pitch, band, nstrips, nwaves;
@@ -107,6 +110,19 @@ __device__ __forceinline__ real recip(real x) {
 template <>
 __device__ __forceinline__ float recip<float>(float x) {
   return __builtin_amdgcn_rcpf(x);  // v_rcp_f32, 1 ulp
+}
+
+// Temperature update on a compensated pair: T = hi + lo advances by delta;
+// the rounding error of hi + delta (TwoSum, exact without contraction) is
+// carried in lo, so per-step increments far below ulp(T) still accumulate.
+template <typename real>
+__device__ __forceinline__ void t_update(real hi, real lo, real delta, real& nhi, real& nlo) {
+  const real s = hi + delta;
+  const real bp = s - hi;
+  const real err = (hi - (s - bp)) + (delta - bp);
+  const real l2 = lo + err;
+  nhi = s + l2;
+  nlo = l2 - (nhi - s);
 }
 
 // Moments of 9 streamed (shifted) populations.
@@ -164,7 +180,9 @@ __device__ __forceinline__ void pull_row(const StepArgs<real>& a, int ic, int r,
     if (side < 0) {
       v = a.fin[q * a.plane + sy * a.pitch + sx];
     } else {
-      const real uwall = a.uw[side];
+      // select, not an indexed load: keeps a locally built argument block
+      // in registers
+      const real uwall = side == 0 ? a.uw[0] : side == 1 ? a.uw[1] : side == 2 ? a.uw[2] : a.uw[3];
       const real eu = side >= 2 ? real(ex(q)) * uwall : real(ey(q)) * uwall;
       v = a.fin[opp(q) * a.plane + rr * a.pitch + ic] + real(6) * wq<real>(q) * eu;
     }
@@ -287,11 +305,18 @@ __device__ void march_general(const StepArgs<real>& a, int lane, int i, int j0, 
     else Fs = face_flux<real, CONV>(al, uy_p, uy_c, t0, t1, t2, t3);
     if (!a.yper && j == a.ny - 1) Fn = a.tfix[3] ? real(-2) * al * (a.Tw[3] - t2) : real(0);
     else Fn = face_flux<real, CONV>(al, uy_c, uy_n, t1, t2, t3, t4);
-    const real Tnew = t2 - (Fe - Fw) - (Fn - Fs);
+    real Tnew, Tlo = real(0);
+    if (a.Tlo_in) {
+      const real lo = a.Tlo_in[j * a.pitch + ic];
+      t_update(t2, lo, -(Fe - Fw) - (Fn - Fs), Tnew, Tlo);
+    } else {
+      Tnew = t2 - (Fe - Fw) - (Fn - Fs);
+    }
     if (act) {
       real fo[9];
       collide(a, fc, dr_c, ux_c, uy_c, Tnew, fo);
       store_node(a, j * a.pitch + i, fo, Tnew, dr_c, ux_c, uy_c);
+      if (a.Tlo_out) a.Tlo_out[j * a.pitch + i] = Tlo;
     }
     uy_p = uy_c;
 #pragma unroll
@@ -421,10 +446,17 @@ __device__ void march_interior(const StepArgs<real>& a, int lane, int i, int j0,
     const real Fe = face_flux<real, CONV>(al, ux_c, uE, tW1, t2, tE1, tE2);
     const real Fw = __shfl_up(Fe, 1, 64);
     const real Fn = face_flux<real, CONV>(al, uy_c, uy_n, t1, t2, t3, t4);
-    const real Tnew = t2 - (Fe - Fw) - (Fn - Fs);
+    real Tnew, Tlo = real(0);
+    if (a.Tlo_in) {
+      const real lo = a.Tlo_in[j * P + i];
+      t_update(t2, lo, -(Fe - Fw) - (Fn - Fs), Tnew, Tlo);
+    } else {
+      Tnew = t2 - (Fe - Fw) - (Fn - Fs);
+    }
     if (act) {
       real fo[9];
       collide(a, fc, dr_c, ux_c, uy_c, Tnew, fo);
+      if (a.Tlo_out) a.Tlo_out[j * P + i] = Tlo;
       const int vo = (j * P + i) * es;
 #pragma unroll
       for (int q = 0; q < 9; ++q) bstore<real>(fo[q], wf, vo, q * a.plane * es);
@@ -495,6 +527,129 @@ void k_hybrid_step(StepArgs<real> a) {
 }
 
 // ---------------------------------------------------------------------------
+// Batched step: many cavities, one launch.  The work list is a table of
+// tiles (cavity, strip, first row, end row); each wave takes one tile and
+// runs exactly the march of the single-cavity kernel on it, with the
+// cavity's geometry, parameters and buffers read from a descriptor table in
+// device memory (wave-uniform, so they land in scalar registers).  Buffer
+// [cur ^ parity] is read and [cur ^ parity ^ 1] written, so a sequence of
+// launches with alternating parity can be captured in a graph once and
+// replayed; the number of live tiles is read from device memory, so the
+// same graph serves a shrinking set of unconverged cavities.
+template <typename real, int CONV>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LF_STEP_WAVES(real))))
+void k_batch_step(const TileDesc* __restrict__ tiles, const int* __restrict__ ntiles,
+                  const CavDesc<real>* __restrict__ cavs, int parity, int write_mom) {
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int per = nb / 8, rem = nb % 8, x = b % 8;
+  const int lb = x * per + (x < rem ? x : rem) + b / 8;
+  // the wave index is uniform; telling the compiler so makes the tile and
+  // cavity descriptors scalar loads held in SGPRs
+  const int wave = __builtin_amdgcn_readfirstlane(lb * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  if (wave >= *ntiles) return;  // uniform per wave
+  const TileDesc t = tiles[wave];
+  const CavDesc<real>& cd = cavs[t.cav];
+  StepArgs<real> a;
+  const int in = cd.cur ^ parity;
+  a.fin = cd.f[in];
+  a.fout = cd.f[in ^ 1];
+  a.Tin = cd.T[in];
+  a.Tout = cd.T[in ^ 1];
+  a.Tlo_in = cd.Tlo[in];
+  a.Tlo_out = cd.Tlo[in ^ 1];
+  a.mom = write_mom ? cd.mom : nullptr;
+  a.plane = cd.plane;
+  a.nx = cd.nx;
+  a.ny = cd.ny;
+  a.pitch = cd.pitch;
+  a.band = t.j1 - t.j0;
+  a.nstrips = 0;
+  a.nwaves = 0;
+  a.xper = 0;
+  a.yper = 0;
+  a.conv = CONV;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    a.tfix[k] = cd.tfix[k];
+    a.uw[k] = real(cd.uw[k]);
+    a.Tw[k] = real(cd.Tw[k]);
+  }
+  a.omega = real(cd.omega);
+  a.alpha = real(cd.alpha);
+  a.gbeta = real(cd.gbeta);
+  a.Tref = real(cd.Tref);
+  a.gx = real(0);
+  a.gy = real(0);
+  const int lane = threadIdx.x & 63;
+  const int c0 = t.strip * kOut;
+  const int i = c0 + lane - 1;
+  const int j0 = t.j0, j1 = t.j1;
+  const bool interior = c0 - 1 >= 1 && c0 + kOut <= a.nx - 2 && j0 - 1 >= 2 && j1 <= a.ny - 2;
+  if (interior) march_interior<real, CONV>(a, lane, i, j0, j1);
+  else march_general<real, CONV>(a, lane, i, j0, j1);
+}
+
+// Batched residual, pass 1: one block per (cavity, row range); six FP64
+// sums and a non-finite count per block, snapshot updated.
+template <typename real>
+__global__ __launch_bounds__(256) void k_batch_resid(const ResidTile* __restrict__ rt,
+                                                     const int* __restrict__ nrt,
+                                                     const CavDesc<real>* __restrict__ cavs,
+                                                     double* __restrict__ part) {
+  if ((int)blockIdx.x >= *nrt) return;
+  __shared__ double sh[4][7];
+  const ResidTile t = rt[blockIdx.x];
+  const CavDesc<real>& cd = cavs[t.cav];
+  const real* mom = cd.mom;
+  const real* T = cd.T[cd.cur];
+  real* snap = cd.snap;
+  const int P = cd.plane;
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int j = t.j0; j < t.j1; ++j)
+    for (int i = threadIdx.x; i < cd.nx; i += 256) {
+      const int o = j * cd.pitch + i;
+      const double u = (double)mom[P + o], v = (double)mom[2 * P + o], tt = (double)T[o];
+      const double su = (double)snap[o], sv = (double)snap[P + o], st = (double)snap[2 * P + o];
+      acc[0] += (u - su) * (u - su);
+      acc[1] += u * u;
+      acc[2] += (v - sv) * (v - sv);
+      acc[3] += v * v;
+      acc[4] += (tt - st) * (tt - st);
+      acc[5] += tt * tt;
+      if (!(isfinite(u) && isfinite(v) && isfinite(tt))) acc[6] += 1.0;
+      snap[o] = mom[P + o];
+      snap[P + o] = mom[2 * P + o];
+      snap[2 * P + o] = T[o];
+    }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    double v = acc[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) sh[w][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 7; ++k)
+      part[blockIdx.x * 8 + k] = ((sh[0][k] + sh[1][k]) + (sh[2][k] + sh[3][k]));
+}
+
+// Batched residual, pass 2: per live cavity, its blocks' partials in order.
+__global__ __launch_bounds__(256) void k_batch_fold(const FoldDesc* __restrict__ fd,
+                                                    const int* __restrict__ nfold,
+                                                    const double* __restrict__ part,
+                                                    double* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= *nfold) return;
+  const FoldDesc d = fd[k];
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int b = 0; b < d.count; ++b)
+    for (int q = 0; q < 7; ++q) acc[q] += part[(d.start + b) * 8 + q];
+  for (int q = 0; q < 7; ++q) out[d.cav * 8 + q] = acc[q];
+}
+
+// ---------------------------------------------------------------------------
 template <typename real>
 __global__ __launch_bounds__(256) void k_init(int nx, int ny, int pitch, int plane,
                                               const double* __restrict__ T0,
@@ -502,7 +657,8 @@ __global__ __launch_bounds__(256) void k_init(int nx, int ny, int pitch, int pla
                                               const double* __restrict__ v0,
                                               real* __restrict__ f, real* __restrict__ T,
                                               real* __restrict__ mom,
-                                              real* __restrict__ snap) {
+                                              real* __restrict__ snap,
+                                              real* __restrict__ Tlo) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= nx) return;
@@ -516,6 +672,7 @@ __global__ __launch_bounds__(256) void k_init(int nx, int ny, int pitch, int pla
     f[q * plane + o] = real(wq<double>(q) * (3.0 * eu + 4.5 * eu * eu - usq));
   }
   T[o] = real(t);
+  if (Tlo) Tlo[o] = real(t - (double)real(t));
   mom[o] = real(1);
   mom[plane + o] = real(u);
   mom[2 * plane + o] = real(v);
@@ -529,8 +686,11 @@ __global__ __launch_bounds__(256) void k_init(int nx, int ny, int pitch, int pla
 template <typename real>
 hipError_t launch_hybrid_step(const Grid& g, const WallSet& w, const HybridParams& p,
                               const real* fin, real* fout, const real* Tin, real* Tout,
-                              real* mom, int band, hipStream_t s) {
+                              const real* Tlo_in, real* Tlo_out, real* mom, int band,
+                              hipStream_t s) {
   StepArgs<real> a;
+  a.Tlo_in = Tlo_in;
+  a.Tlo_out = Tlo_out;
   a.fin = fin;
   a.fout = fout;
   a.Tin = Tin;
@@ -570,22 +730,63 @@ hipError_t launch_hybrid_step(const Grid& g, const WallSet& w, const HybridParam
 
 template <typename real>
 hipError_t launch_init(const Grid& g, const double* T0, const double* u0, const double* v0,
-                       real* f, real* T, real* mom, real* snap, hipStream_t s) {
+                       real* f, real* T, real* mom, real* snap, real* Tlo, hipStream_t s) {
   dim3 grid((g.nx + 255) / 256, g.ny);
   hipLaunchKernelGGL(k_init<real>, grid, dim3(256), 0, s, g.nx, g.ny, g.pitch,
-                     (int)g.plane, T0, u0, v0, f, T, mom, snap);
+                     (int)g.plane, T0, u0, v0, f, T, mom, snap, Tlo);
   return hipGetLastError();
 }
 
+template <typename real>
+hipError_t launch_batch_step(const TileDesc* tiles, const int* ntiles, int max_tiles,
+                             const CavDesc<real>* cavs, int parity, int write_mom, int conv,
+                             hipStream_t s) {
+  const int blocks = (max_tiles + 3) / 4;
+  if (blocks < 1) return hipSuccess;
+  if (conv == 1)
+    hipLaunchKernelGGL((k_batch_step<real, 1>), dim3(blocks), dim3(256), 0, s, tiles, ntiles,
+                       cavs, parity, write_mom);
+  else if (conv == 2)
+    hipLaunchKernelGGL((k_batch_step<real, 2>), dim3(blocks), dim3(256), 0, s, tiles, ntiles,
+                       cavs, parity, write_mom);
+  else
+    hipLaunchKernelGGL((k_batch_step<real, 0>), dim3(blocks), dim3(256), 0, s, tiles, ntiles,
+                       cavs, parity, write_mom);
+  return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_batch_residual(const ResidTile* rt, const int* nrt, int max_rt,
+                                 const FoldDesc* fd, const int* nfold, int max_fold,
+                                 const CavDesc<real>* cavs, double* part, double* out,
+                                 hipStream_t s) {
+  if (max_rt < 1 || max_fold < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_resid<real>, dim3(max_rt), dim3(256), 0, s, rt, nrt, cavs, part);
+  hipLaunchKernelGGL(k_batch_fold, dim3((max_fold + 255) / 256), dim3(256), 0, s, fd, nfold,
+                     part, out);
+  return hipGetLastError();
+}
+
+template hipError_t launch_batch_step<float>(const TileDesc*, const int*, int,
+                                             const CavDesc<float>*, int, int, int, hipStream_t);
+template hipError_t launch_batch_step<double>(const TileDesc*, const int*, int,
+                                              const CavDesc<double>*, int, int, int, hipStream_t);
+template hipError_t launch_batch_residual<float>(const ResidTile*, const int*, int, const FoldDesc*,
+                                                 const int*, int, const CavDesc<float>*, double*,
+                                                 double*, hipStream_t);
+template hipError_t launch_batch_residual<double>(const ResidTile*, const int*, int,
+                                                  const FoldDesc*, const int*, int,
+                                                  const CavDesc<double>*, double*, double*,
+                                                  hipStream_t);
 template hipError_t launch_hybrid_step<float>(const Grid&, const WallSet&, const HybridParams&,
                                               const float*, float*, const float*, float*,
-                                              float*, int, hipStream_t);
+                                              const float*, float*, float*, int, hipStream_t);
 template hipError_t launch_hybrid_step<double>(const Grid&, const WallSet&, const HybridParams&,
                                                const double*, double*, const double*, double*,
-                                               double*, int, hipStream_t);
+                                               const double*, double*, double*, int, hipStream_t);
 template hipError_t launch_init<float>(const Grid&, const double*, const double*, const double*,
-                                       float*, float*, float*, float*, hipStream_t);
+                                       float*, float*, float*, float*, float*, hipStream_t);
 template hipError_t launch_init<double>(const Grid&, const double*, const double*, const double*,
-                                        double*, double*, double*, double*, hipStream_t);
+                                        double*, double*, double*, double*, double*, hipStream_t);
 
 }  // namespace lf

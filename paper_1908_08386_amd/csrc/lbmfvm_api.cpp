@@ -11,13 +11,14 @@
 #include <vector>
 
 #include "../../include/lbmfvm.h"
+#include "lf_host.h"
 #include "lf_internal.h"
 
 namespace {
-
 thread_local char g_err[512] = "";
+}  // namespace
 
-lf_status fail(lf_status st, const char* fmt, ...) {
+lf_status lf_fail(lf_status st, const char* fmt, ...) {
   va_list ap;
   va_start(ap, fmt);
   vsnprintf(g_err, sizeof(g_err), fmt, ap);
@@ -25,22 +26,9 @@ lf_status fail(lf_status st, const char* fmt, ...) {
   return st;
 }
 
-#define HIP_TRY(expr)                                                        \
-  do {                                                                       \
-    hipError_t e_ = (expr);                                                  \
-    if (e_ != hipSuccess)                                                    \
-      return fail(LF_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));       \
-  } while (0)
-
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-}  // namespace
-
-struct lf_ctx {
-  int device;
-  hipStream_t stream;
-  int band;  // 0: automatic
-};
+#define fail lf_fail
+#define HIP_TRY LF_HIP_TRY
+#define align_up lf_align_up
 
 struct lf_case {
   lf_ctx* ctx;
@@ -54,6 +42,8 @@ struct lf_case {
   char* ws;
   size_t ws_bytes;
   size_t off_f[2], off_T[2], off_mom, off_snap, off_part, off_out, off_stage, need;
+  size_t off_Tlo[2];  // compensated-temperature low words (0 if unused)
+  bool tcomp;
   int nblk;  // blocks of the reduction passes
   int cur;   // buffer holding the current state
   int64_t steps;
@@ -175,6 +165,7 @@ lf_status lf_ctx_create(int hip_device, void* hip_stream, lf_ctx** out) {
   HIP_TRY(hipSetDevice(hip_device));
   lf_ctx* c = new (std::nothrow) lf_ctx;
   if (!c) return fail(LF_ENOMEM, "ctx allocation");
+  memset(c, 0, sizeof(*c));
   c->device = hip_device;
   c->stream = (hipStream_t)hip_stream;
   c->band = 0;
@@ -203,6 +194,11 @@ static void layout(lf_case* c) {
   c->off_T[1] = o; o += pb;
   c->off_mom = o; o += 3 * pb;
   c->off_snap = o; o += 3 * pb;
+  c->off_Tlo[0] = c->off_Tlo[1] = 0;
+  if (c->tcomp) {
+    c->off_Tlo[0] = o; o += pb;
+    c->off_Tlo[1] = o; o += pb;
+  }
   c->off_part = o; o += align_up((size_t)c->nblk * 8 * sizeof(double), 256);
   c->off_out = o; o += 256 * sizeof(double);
   c->off_stage = o; o += align_up((size_t)3 * g.nx * g.ny * sizeof(double), 256);
@@ -260,6 +256,7 @@ lf_status lf_case_create(lf_ctx* ctx, const lf_case_desc* d, lf_case** out) {
     c->sp.tfix[LF_SIDE_E] = 1; c->sp.Tw[LF_SIDE_E] = -0.5;
     layout_split(c);
   } else {
+    c->tcomp = d->precision == LF_F32 && d->tcomp;
     layout(c);
   }
   *out = c;
@@ -342,10 +339,14 @@ lf_status lf_case_set_lattice(lf_case* c, double nu, double alpha, double gbeta,
   return LF_OK;
 }
 
-lf_status lf_case_set_physics(lf_case* c, const lf_physics* ph) {
-  if (!c || !ph) return fail(LF_EINVAL, "NULL argument");
+}  // extern "C"
+
+// Lattice parameters from the physical groups (Eq 15, 20, 42, 82-89), shared
+// by single cavities and batches.  out = {U_char, nu, tau, alpha, tau_T,
+// g beta, T_ref, Ma}.
+lf_status lf_derive_params(const lf_physics* ph, int ny, int split, double out[8]) {
   if (!(ph->Ra > 0.0) || !(ph->Pr > 0.0)) return fail(LF_EINVAL, "Ra and Pr must be > 0");
-  const double H = (double)c->g.ny;
+  const double H = (double)ny;
   double U = ph->U_char;
   if (!(U > 0.0)) {
     // buoyancy velocity sqrt(g beta dT H) in lattice units: 0.1 unless the
@@ -354,7 +355,7 @@ lf_status lf_case_set_physics(lf_case* c, const lf_physics* ph) {
     U = 0.1;
     const double ua = 0.2 * sqrt(ph->Ra * ph->Pr) / H;
     if (ua < U) U = ua;
-    if (c->desc.mode == LF_MODE_SPLIT) {
+    if (split) {
       // the artificial-compressibility FV zone needs nu <= 1/12
       const double un = 0.08 * sqrt(ph->Ra / ph->Pr) / H;
       if (un < U) U = un;
@@ -366,18 +367,27 @@ lf_status lf_case_set_physics(lf_case* c, const lf_physics* ph) {
   // g beta dT = U^2 / H with dT = 1
   const double nu = U * H * sqrt(ph->Pr / ph->Ra);
   const double alpha = nu / ph->Pr;
-  const double gbeta = U * U / H;
-  const double T_ref = isnan(ph->T_ref) ? 0.0 : ph->T_ref;
-  lf_status st = apply_lattice(c, nu, alpha, gbeta, T_ref, ph->body_gx, ph->body_gy, ph->conv);
+  out[0] = U;
+  out[1] = nu;
+  out[2] = 3.0 * nu + 0.5;
+  out[3] = alpha;
+  out[4] = 3.0 * alpha + 0.5;
+  out[5] = U * U / H;
+  out[6] = isnan(ph->T_ref) ? 0.0 : ph->T_ref;
+  out[7] = U * sqrt(3.0);  // Ma = U / c_s (Eq 84)
+  return LF_OK;
+}
+
+extern "C" {
+
+lf_status lf_case_set_physics(lf_case* c, const lf_physics* ph) {
+  if (!c || !ph) return fail(LF_EINVAL, "NULL argument");
+  double prm[8];
+  lf_status st = lf_derive_params(ph, c->g.ny, c->desc.mode == LF_MODE_SPLIT, prm);
   if (st != LF_OK) return st;
-  c->params[0] = U;
-  c->params[1] = nu;
-  c->params[2] = 3.0 * nu + 0.5;
-  c->params[3] = alpha;
-  c->params[4] = 3.0 * alpha + 0.5;
-  c->params[5] = gbeta;
-  c->params[6] = T_ref;
-  c->params[7] = U * sqrt(3.0);  // Ma = U / c_s (Eq 84)
+  st = apply_lattice(c, prm[1], prm[3], prm[5], prm[6], ph->body_gx, ph->body_gy, ph->conv);
+  if (st != LF_OK) return st;
+  memcpy(c->params, prm, sizeof(prm));
   c->have_params = true;
   return LF_OK;
 }
@@ -440,11 +450,12 @@ lf_status lf_case_init(lf_case* c, const double* T0, const double* u0, const dou
   } else if (c->desc.precision == LF_F32) {
     HIP_TRY(lf::launch_init<float>(c->g, dT, du, dv, fptr<float>(c, c->off_f[0]),
                                    fptr<float>(c, c->off_T[0]), fptr<float>(c, c->off_mom),
-                                   fptr<float>(c, c->off_snap), s));
+                                   fptr<float>(c, c->off_snap),
+                                   c->tcomp ? fptr<float>(c, c->off_Tlo[0]) : nullptr, s));
   } else {
     HIP_TRY(lf::launch_init<double>(c->g, dT, du, dv, fptr<double>(c, c->off_f[0]),
                                     fptr<double>(c, c->off_T[0]), fptr<double>(c, c->off_mom),
-                                    fptr<double>(c, c->off_snap), s));
+                                    fptr<double>(c, c->off_snap), nullptr, s));
   }
   // the host arrays may be freed on return: wait for the uploads
   HIP_TRY(hipStreamSynchronize(s));
@@ -474,9 +485,11 @@ static lf_status step_impl(lf_case* c, int64_t n) {
   for (int64_t k = 0; k < n; ++k) {
     const int a = c->cur, b = a ^ 1;
     real* mom = (k == n - 1) ? fptr<real>(c, c->off_mom) : nullptr;
-    HIP_TRY(lf::launch_hybrid_step<real>(c->g, c->w, c->p, fptr<real>(c, c->off_f[a]),
-                                         fptr<real>(c, c->off_f[b]), fptr<real>(c, c->off_T[a]),
-                                         fptr<real>(c, c->off_T[b]), mom, band, s));
+    HIP_TRY(lf::launch_hybrid_step<real>(
+        c->g, c->w, c->p, fptr<real>(c, c->off_f[a]), fptr<real>(c, c->off_f[b]),
+        fptr<real>(c, c->off_T[a]), fptr<real>(c, c->off_T[b]),
+        c->tcomp ? fptr<real>(c, c->off_Tlo[a]) : nullptr,
+        c->tcomp ? fptr<real>(c, c->off_Tlo[b]) : nullptr, mom, band, s));
     c->cur = b;
   }
   c->steps += n;
@@ -617,11 +630,7 @@ lf_status lf_case_run_to_steady(lf_case* c, double tol, int check_every, int64_t
     const double m = fmax(r[0], fmax(r[1], r[2]));
     hist.push_back(m);
     if (m <= tol || (r[0] == 0.0 && r[1] == 0.0 && r[2] == 0.0)) { fired = LF_STOP_TOL; break; }
-    if (c->desc.precision == LF_F32 && m <= 1e-6 && hist.size() >= 4) {
-      // FP32 rounding floor: no 10 % drop over the last three checks
-      const double before = hist[hist.size() - 4];
-      if (m > 0.9 * before) { fired = LF_STOP_FLOOR; break; }
-    }
+    if (c->desc.precision == LF_F32 && lf_at_floor(hist)) { fired = LF_STOP_FLOOR; break; }
   }
   if (steps_taken) *steps_taken = done;
   if (r_final) memcpy(r_final, r, sizeof(r));

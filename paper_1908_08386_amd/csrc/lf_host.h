@@ -1,0 +1,53 @@
+// Host-side helpers shared by the C-ABI translation units.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/lbmfvm.h"
+
+// set the thread-local error message and return st
+lf_status lf_fail(lf_status st, const char* fmt, ...);
+
+#define LF_HIP_TRY(expr)                                                   \
+  do {                                                                     \
+    hipError_t e_ = (expr);                                                \
+    if (e_ != hipSuccess)                                                  \
+      return lf_fail(LF_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));  \
+  } while (0)
+
+static inline size_t lf_align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// lattice parameters from Ra, Pr, U_char (0 = default rule), T_ref (NaN = 0)
+lf_status lf_derive_params(const lf_physics* ph, int ny, int split, double out[8]);
+
+// FP32 rounding floor of the residual: the largest residual is <= 1e-6 and
+// the last four checks set no new minimum (noise around a floor, not a slow
+// decay, which keeps setting new minima)
+#include <vector>
+static inline bool lf_at_floor(const std::vector<double>& h) {
+  const size_t n = h.size();
+  if (n < 6 || h[n - 1] > 1e-6) return false;
+  double before = h[0];
+  for (size_t k = 1; k + 4 < n; ++k) before = h[k] < before ? h[k] : before;
+  for (size_t k = n - 4; k < n; ++k)
+    if (h[k] < before) return false;
+  return true;
+}
+
+// band heights chosen per cavity-height class by the autotuner (0 = none)
+struct lf_tuning {
+  int valid;
+  int ny_class[16];
+  int band[16];
+  int nclass;
+};
+
+struct lf_ctx {
+  int device;
+  hipStream_t stream;
+  int band;  // rows per wave for single cavities; 0: automatic
+  lf_tuning tune;
+};

@@ -31,21 +31,66 @@ struct Grid {
   long long plane;    // elements per plane = ny * pitch
 };
 
+// ---- batched Mode H -------------------------------------------------------
+// One wave-sized tile of one cavity: 62 output columns from strip * 62,
+// rows j0 .. j1 - 1.
+struct TileDesc {
+  int cav, strip, j0, j1;
+};
+// One cavity of a batch: buffers, geometry, parameters, walls (no periodic
+// sides).  cur: buffer holding the state at the start of a launch sequence.
+template <typename real>
+struct CavDesc {
+  real* f[2];
+  real* T[2];
+  real* Tlo[2];  // compensated temperature low words, or null
+  real* mom;   // rho, u, v planes
+  real* snap;  // residual snapshot u, v, T planes
+  int nx, ny, pitch, plane;
+  int cur, pad0;
+  int tfix[4];
+  double Tw[4];
+  double uw[4];
+  double omega, alpha, gbeta, Tref;
+};
+// Residual work unit (rows j0 .. j1 - 1 of one cavity) and per-cavity fold
+// of consecutive partials.
+struct ResidTile {
+  int cav, j0, j1, pad;
+};
+struct FoldDesc {
+  int cav, start, count, pad;
+};
+
+template <typename real>
+hipError_t launch_batch_step(const TileDesc* tiles, const int* ntiles, int max_tiles,
+                             const CavDesc<real>* cavs, int parity, int write_mom, int conv,
+                             hipStream_t s);
+// residual sums per live cavity into out[cav * 8 + 0 .. 6]
+template <typename real>
+hipError_t launch_batch_residual(const ResidTile* rt, const int* nrt, int max_rt,
+                                 const FoldDesc* fd, const int* nfold, int max_fold,
+                                 const CavDesc<real>* cavs, double* part, double* out,
+                                 hipStream_t s);
+
 // One fused Mode H step: pull-stream + bounce-back + moments + explicit FV
 // energy update + BGK collision with buoyancy.  f planes are stored shifted
 // (f - w_q).  mom (rho, u, v planes) is written only when non-null.
+// Tlo_in / Tlo_out: low words of a compensated temperature (or null).
 template <typename real>
 hipError_t launch_hybrid_step(const Grid& g, const WallSet& w,
                               const HybridParams& p, const real* fin,
                               real* fout, const real* Tin, real* Tout,
+                              const real* Tlo_in, real* Tlo_out,
                               real* mom, int band, hipStream_t s);
 
 // f = f_eq(1, u0) - w, T = T0, mom = (1, u0, v0), snapshots = (u0, v0, T0)
 // from dense double staging arrays (u0 / v0 may be null for zero).
+// Tlo (or null) receives T0 - T in the case precision.
 template <typename real>
 hipError_t launch_init(const Grid& g, const double* T0, const double* u0,
                        const double* v0, real* f, real* T, real* mom,
-                       real* snap, hipStream_t s);
+                       real* snap, real* Tlo, hipStream_t s);
 
 // Residual partial sums: per block six FP64 sums
 // {sum (u-us)^2, sum u^2, sum (v-vs)^2, sum v^2, sum (T-Ts)^2, sum T^2}
