@@ -7,7 +7,8 @@ library (``paper_1908_08386_amd``) and never imports it.
 
 The arithmetic lives in ``lbmfvm_oracle.c`` (Mode H, Sec. 5) and
 ``dd_oracle.c`` (domain decomposition, Sec. 4); this module only marshals
-numpy arrays through ctypes.
+numpy arrays through ctypes.  ``net.py`` is the numpy FP64 reference of the
+learned initial guess (not part of the paper).
 """
 from __future__ import annotations
 
