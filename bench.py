@@ -82,6 +82,9 @@ def main():
     ap.add_argument("--hbm-point", type=int, default=4096,
                     help="also time the kernel on an n x n cavity whose working set is far "
                          "larger than the on-die caches (0 = skip)")
+    ap.add_argument("--batch-point", type=int, default=256,
+                    help="also time one launch per step over this many heterogeneous cavities "
+                         "of the sweep distribution (0 = skip)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -206,6 +209,25 @@ def main():
                               "frac_of_8TBs": round(ach / HBM_PEAK_GBS, 4),
                               "U_char": sp.params()["U_char"]}
         del sp
+
+    if args.batch_point:
+        from synth_inputs import cavity_sweep
+        cases = cavity_sweep(args.batch_point)
+        nodes = sum(cc["nx"] * cc["ny"] for cc in cases)
+        bt = lf.Batch(ctx, cases, "f32")
+        bt.init([perturbation(cc["nx"], cc["ny"], cc["seed"]) for cc in cases])
+        bt.step(10)
+        a_ms = bt.profile_steps(100)
+        b = BYTES_PER_LU_F32 * nodes
+        ach = b / (a_ms * 1e-3) / 1e9
+        out["batch_point"] = {"workload": f"{len(cases)} heterogeneous side-heated cavities "
+                                          "(ny 64..512, A 1..4, Ra 1e3..1e6, Pr 0.71/7), FP32, "
+                                          "all active, one launch per step",
+                              "nodes": nodes, "ms_per_step": round(a_ms, 5),
+                              "mlups": round(nodes / (a_ms * 1e-3) / 1e6, 1),
+                              "achieved_GBs_at_80B": round(ach, 1),
+                              "frac_of_8TBs": round(ach / HBM_PEAK_GBS, 4)}
+        del bt
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, n, T0, args.cpu_seconds)

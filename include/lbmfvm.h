@@ -243,6 +243,79 @@ lf_status lf_autotune(lf_ctx* ctx, const char* cache_path, int budget_ms,
 lf_status lf_ctx_get_tuning(const lf_ctx* ctx, int* nclass, int ny_class[16],
                             int band[16]);
 
+/* As lf_batch_init, but every non-NULL entry is a DEVICE pointer to a dense
+ * [ny][nx] array of doubles (read on the context stream; the arrays must
+ * stay valid until the stream reaches this point).                         */
+lf_status lf_batch_init_device(lf_batch* b, const double* const* T0,
+                               const double* const* u0, const double* const* v0);
+
+/* ---- learned initial guess (not part of the paper) ---------------------- */
+/* An encoder-decoder convolutional network maps the cavity parameters to
+ * steady fields on a res x res canvas (the unit square, cell-centred):
+ * channels u/U_char, v/U_char and theta = T + 1/2.  Inputs per pixel, in
+ * this order: X, Y (cell centres on the unit square), (log10 Ra - 4.5)/1.5,
+ * (Pr - 3.855)/3.145, A/4, then zeros up to cin.  The ten 3x3 convolutions
+ * (zero padding 1), widths w0..w4:
+ *   e0 = silu(conv_s1(x)); e_k = silu(conv_s2(e_{k-1})), k = 1..4;
+ *   d3 = silu(conv(up2(e4))) + e3; d2, d1, d0 likewise (up2 = nearest x2);
+ *   y = conv(d0) (linear, cout channels, the first 3 are used).
+ * Parameters: FP32 master copy, flat, per layer weights [Cout][3][3][Cin]
+ * then bias [Cout]; the convolutions run on bf16 operands with FP32
+ * accumulation (gfx950 matrix cores); training is MSE over the 3 channels
+ * with Adam (beta1 0.9, beta2 0.999, eps 1e-8).
+ * Device inputs: feat = [N][3] floats (log10 Ra, Pr, A) per sample,
+ * target = [N][3][res][res] floats, idx = [batch] int32 sample indices (or
+ * NULL for 0 .. batch-1), each in 0 .. N-1 (not checked: device memory).
+ * batch <= max_batch.                                                     */
+typedef struct {
+  int res;         /* canvas size, a multiple of 16                          */
+  int cin, cout;   /* cin = 8 (5 used); cout a multiple of 8 (3 used)        */
+  int widths[5];   /* multiples of 8                                         */
+  int max_batch;
+} lf_net_desc;
+typedef struct lf_net lf_net;
+lf_status lf_net_create(lf_ctx* ctx, const lf_net_desc* desc, lf_net** out);
+lf_status lf_net_destroy(lf_net* net);
+lf_status lf_net_param_count(const lf_net* net, int64_t* n);
+lf_status lf_net_workspace_bytes(const lf_net* net, size_t* bytes);
+lf_status lf_net_bind_workspace(lf_net* net, void* dev_ptr, size_t bytes);
+/* Host copies of the flat FP32 parameters; set also clears Adam's state.  */
+lf_status lf_net_set_weights(lf_net* net, const float* host, int64_t n);
+lf_status lf_net_get_weights(lf_net* net, float* host, int64_t n);
+/* Gradient of the last lf_net_backward (flat layout of the parameters).   */
+lf_status lf_net_get_grads(lf_net* net, float* host, int64_t n);
+/* Forward pass; pred (device, may be NULL) receives [batch][3][res][res].  */
+lf_status lf_net_forward(lf_net* net, const float* feat, const int* idx, int batch,
+                         float* pred);
+/* Raw output [batch][res][res][cout] of the last forward pass (host).     */
+lf_status lf_net_get_output(lf_net* net, float* host, size_t n);
+/* Forward + MSE + backward into the gradient buffer; loss (device float,
+ * may be NULL) receives the mean squared error.  Asynchronous.            */
+lf_status lf_net_backward(lf_net* net, const float* feat, const float* target,
+                          const int* idx, int batch, float* loss);
+/* One Adam step with the gradient buffer.                                 */
+lf_status lf_net_adam(lf_net* net, float lr);
+/* lf_net_backward followed by lf_net_adam.                                */
+lf_status lf_net_train_step(lf_net* net, const float* feat, const float* target,
+                            const int* idx, int batch, float lr, float* loss);
+/* Multiply-add count (x2) of one forward pass of one sample, and of the
+ * three passes of one training sample (forward, input and weight grads).  */
+lf_status lf_net_flops(const lf_net* net, double* fwd, double* train);
+/* nsteps training steps on one batch between two HIP events (synchronises);
+ * mean milliseconds per step.  For measurement.                           */
+lf_status lf_net_profile_train(lf_net* net, const float* feat, const float* target,
+                               const int* idx, int batch, float lr, int nsteps,
+                               double* avg_ms);
+
+/* Bilinear resampling between cell-centred grids covering the same
+ * rectangle: destination centre (i + 1/2)/dnx maps to the source index
+ * coordinate (i + 1/2) snx/dnx - 1/2, clamped to [0, snx - 1] (same in y);
+ * dst[j][i] = value * scale + offset.  src rows are src_row_stride elements
+ * apart; dst is dense [dny][dnx].  Device pointers; asynchronous.          */
+lf_status lf_resample(lf_ctx* ctx, const void* src, int src_is_f64, int snx, int sny,
+                      int64_t src_row_stride, void* dst, int dst_is_f64, int dnx,
+                      int dny, double scale, double offset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -72,8 +72,14 @@ class lf_nusselt(ctypes.Structure):
                  "nu_hot_o2", "nu_cold_o2")]
 
 
+class lf_net_desc(ctypes.Structure):
+    _fields_ = [("res", ctypes.c_int), ("cin", ctypes.c_int), ("cout", ctypes.c_int),
+                ("widths", ctypes.c_int * 5), ("max_batch", ctypes.c_int)]
+
+
 _vp = ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
+_fp = ctypes.POINTER(ctypes.c_float)
 _i64 = ctypes.c_int64
 
 _SIGS = {
@@ -127,6 +133,27 @@ _SIGS = {
     "lf_ctx_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(ctypes.c_int)]),
+    "lf_batch_init_device": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                            ctypes.POINTER(_vp)]),
+    "lf_net_create": (ctypes.c_int, [_vp, ctypes.POINTER(lf_net_desc), ctypes.POINTER(_vp)]),
+    "lf_net_destroy": (ctypes.c_int, [_vp]),
+    "lf_net_param_count": (ctypes.c_int, [_vp, ctypes.POINTER(_i64)]),
+    "lf_net_workspace_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "lf_net_bind_workspace": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
+    "lf_net_set_weights": (ctypes.c_int, [_vp, _fp, _i64]),
+    "lf_net_get_weights": (ctypes.c_int, [_vp, _fp, _i64]),
+    "lf_net_get_grads": (ctypes.c_int, [_vp, _fp, _i64]),
+    "lf_net_forward": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
+    "lf_net_get_output": (ctypes.c_int, [_vp, _fp, ctypes.c_size_t]),
+    "lf_net_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, _vp]),
+    "lf_net_adam": (ctypes.c_int, [_vp, ctypes.c_float]),
+    "lf_net_train_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_float, _vp]),
+    "lf_net_flops": (ctypes.c_int, [_vp, _dp, _dp]),
+    "lf_net_profile_train": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_float,
+                                            ctypes.c_int, _dp]),
+    "lf_resample": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64, _vp,
+                                   ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                   ctypes.c_double]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -194,7 +221,7 @@ class Context:
         _check(_lib.lf_ctx_set_band(self._h, int(rows)), "lf_ctx_set_band")
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.lf_ctx_destroy(self._h)
             self._h = None
 
@@ -225,7 +252,7 @@ class Case:
                                            nb.value), "lf_case_bind_workspace")
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.lf_case_destroy(self._h)
             self._h = None
 
@@ -372,7 +399,7 @@ class Batch:
                                             nb.value), "lf_batch_bind_workspace")
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.lf_batch_destroy(self._h)
             self._h = None
 
@@ -402,6 +429,38 @@ class Batch:
             return P
         _check(_lib.lf_batch_init(self._h, arr(T0), arr(u0), arr(v0)), "lf_batch_init")
         return self
+
+    def init_device(self, T0=None, u0=None, v0=None):
+        """Initial fields from lists of float64 CUDA tensors [ny][nx] (or
+        None entries); read asynchronously on the context stream."""
+        def arr(lst):
+            if lst is None:
+                return None
+            P = (_vp * self.n)()
+            for k in range(self.n):
+                a = lst[k]
+                if a is None:
+                    P[k] = None
+                    continue
+                assert a.is_cuda and a.dtype == torch.float64 and a.is_contiguous()
+                assert tuple(a.shape) == self.shapes[k], (k, tuple(a.shape), self.shapes[k])
+                P[k] = a.data_ptr()
+            return P
+        _check(_lib.lf_batch_init_device(self._h, arr(T0), arr(u0), arr(v0)),
+               "lf_batch_init_device")
+        return self
+
+    def fetch_device(self, idx: int, field, out: torch.Tensor):
+        """Copy a field into a contiguous float32 or float64 CUDA tensor
+        [ny][nx] (asynchronous on the context stream)."""
+        assert out.is_cuda and out.is_contiguous() and tuple(out.shape) == self.shapes[idx]
+        as64 = 1 if out.dtype == torch.float64 else 0
+        assert as64 or out.dtype == torch.float32
+        _check(_lib.lf_batch_fetch(self._h, int(idx), _FIELDS.get(field, field),
+                                   ctypes.c_void_p(out.data_ptr()),
+                                   out.numel() * out.element_size(), 1, as64),
+               "lf_batch_fetch")
+        return out
 
     def step(self, n: int):
         _check(_lib.lf_batch_step(self._h, int(n)), "lf_batch_step")
@@ -452,4 +511,143 @@ class Batch:
         a = ctypes.c_double()
         _check(_lib.lf_batch_profile_steps(self._h, int(n), ctypes.byref(a)),
                "lf_batch_profile_steps")
+        return a.value
+
+
+def resample(ctx: Context, src: torch.Tensor, dst: torch.Tensor, scale=1.0, offset=0.0):
+    """Bilinear resampling of a cell-centred CUDA tensor src [sny][snx] (rows
+    may be strided) into the contiguous CUDA tensor dst [dny][dnx]:
+    dst = value * scale + offset (see lf_resample)."""
+    assert src.is_cuda and dst.is_cuda and dst.is_contiguous() and src.stride(1) == 1
+    assert src.dtype in (torch.float32, torch.float64) and dst.dtype in (torch.float32,
+                                                                          torch.float64)
+    sny, snx = src.shape
+    dny, dnx = dst.shape
+    _check(_lib.lf_resample(ctx._h, ctypes.c_void_p(src.data_ptr()),
+                            int(src.dtype == torch.float64), snx, sny, src.stride(0),
+                            ctypes.c_void_p(dst.data_ptr()), int(dst.dtype == torch.float64),
+                            dnx, dny, float(scale), float(offset)), "lf_resample")
+    return dst
+
+
+class Net:
+    """The learned initial guess (see lf_net_* in lbmfvm.h).  Device inputs
+    are torch tensors: feat float32 [N][3] (log10 Ra, Pr, A), target float32
+    [N][3][res][res], idx int32 [batch]."""
+
+    def __init__(self, ctx: Context, res=128, widths=(32, 32, 64, 64, 128), cout=8,
+                 max_batch=32):
+        self.ctx = ctx
+        self.res, self.widths, self.cout, self.max_batch = res, tuple(widths), cout, max_batch
+        d = lf_net_desc(res, 8, cout, (ctypes.c_int * 5)(*widths), max_batch)
+        h = _vp()
+        _check(_lib.lf_net_create(ctx._h, ctypes.byref(d), ctypes.byref(h)), "lf_net_create")
+        self._h = h
+        n = _i64()
+        _check(_lib.lf_net_param_count(h, ctypes.byref(n)), "lf_net_param_count")
+        self.nparam = n.value
+        nb = ctypes.c_size_t()
+        _check(_lib.lf_net_workspace_bytes(h, ctypes.byref(nb)), "lf_net_workspace_bytes")
+        self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=f"cuda:{ctx.device}")
+        _check(_lib.lf_net_bind_workspace(h, ctypes.c_void_p(self.workspace.data_ptr()),
+                                          nb.value), "lf_net_bind_workspace")
+        self.loss_dev = torch.zeros(1, dtype=torch.float32, device=f"cuda:{ctx.device}")
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.lf_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def layer_shapes(self):
+        """(Cout, Cin) of the ten convolutions, in the flat parameter order."""
+        w0, w1, w2, w3, w4 = self.widths
+        co = [w0, w1, w2, w3, w4, w3, w2, w1, w0, self.cout]
+        ci = [8, w0, w1, w2, w3, w4, w3, w2, w1, w0]
+        return list(zip(co, ci))
+
+    def he_uniform(self, u: np.ndarray) -> np.ndarray:
+        """Weights uniform in +-sqrt(6 / fan_in) from uniforms u in [0, 1)
+        (one per parameter), biases zero; fan_in counts the 5 real input
+        channels of the first layer."""
+        u = np.asarray(u, np.float64)
+        assert u.size == self.nparam
+        out = np.zeros(self.nparam, np.float32)
+        k = 0
+        for li, (o, i) in enumerate(self.layer_shapes()):
+            nw = o * 9 * i
+            fan = 9 * (5 if li == 0 else i)
+            b = math.sqrt(6.0 / fan) * (0.5 if li == len(self.layer_shapes()) - 1 else 1.0)
+            out[k:k + nw] = ((2.0 * u[k:k + nw] - 1.0) * b).astype(np.float32)
+            k += nw + o
+        return out
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(w, np.float32)
+        _check(_lib.lf_net_set_weights(self._h, w.ctypes.data_as(_fp), w.size),
+               "lf_net_set_weights")
+        return self
+
+    def weights(self) -> np.ndarray:
+        out = np.empty(self.nparam, np.float32)
+        _check(_lib.lf_net_get_weights(self._h, out.ctypes.data_as(_fp), out.size),
+               "lf_net_get_weights")
+        return out
+
+    def grads(self) -> np.ndarray:
+        out = np.empty(self.nparam, np.float32)
+        _check(_lib.lf_net_get_grads(self._h, out.ctypes.data_as(_fp), out.size),
+               "lf_net_get_grads")
+        return out
+
+    @staticmethod
+    def _p(t):
+        return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+    def forward(self, feat, idx=None, batch=None, pred=None):
+        batch = int(batch if batch is not None else (idx.numel() if idx is not None
+                                                      else feat.shape[0]))
+        _check(_lib.lf_net_forward(self._h, self._p(feat), self._p(idx), batch, self._p(pred)),
+               "lf_net_forward")
+        return pred
+
+    def output(self, batch) -> np.ndarray:
+        out = np.empty((batch, self.res, self.res, self.cout), np.float32)
+        _check(_lib.lf_net_get_output(self._h, out.ctypes.data_as(_fp), out.size),
+               "lf_net_get_output")
+        return out
+
+    def backward(self, feat, target, idx=None, batch=None):
+        batch = int(batch if batch is not None else (idx.numel() if idx is not None
+                                                      else feat.shape[0]))
+        _check(_lib.lf_net_backward(self._h, self._p(feat), self._p(target), self._p(idx), batch,
+                                    self._p(self.loss_dev)), "lf_net_backward")
+        return self
+
+    def adam(self, lr):
+        _check(_lib.lf_net_adam(self._h, float(lr)), "lf_net_adam")
+        return self
+
+    def train_step(self, feat, target, idx, lr):
+        _check(_lib.lf_net_train_step(self._h, self._p(feat), self._p(target), self._p(idx),
+                                      int(idx.numel()), float(lr), self._p(self.loss_dev)),
+               "lf_net_train_step")
+        return self
+
+    def loss(self) -> float:
+        """Loss of the last backward / training step (synchronises)."""
+        return float(self.loss_dev.item())
+
+    def flops(self):
+        f, t = ctypes.c_double(), ctypes.c_double()
+        _check(_lib.lf_net_flops(self._h, ctypes.byref(f), ctypes.byref(t)), "lf_net_flops")
+        return f.value, t.value
+
+    def profile_train(self, feat, target, idx, lr, nsteps) -> float:
+        a = ctypes.c_double()
+        _check(_lib.lf_net_profile_train(self._h, self._p(feat), self._p(target), self._p(idx),
+                                         int(idx.numel()), float(lr), int(nsteps),
+                                         ctypes.byref(a)), "lf_net_profile_train")
         return a.value

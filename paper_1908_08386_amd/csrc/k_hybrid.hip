@@ -540,13 +540,21 @@ template <typename real, int CONV>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LF_STEP_WAVES(real))))
 void k_batch_step(const TileDesc* __restrict__ tiles, const int* __restrict__ ntiles,
                   const CavDesc<real>* __restrict__ cavs, int parity, int write_mom) {
-  const int nb = gridDim.x, b = blockIdx.x;
+  // The grid is sized for the largest tile table (band 1, all cavities
+  // live); only the first ceil(live / waves-per-block) blocks have work.
+  // Those are spread round-robin over the 8 XCDs, so the XCD-contiguous
+  // renumbering is taken over them alone: taken over the whole grid it
+  // would hand every live tile to the first XCDs.
+  const int wpb = blockDim.x >> 6;
+  const int live = *ntiles;
+  const int nb = (live + wpb - 1) / wpb, b = blockIdx.x;
+  if (b >= nb) return;
   const int per = nb / 8, rem = nb % 8, x = b % 8;
   const int lb = x * per + (x < rem ? x : rem) + b / 8;
   // the wave index is uniform; telling the compiler so makes the tile and
   // cavity descriptors scalar loads held in SGPRs
-  const int wave = __builtin_amdgcn_readfirstlane(lb * (blockDim.x >> 6) + (threadIdx.x >> 6));
-  if (wave >= *ntiles) return;  // uniform per wave
+  const int wave = __builtin_amdgcn_readfirstlane(lb * wpb + (threadIdx.x >> 6));
+  if (wave >= live) return;  // uniform per wave
   const TileDesc t = tiles[wave];
   const CavDesc<real>& cd = cavs[t.cav];
   StepArgs<real> a;

@@ -391,8 +391,8 @@ lf_status lf_batch_set_band(lf_batch* b, int idx, int rows) {
   return b->inited ? upload_tables(b) : LF_OK;
 }
 
-lf_status lf_batch_init(lf_batch* b, const double* const* T0, const double* const* u0,
-                        const double* const* v0) {
+static lf_status init_impl(lf_batch* b, const double* const* T0, const double* const* u0,
+                           const double* const* v0, bool on_device) {
   if (!b) return lf_fail(LF_EINVAL, "NULL batch");
   if (!b->ws) return lf_fail(LF_EWORKSPACE, "no workspace bound");
   hipStream_t s = b->ctx->stream;
@@ -401,9 +401,15 @@ lf_status lf_batch_init(lf_batch* b, const double* const* T0, const double* cons
     Cav& c = b->cav[k];
     const size_t n = (size_t)c.nx * c.ny;
     const double* dT = nullptr; const double* du = nullptr; const double* dv = nullptr;
-    if (T0 && T0[k]) { LF_HIP_TRY(hipMemcpyAsync(st, T0[k], n * 8, hipMemcpyHostToDevice, s)); dT = st; }
-    if (u0 && u0[k]) { LF_HIP_TRY(hipMemcpyAsync(st + n, u0[k], n * 8, hipMemcpyHostToDevice, s)); du = st + n; }
-    if (v0 && v0[k]) { LF_HIP_TRY(hipMemcpyAsync(st + 2 * n, v0[k], n * 8, hipMemcpyHostToDevice, s)); dv = st + 2 * n; }
+    if (on_device) {
+      dT = T0 ? T0[k] : nullptr;
+      du = u0 ? u0[k] : nullptr;
+      dv = v0 ? v0[k] : nullptr;
+    } else {
+      if (T0 && T0[k]) { LF_HIP_TRY(hipMemcpyAsync(st, T0[k], n * 8, hipMemcpyHostToDevice, s)); dT = st; }
+      if (u0 && u0[k]) { LF_HIP_TRY(hipMemcpyAsync(st + n, u0[k], n * 8, hipMemcpyHostToDevice, s)); du = st + n; }
+      if (v0 && v0[k]) { LF_HIP_TRY(hipMemcpyAsync(st + 2 * n, v0[k], n * 8, hipMemcpyHostToDevice, s)); dv = st + 2 * n; }
+    }
     lf::Grid g;
     g.nx = c.nx;
     g.ny = c.ny;
@@ -420,7 +426,7 @@ lf_status lf_batch_init(lf_batch* b, const double* const* T0, const double* cons
                                          (double*)(b->ws + c.off_mom),
                                          (double*)(b->ws + c.off_snap), nullptr, s));
     // staging is reused for the next cavity: wait for this one
-    LF_HIP_TRY(hipStreamSynchronize(s));
+    if (!on_device) LF_HIP_TRY(hipStreamSynchronize(s));
     c.cur = 0;
     c.active = true;
     c.steps = 0;
@@ -429,6 +435,16 @@ lf_status lf_batch_init(lf_batch* b, const double* const* T0, const double* cons
   }
   b->inited = true;
   return upload_tables(b);
+}
+
+lf_status lf_batch_init(lf_batch* b, const double* const* T0, const double* const* u0,
+                        const double* const* v0) {
+  return init_impl(b, T0, u0, v0, false);
+}
+
+lf_status lf_batch_init_device(lf_batch* b, const double* const* T0, const double* const* u0,
+                               const double* const* v0) {
+  return init_impl(b, T0, u0, v0, true);
 }
 
 lf_status lf_batch_step(lf_batch* b, int64_t nsteps) {

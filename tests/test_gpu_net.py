@@ -1,0 +1,172 @@
+"""The learned initial guess on the GPU against the FP64 numpy reference:
+forward and backward passes on the same bfloat16-rounded weights and inputs,
+Adam steps, a short training run, bilinear resampling and device-side
+initial fields of a batch."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import net as onet
+from synth_inputs import perturbation, uniform01
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lf():
+    import paper_1908_08386_amd as lf
+    return lf
+
+
+@pytest.fixture(scope="module")
+def ctx(lf):
+    return lf.Context(0)
+
+
+def rel_linf(a, b):
+    return float(np.abs(np.asarray(a, np.float64) - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def make_weights(n, seed):
+    """He-uniform weights and small non-zero biases from seeded uniforms."""
+    u = uniform01(seed, n.nparam)
+    w = n.he_uniform(u)
+    k = 0
+    for o, i in n.layer_shapes():
+        k += o * 9 * i
+        w[k:k + o] = (0.2 * (u[k:k + o] - 0.5)).astype(np.float32)
+        k += o
+    return w
+
+
+def cpu_flat(n, w):
+    """The GPU's operands: bf16 weights, FP32 biases."""
+    f = np.asarray(w, np.float64).copy()
+    k = 0
+    for o, i in n.layer_shapes():
+        f[k:k + o * 9 * i] = onet.bf16_round(w[k:k + o * 9 * i])
+        k += o * 9 * i + o
+    return f
+
+
+FEAT = np.array([[5.3, 0.71, 2.0], [3.7, 7.0, 1.0], [4.4, 0.71, 4.0]], np.float32)
+
+
+def targets(R, nb, seed):
+    return (0.5 * (uniform01(seed, nb * 3 * R * R) - 0.5)).reshape(nb, 3, R, R).astype(np.float32)
+
+
+@pytest.mark.parametrize("res,widths", [(128, (32, 32, 64, 64, 128)), (32, (8, 16, 24, 40, 64))])
+def test_forward_backward_vs_fp64(lf, ctx, res, widths):
+    n = lf.Net(ctx, res, widths, 8, max_batch=4)
+    w = make_weights(n, 11)
+    n.set_weights(w)
+    B = 3
+    feat = torch.tensor(FEAT, device="cuda")
+    tgt_h = targets(res, B, 12)
+    tgt = torch.tensor(tgt_h, device="cuda")
+    n.backward(feat, tgt, batch=B)
+    y_g = n.output(B)
+    g_g = n.grads()
+    loss_g = n.loss()
+
+    flat = cpu_flat(n, w)
+    x = onet.bf16_round(onet.net_inputs(FEAT.astype(np.float64), res))
+    y_c, cache = onet.forward(flat, x, widths, 8)
+    loss_c, dy = onet.mse(y_c, tgt_h.astype(np.float64).transpose(0, 2, 3, 1))
+    g_c = onet.backward(flat, cache, dy, widths, 8)
+
+    assert rel_linf(y_g, y_c) <= 1e-2
+    assert abs(loss_g - loss_c) <= 1e-2 * loss_c
+    k = 0
+    for li, (o, i) in enumerate(n.layer_shapes()):
+        nw = o * 9 * i
+        ew = rel_linf(g_g[k:k + nw], g_c[k:k + nw])
+        eb = rel_linf(g_g[k + nw:k + nw + o], g_c[k + nw:k + nw + o])
+        assert ew <= 2e-2 and eb <= 2e-2, (li, ew, eb)
+        k += nw + o
+
+
+def test_adam_steps_vs_fp64(lf, ctx):
+    n = lf.Net(ctx, 32, (8, 16, 24, 40, 64), 8, max_batch=4)
+    w0 = make_weights(n, 21)
+    n.set_weights(w0)
+    feat = torch.tensor(FEAT, device="cuda")
+    tgt = torch.tensor(targets(32, 3, 22), device="cuda")
+    w, m, v = w0.astype(np.float64), np.zeros(n.nparam), np.zeros(n.nparam)
+    for t in (1, 2):
+        n.backward(feat, tgt, batch=3)
+        g = n.grads().astype(np.float64)
+        n.adam(2e-3)
+        w, m, v = onet.adam_step(w, m, v, g, t, lr=2e-3)
+        assert np.abs(n.weights() - w).max() <= 1e-5, t
+
+
+def test_training_reduces_loss(lf, ctx):
+    R = 32
+    n = lf.Net(ctx, R, (8, 16, 24, 40, 64), 8, max_batch=8)
+    n.set_weights(make_weights(n, 31))
+    feat_h = np.array([[3 + 0.4 * k, (0.71, 7.0)[k % 2], 1 + k % 4] for k in range(8)], np.float32)
+    c = (np.arange(R) + 0.5) / R
+    X, Y = np.meshgrid(c, c)
+    tgt_h = np.stack([np.stack([np.sin(np.pi * X) * np.cos(np.pi * Y) * f[0] / 6,
+                                -np.cos(np.pi * X) * np.sin(np.pi * Y) * f[2] / 4,
+                                0.5 * (1 - X) + 0.1 * f[1] / 7 * Y]) for f in feat_h])
+    feat = torch.tensor(feat_h, device="cuda")
+    tgt = torch.tensor(tgt_h.astype(np.float32), device="cuda")
+    idx = torch.arange(8, dtype=torch.int32, device="cuda")
+    n.backward(feat, tgt, idx)
+    first = n.loss()
+    for _ in range(300):
+        n.train_step(feat, tgt, idx, 3e-3)
+    n.backward(feat, tgt, idx)
+    last = n.loss()
+    assert np.isfinite(last) and last < 0.1 * first, (first, last)
+    # the prediction path returns the three channel planes of the output
+    pred = torch.empty(8, 3, R, R, device="cuda")
+    n.forward(feat, idx, pred=pred)
+    raw = n.output(8)
+    assert np.array_equal(pred.cpu().numpy(), raw[..., :3].transpose(0, 3, 1, 2))
+
+
+def test_net_errors(lf, ctx):
+    with pytest.raises(lf.LFError) as e:
+        lf.Net(ctx, 40, (8, 8, 8, 8, 8))
+    assert e.value.status == lf.LF_EINVAL
+    with pytest.raises(lf.LFError):
+        lf.Net(ctx, 32, (8, 12, 8, 8, 8))
+    n = lf.Net(ctx, 32, (8, 8, 8, 8, 8), max_batch=2)
+    feat = torch.tensor(FEAT, device="cuda")
+    with pytest.raises(lf.LFError):
+        n.forward(feat, batch=3)
+    with pytest.raises(lf.LFError):
+        n.set_weights(np.zeros(n.nparam - 1, np.float32))
+
+
+@pytest.mark.parametrize("dst_dtype", [torch.float64, torch.float32])
+def test_resample_vs_fp64(lf, ctx, dst_dtype):
+    r = np.random.default_rng(5)
+    wide = r.standard_normal((37, 61))
+    src = torch.tensor(wide, device="cuda")[:, 3:56]   # row stride 61, 53 columns
+    for dny, dnx in ((128, 128), (20, 200), (37, 53)):
+        dst = torch.empty(dny, dnx, dtype=dst_dtype, device="cuda")
+        lf.resample(ctx, src, dst, scale=2.5, offset=-0.25)
+        ref = onet.bilinear(wide[:, 3:56], dny, dnx) * 2.5 - 0.25
+        tol = 1e-13 if dst_dtype == torch.float64 else 1e-6
+        assert np.abs(dst.cpu().numpy() - ref).max() <= tol * np.abs(ref).max()
+
+
+def test_batch_init_device_equals_host(lf, ctx):
+    cases = [dict(nx=96, ny=48, Ra=1e5, Pr=0.71), dict(nx=64, ny=64, Ra=1e4, Pr=7.0)]
+    T0 = [perturbation(c["nx"], c["ny"], 40 + k, amp=0.1) for k, c in enumerate(cases)]
+    u0 = [0.01 * perturbation(c["nx"], c["ny"], 50 + k, amp=1.0) for k, c in enumerate(cases)]
+    h = lf.Batch(ctx, cases, "f32").init(T0, u0, None)
+    d = lf.Batch(ctx, cases, "f32")
+    Td = [torch.tensor(a, device="cuda") for a in T0]
+    ud = [torch.tensor(a, device="cuda") for a in u0]
+    d.init_device(Td, ud, None)
+    h.step(20)
+    d.step(20)
+    for k in range(2):
+        for f in ("u", "v", "T"):
+            assert np.array_equal(h.fetch(k, f), d.fetch(k, f)), (k, f)
