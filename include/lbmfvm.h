@@ -216,8 +216,12 @@ lf_status lf_batch_step(lf_batch* b, int64_t nsteps);
  * untouched), then re-snapshot; synchronises.                             */
 lf_status lf_batch_residual(lf_batch* b, double* r3n);
 /* Per-cavity stop rule of lf_case_run_to_steady with an even check_every;
- * converged cavities stop stepping.  steps_each / rule_each / r_each (3 per
- * cavity) may be NULL.  LF_ENOTCONV if a cavity hit max_steps.            */
+ * converged cavities stop stepping.  max_steps bounds each cavity's steps
+ * since init; a cavity stopped by an earlier call's max_steps resumes (so a
+ * long run can be split into calls with growing limits), a converged or
+ * diverged one does not.  steps_each / rule_each (0: stopped at max_steps,
+ * -1: diverged) / r_each (3 per cavity) may be NULL.  LF_ENOTCONV if a
+ * cavity stopped at max_steps.                                             */
 lf_status lf_batch_run_to_steady(lf_batch* b, double tol, int check_every,
                                  int64_t max_steps, int64_t* steps_each,
                                  int* rule_each, double* r_each);

@@ -200,6 +200,16 @@ class Context:
         _check(_lib.lf_ctx_create(self.device, s, ctypes.byref(h)), "lf_ctx_create")
         self._h = h
 
+    def enter(self):
+        """Order the library stream after the work torch has queued on its
+        current stream (inputs written by torch ops)."""
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def leave(self):
+        """Order torch's current stream after the work queued on the library
+        stream (outputs read by torch ops)."""
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
     def autotune(self, cache_path: str, budget_ms: int = 3000, scratch_bytes: int = 1 << 30):
         """Load or measure the batch band table (see lf_autotune)."""
         scratch = torch.empty(int(scratch_bytes), dtype=torch.uint8, device=f"cuda:{self.device}")
@@ -347,9 +357,11 @@ class Case:
     def fetch_device(self, field, out: torch.Tensor):
         """Copy a field into a device tensor (float64, or the case precision)."""
         as64 = 1 if out.dtype == torch.float64 else 0
+        self.ctx.enter()
         _check(_lib.lf_case_fetch(self._h, _FIELDS.get(field, field),
                                   ctypes.c_void_p(out.data_ptr()),
                                   out.numel() * out.element_size(), 1, as64), "lf_case_fetch")
+        self.ctx.leave()
         return out
 
     def mass(self):
@@ -446,8 +458,10 @@ class Batch:
                 assert tuple(a.shape) == self.shapes[k], (k, tuple(a.shape), self.shapes[k])
                 P[k] = a.data_ptr()
             return P
+        self.ctx.enter()
         _check(_lib.lf_batch_init_device(self._h, arr(T0), arr(u0), arr(v0)),
                "lf_batch_init_device")
+        self.ctx.leave()
         return self
 
     def fetch_device(self, idx: int, field, out: torch.Tensor):
@@ -456,10 +470,12 @@ class Batch:
         assert out.is_cuda and out.is_contiguous() and tuple(out.shape) == self.shapes[idx]
         as64 = 1 if out.dtype == torch.float64 else 0
         assert as64 or out.dtype == torch.float32
+        self.ctx.enter()
         _check(_lib.lf_batch_fetch(self._h, int(idx), _FIELDS.get(field, field),
                                    ctypes.c_void_p(out.data_ptr()),
                                    out.numel() * out.element_size(), 1, as64),
                "lf_batch_fetch")
+        self.ctx.leave()
         return out
 
     def step(self, n: int):
@@ -523,10 +539,12 @@ def resample(ctx: Context, src: torch.Tensor, dst: torch.Tensor, scale=1.0, offs
                                                                           torch.float64)
     sny, snx = src.shape
     dny, dnx = dst.shape
+    ctx.enter()
     _check(_lib.lf_resample(ctx._h, ctypes.c_void_p(src.data_ptr()),
                             int(src.dtype == torch.float64), snx, sny, src.stride(0),
                             ctypes.c_void_p(dst.data_ptr()), int(dst.dtype == torch.float64),
                             dnx, dny, float(scale), float(offset)), "lf_resample")
+    ctx.leave()
     return dst
 
 
@@ -609,8 +627,10 @@ class Net:
     def forward(self, feat, idx=None, batch=None, pred=None):
         batch = int(batch if batch is not None else (idx.numel() if idx is not None
                                                       else feat.shape[0]))
+        self.ctx.enter()
         _check(_lib.lf_net_forward(self._h, self._p(feat), self._p(idx), batch, self._p(pred)),
                "lf_net_forward")
+        self.ctx.leave()
         return pred
 
     def output(self, batch) -> np.ndarray:
@@ -622,8 +642,10 @@ class Net:
     def backward(self, feat, target, idx=None, batch=None):
         batch = int(batch if batch is not None else (idx.numel() if idx is not None
                                                       else feat.shape[0]))
+        self.ctx.enter()
         _check(_lib.lf_net_backward(self._h, self._p(feat), self._p(target), self._p(idx), batch,
                                     self._p(self.loss_dev)), "lf_net_backward")
+        self.ctx.leave()
         return self
 
     def adam(self, lr):
@@ -631,9 +653,11 @@ class Net:
         return self
 
     def train_step(self, feat, target, idx, lr):
+        self.ctx.enter()
         _check(_lib.lf_net_train_step(self._h, self._p(feat), self._p(target), self._p(idx),
                                       int(idx.numel()), float(lr), self._p(self.loss_dev)),
                "lf_net_train_step")
+        self.ctx.leave()
         return self
 
     def loss(self) -> float:
@@ -647,6 +671,7 @@ class Net:
 
     def profile_train(self, feat, target, idx, lr, nsteps) -> float:
         a = ctypes.c_double()
+        self.ctx.enter()
         _check(_lib.lf_net_profile_train(self._h, self._p(feat), self._p(target), self._p(idx),
                                          int(idx.numel()), float(lr), int(nsteps),
                                          ctypes.byref(a)), "lf_net_profile_train")

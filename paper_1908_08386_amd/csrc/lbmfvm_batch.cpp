@@ -484,6 +484,18 @@ lf_status lf_batch_run_to_steady(lf_batch* b, double tol, int check_every, int64
   if (!(tol > 0.0) || check_every < 2 || (check_every & 1) || max_steps < 0)
     return lf_fail(LF_EINVAL, "tol > 0 and an even check_every >= 2 are required");
   hipStream_t s = b->ctx->stream;
+  // cavities stopped by an earlier call's step limit (rule 0) resume while
+  // under this call's limit; converged or diverged ones stay stopped
+  bool resumed = false;
+  for (auto& c : b->cav)
+    if (!c.active && c.rule == 0 && c.steps < max_steps) {
+      c.active = true;
+      resumed = true;
+    }
+  if (resumed) {
+    lf_status su = upload_tables(b);
+    if (su != LF_OK) return su;
+  }
   // snapshot the live cavities, then replay "K steps + residual"
   LF_HIP_TRY(enqueue_residual_any(b));
   lf_status st = ensure_graph(b, check_every);

@@ -117,6 +117,22 @@ def test_batch_run_to_steady_fp32_sweep_sample(lf, ctx):
         assert abs(nb - no) <= 1e-4 * abs(no), (k, c, nb, no, steps[k], rules[k], r[k])
 
 
+def test_run_to_steady_resumes_after_step_limit(lf, ctx):
+    """A run split into calls with growing max_steps equals one call."""
+    cases = [dict(nx=32, ny=32, Ra=1e4, Pr=0.71, seed=0), dict(nx=48, ny=24, Ra=1e3, Pr=7.0, seed=0)]
+    one = lf.Batch(ctx, cases, "f64").init()
+    s1, r1, _ = one.run_to_steady(tol=1e-8, check_every=1000, max_steps=400000)
+    two = lf.Batch(ctx, cases, "f64").init()
+    sa, ra, _ = two.run_to_steady(tol=1e-8, check_every=1000, max_steps=6000,
+                                  raise_on_notconv=False)
+    assert np.all(ra == 0) and np.all(sa == 6000)
+    s2, r2, _ = two.run_to_steady(tol=1e-8, check_every=1000, max_steps=400000)
+    assert np.array_equal(s1, s2) and np.array_equal(r1, r2)
+    for k in range(2):
+        for f in ("u", "v", "T"):
+            assert np.array_equal(one.fetch(k, f), two.fetch(k, f)), (k, f)
+
+
 def test_autotuner_writes_and_loads_cache(lf, ctx, tmp_path):
     path = str(tmp_path / "tune.json")
     table = ctx.autotune(path, budget_ms=1400, scratch_bytes=1 << 30)
