@@ -315,10 +315,14 @@ lf_status lf_net_profile_train(lf_net* net, const float* feat, const float* targ
  * rectangle: destination centre (i + 1/2)/dnx maps to the source index
  * coordinate (i + 1/2) snx/dnx - 1/2, clamped to [0, snx - 1] (same in y);
  * dst[j][i] = value * scale + offset.  src rows are src_row_stride elements
- * apart; dst is dense [dny][dnx].  Device pointers; asynchronous.          */
+ * apart; dst is dense [dny][dnx].  Device pointers; asynchronous.
+ * flags: LF_RESAMPLE_ANTISYM keeps the part that is odd under the 180-degree
+ * rotation, dst[j][i] = (d[j][i] - d[dny-1-j][dnx-1-i]) / 2 of the plain
+ * result d (the side-heated cavity's steady T, u and v are odd).          */
+enum { LF_RESAMPLE_ANTISYM = 1 };
 lf_status lf_resample(lf_ctx* ctx, const void* src, int src_is_f64, int snx, int sny,
                       int64_t src_row_stride, void* dst, int dst_is_f64, int dnx,
-                      int dny, double scale, double offset);
+                      int dny, double scale, double offset, int flags);
 
 #ifdef __cplusplus
 }

@@ -153,7 +153,7 @@ _SIGS = {
                                             ctypes.c_int, _dp]),
     "lf_resample": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64, _vp,
                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
-                                   ctypes.c_double]),
+                                   ctypes.c_double, ctypes.c_int]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -530,10 +530,15 @@ class Batch:
         return a.value
 
 
-def resample(ctx: Context, src: torch.Tensor, dst: torch.Tensor, scale=1.0, offset=0.0):
+RESAMPLE_ANTISYM = 1
+
+
+def resample(ctx: Context, src: torch.Tensor, dst: torch.Tensor, scale=1.0, offset=0.0,
+             antisym=False):
     """Bilinear resampling of a cell-centred CUDA tensor src [sny][snx] (rows
     may be strided) into the contiguous CUDA tensor dst [dny][dnx]:
-    dst = value * scale + offset (see lf_resample)."""
+    dst = value * scale + offset, optionally reduced to its part that is odd
+    under the 180-degree rotation (see lf_resample)."""
     assert src.is_cuda and dst.is_cuda and dst.is_contiguous() and src.stride(1) == 1
     assert src.dtype in (torch.float32, torch.float64) and dst.dtype in (torch.float32,
                                                                           torch.float64)
@@ -543,7 +548,8 @@ def resample(ctx: Context, src: torch.Tensor, dst: torch.Tensor, scale=1.0, offs
     _check(_lib.lf_resample(ctx._h, ctypes.c_void_p(src.data_ptr()),
                             int(src.dtype == torch.float64), snx, sny, src.stride(0),
                             ctypes.c_void_p(dst.data_ptr()), int(dst.dtype == torch.float64),
-                            dnx, dny, float(scale), float(offset)), "lf_resample")
+                            dnx, dny, float(scale), float(offset),
+                            RESAMPLE_ANTISYM if antisym else 0), "lf_resample")
     ctx.leave()
     return dst
 

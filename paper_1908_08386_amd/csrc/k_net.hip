@@ -341,13 +341,10 @@ __global__ void k_weights_bf16(const float* __restrict__ w, int Cout, int Cin,
   wt[((size_t)tap * Cin + ci) * Cout + co] = h;
 }
 
-template <typename Tin, typename Tout>
-__global__ void k_resample(const Tin* __restrict__ src, int snx, int sny, long long sstride,
-                           Tout* __restrict__ dst, int dnx, int dny, double scale,
-                           double offset) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (long long)dnx * dny) return;
-  const int x = (int)(i % dnx), y = (int)(i / dnx);
+template <typename Tin>
+__device__ __forceinline__ double bilinear_at(const Tin* __restrict__ src, int snx, int sny,
+                                              long long sstride, int x, int y, int dnx,
+                                              int dny) {
   double qx = ((double)x + 0.5) * snx / dnx - 0.5;
   double qy = ((double)y + 0.5) * sny / dny - 0.5;
   qx = fmin(fmax(qx, 0.0), (double)(snx - 1));
@@ -359,7 +356,26 @@ __global__ void k_resample(const Tin* __restrict__ src, int snx, int sny, long l
   const double s10 = (double)src[y1 * sstride + x0], s11 = (double)src[y1 * sstride + x1];
   const double top = s00 * (1.0 - fx) + s01 * fx;
   const double bot = s10 * (1.0 - fx) + s11 * fx;
-  dst[i] = (Tout)((top * (1.0 - fy) + bot * fy) * scale + offset);
+  return top * (1.0 - fy) + bot * fy;
+}
+
+// antisym: the result is made odd under the 180-degree rotation of the
+// rectangle, r(p) = (v(p) - v(rot p)) / 2 with v = value * scale + offset.
+template <typename Tin, typename Tout>
+__global__ void k_resample(const Tin* __restrict__ src, int snx, int sny, long long sstride,
+                           Tout* __restrict__ dst, int dnx, int dny, double scale,
+                           double offset, int antisym) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)dnx * dny) return;
+  const int x = (int)(i % dnx), y = (int)(i / dnx);
+  const double v = bilinear_at(src, snx, sny, sstride, x, y, dnx, dny) * scale + offset;
+  if (!antisym) {
+    dst[i] = (Tout)v;
+    return;
+  }
+  const double w =
+      bilinear_at(src, snx, sny, sstride, dnx - 1 - x, dny - 1 - y, dnx, dny) * scale + offset;
+  dst[i] = (Tout)(0.5 * (v - w));
 }
 
 inline unsigned nblocks(long long n, int b = 256) { return (unsigned)((n + b - 1) / b); }
@@ -521,20 +537,20 @@ hipError_t launch_weights_bf16(const float* w, int Cout, int Cin, uint16_t* wb, 
 
 hipError_t launch_resample(const void* src, int src_f64, int snx, int sny, long long sstride,
                            void* dst, int dst_f64, int dnx, int dny, double scale, double offset,
-                           hipStream_t s) {
+                           int antisym, hipStream_t s) {
   const dim3 grid(nblocks((long long)dnx * dny)), blk(256);
   if (src_f64 && dst_f64)
     hipLaunchKernelGGL((k_resample<double, double>), grid, blk, 0, s, (const double*)src, snx,
-                       sny, sstride, (double*)dst, dnx, dny, scale, offset);
+                       sny, sstride, (double*)dst, dnx, dny, scale, offset, antisym);
   else if (src_f64)
     hipLaunchKernelGGL((k_resample<double, float>), grid, blk, 0, s, (const double*)src, snx,
-                       sny, sstride, (float*)dst, dnx, dny, scale, offset);
+                       sny, sstride, (float*)dst, dnx, dny, scale, offset, antisym);
   else if (dst_f64)
     hipLaunchKernelGGL((k_resample<float, double>), grid, blk, 0, s, (const float*)src, snx,
-                       sny, sstride, (double*)dst, dnx, dny, scale, offset);
+                       sny, sstride, (double*)dst, dnx, dny, scale, offset, antisym);
   else
     hipLaunchKernelGGL((k_resample<float, float>), grid, blk, 0, s, (const float*)src, snx,
-                       sny, sstride, (float*)dst, dnx, dny, scale, offset);
+                       sny, sstride, (float*)dst, dnx, dny, scale, offset, antisym);
   return hipGetLastError();
 }
 

@@ -391,12 +391,13 @@ lf_status lf_net_profile_train(lf_net* net, const float* feat, const float* targ
 
 lf_status lf_resample(lf_ctx* ctx, const void* src, int src_is_f64, int snx, int sny,
                       int64_t src_row_stride, void* dst, int dst_is_f64, int dnx, int dny,
-                      double scale, double offset) {
+                      double scale, double offset, int flags) {
   if (!ctx || !src || !dst) return lf_fail(LF_EINVAL, "NULL argument");
   if (snx < 1 || sny < 1 || dnx < 1 || dny < 1 || src_row_stride < snx)
     return lf_fail(LF_EINVAL, "bad sizes");
+  if (flags & ~LF_RESAMPLE_ANTISYM) return lf_fail(LF_EINVAL, "unknown flags %d", flags);
   LF_HIP_TRY(lf::launch_resample(src, src_is_f64, snx, sny, src_row_stride, dst, dst_is_f64, dnx,
-                                 dny, scale, offset, ctx->stream));
+                                 dny, scale, offset, flags & LF_RESAMPLE_ANTISYM, ctx->stream));
   return LF_OK;
 }
 

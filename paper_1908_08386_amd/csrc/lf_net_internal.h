@@ -64,6 +64,6 @@ hipError_t launch_weights_bf16(const float* w, int Cout, int Cin, uint16_t* wb, 
 // Bilinear resampling of a cell-centred field (see lf_resample).
 hipError_t launch_resample(const void* src, int src_f64, int snx, int sny, long long sstride,
                            void* dst, int dst_f64, int dnx, int dny, double scale,
-                           double offset, hipStream_t s);
+                           double offset, int antisym, hipStream_t s);
 
 }  // namespace lf

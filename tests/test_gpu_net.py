@@ -156,6 +156,19 @@ def test_resample_vs_fp64(lf, ctx, dst_dtype):
         assert np.abs(dst.cpu().numpy() - ref).max() <= tol * np.abs(ref).max()
 
 
+def test_resample_antisym_vs_fp64(lf, ctx):
+    r = np.random.default_rng(8)
+    src_h = r.standard_normal((33, 47))
+    src = torch.tensor(src_h, device="cuda")
+    dst = torch.empty(40, 90, dtype=torch.float64, device="cuda")
+    lf.resample(ctx, src, dst, scale=0.5, offset=0.3, antisym=True)
+    d = onet.bilinear(src_h, 40, 90) * 0.5 + 0.3
+    ref = 0.5 * (d - d[::-1, ::-1])
+    got = dst.cpu().numpy()
+    assert np.abs(got - ref).max() <= 1e-13
+    assert np.abs(got + got[::-1, ::-1]).max() <= 1e-13
+
+
 def test_batch_init_device_equals_host(lf, ctx):
     cases = [dict(nx=96, ny=48, Ra=1e5, Pr=0.71), dict(nx=64, ny=64, Ra=1e4, Pr=7.0)]
     T0 = [perturbation(c["nx"], c["ny"], 40 + k, amp=0.1) for k, c in enumerate(cases)]
