@@ -65,6 +65,51 @@ def cpu_baseline(nx, ny, T0, seconds):
                       f"{steps} steps in {dt:.1f} s"}
 
 
+def time_to_steady(lf, ctx, n, T0, heldout):
+    """Cold start against the learned initial guess, same stop rule (residual
+    1e-8 per 1000 steps or the FP32 floor rule): the n x n cavity of the main
+    workload, then a batch of held-out cavities of the sweep distribution.
+    Warm times include the network's prediction and the resampling."""
+    import numpy as np
+    import torch
+
+    from paper_1908_08386_amd import warmstart as ws
+    from synth_inputs import SEED_HELDOUT, cavity_sweep, perturbation
+    W = np.load(os.path.join(ROOT, "paper_1908_08386_amd", "weights", "warmstart_r128.npz"))
+    net = lf.Net(ctx, int(W["res"]), tuple(int(x) for x in W["widths"]), int(W["cout"]),
+                 max_batch=32)
+    net.set_weights(W["weights"])
+    res = {}
+    one = [{"nx": n, "ny": n, "Ra": 1e6, "Pr": 0.71}]
+    r = ws.compare(ctx, net, one, [T0], max_steps=4_000_000, chunk=500_000)
+    res["cavity"] = {"workload": f"{n}x{n} Ra 1e6 Pr 0.71 FP32",
+                     "seconds_cold": round(r["seconds_cold"], 3),
+                     "seconds_warm": round(r["seconds_warm"], 3),
+                     "speedup": round(r["seconds_cold"] / r["seconds_warm"], 3),
+                     "steps_cold": int(r["steps_cold"][0]), "steps_warm": int(r["steps_warm"][0]),
+                     "rule_cold": int(r["rules_cold"][0]), "rule_warm": int(r["rules_warm"][0]),
+                     "nu_cold": float(r["nu_cold"][0]), "nu_warm": float(r["nu_warm"][0]),
+                     "dnu_rel": float(abs(r["nu_warm"][0] - r["nu_cold"][0]) / abs(r["nu_cold"][0]))}
+    if heldout:
+        held = cavity_sweep(heldout, SEED_HELDOUT, max_ny=128)
+        T0h = [perturbation(c["nx"], c["ny"], c["seed"]) for c in held]
+        r = ws.compare(ctx, net, held, T0h, max_steps=3_000_000, chunk=500_000)
+        dnu = np.abs(r["nu_warm"] - r["nu_cold"]) / np.abs(r["nu_cold"])
+        ratio = r["steps_warm"] / np.maximum(r["steps_cold"], 1)
+        res["heldout_batch"] = {
+            "workload": f"{heldout} held-out sweep cavities (seed {SEED_HELDOUT}, ny <= 128), "
+                        "one batch each way",
+            "seconds_cold": round(r["seconds_cold"], 3), "seconds_warm": round(r["seconds_warm"], 3),
+            "speedup": round(r["seconds_cold"] / r["seconds_warm"], 3),
+            "step_ratio_median": round(float(np.median(ratio)), 3),
+            "step_ratio_max": round(float(ratio.max()), 3),
+            "rules_ok": bool(np.all((r["rules_cold"] > 0) & (r["rules_warm"] > 0))),
+            "dnu_rel_max": float(dnu.max())}
+    del net
+    torch.cuda.synchronize()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +127,10 @@ def main():
     ap.add_argument("--hbm-point", type=int, default=4096,
                     help="also time the kernel on an n x n cavity whose working set is far "
                          "larger than the on-die caches (0 = skip)")
+    ap.add_argument("--time-to-steady", type=int, default=1,
+                    help="also time cold and learned (warm) starts to steady state (0 = skip)")
+    ap.add_argument("--heldout", type=int, default=16,
+                    help="held-out cavities (ny <= 128) in the batched warm/cold comparison")
     ap.add_argument("--batch-point", type=int, default=256,
                     help="also time one launch per step over this many heterogeneous cavities "
                          "of the sweep distribution (0 = skip)")
@@ -228,6 +277,9 @@ def main():
                               "achieved_GBs_at_80B": round(ach, 1),
                               "frac_of_8TBs": round(ach / HBM_PEAK_GBS, 4)}
         del bt
+
+    if args.time_to_steady:
+        out["time_to_steady"] = time_to_steady(lf, ctx, n, T0, args.heldout)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, n, T0, args.cpu_seconds)

@@ -1,6 +1,7 @@
 """Train the learned initial guess and compare warm and cold starts.
 
     python -m paper_1908_08386_amd.train_warmstart --out weights.npz [--report r.json]
+    python -m paper_1908_08386_amd.train_warmstart --eval-only weights.npz [--heldout-n N]
 
 1. Draw the training cavities (heterogeneous side-heated cavities: ny from
    64..512 capped at --max-ny-train, A in 1..4, log10 Ra in [3, 6], Pr 0.71
@@ -60,14 +61,27 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--max-steps", type=int, default=3_000_000)
-    ap.add_argument("--out", required=True)
+    ap.add_argument("--out", default="", help="where to save the trained weights (.npz)")
     ap.add_argument("--report", default="")
     ap.add_argument("--skip-eval", action="store_true")
+    ap.add_argument("--eval-only", default="",
+                    help="skip solving and training: evaluate these saved weights")
     a = ap.parse_args(argv)
     widths = tuple(int(x) for x in a.widths.split(","))
+    if not a.eval_only and not a.out:
+        ap.error("--out is required unless --eval-only is given")
     ctx = lf.Context(0)
     report = {"train_n": a.train_n, "max_ny_train": a.max_ny_train, "res": a.res,
               "widths": widths, "epochs": a.epochs, "batch": a.batch, "lr": a.lr}
+
+    if a.eval_only:
+        W = np.load(a.eval_only)
+        net = lf.Net(ctx, int(W["res"]), tuple(int(x) for x in W["widths"]), int(W["cout"]),
+                     max_batch=a.batch)
+        net.set_weights(W["weights"])
+        report = {"weights": a.eval_only}
+        evaluate(a, ctx, net, report)
+        return
 
     log(f"step: solve {a.train_n} training cavities")
     cases = cavity_sweep(a.train_n, SEED_TRAIN, max_ny=a.max_ny_train)
@@ -108,25 +122,38 @@ def main(argv=None):
     log(f"  weights -> {a.out}")
 
     if not a.skip_eval:
-        log(f"step: held-out comparison ({a.heldout_n} cavities)")
-        held = cavity_sweep(a.heldout_n, SEED_HELDOUT, max_ny=a.max_ny_eval or None)
-        T0h = [perturbation(c["nx"], c["ny"], c["seed"]) for c in held]
-        res = ws.compare(ctx, net, held, T0h, max_steps=a.max_steps, log=log)
-        dnu = np.abs(res["nu_warm"] - res["nu_cold"]) / np.abs(res["nu_cold"])
-        ratio = res["steps_warm"] / np.maximum(res["steps_cold"], 1)
-        report["heldout"] = {
-            "n": a.heldout_n, "max_ny": a.max_ny_eval or 512,
-            "seconds_cold": round(res["seconds_cold"], 2), "seconds_warm": round(res["seconds_warm"], 2),
-            "seconds_predict": round(res["seconds_predict"], 3),
-            "speedup_wall": round(res["seconds_cold"] / res["seconds_warm"], 3),
-            "step_ratio_median": round(float(np.median(ratio)), 3),
-            "step_ratio_min": round(float(ratio.min()), 3), "step_ratio_max": round(float(ratio.max()), 3),
-            "steps_cold_total": int(res["steps_cold"].sum()), "steps_warm_total": int(res["steps_warm"].sum()),
-            "dnu_rel_max": float(dnu.max()), "dnu_rel_median": float(np.median(dnu)),
-            "rules_cold": res["rules_cold"].tolist(), "rules_warm": res["rules_warm"].tolist(),
-            "steps_cold": res["steps_cold"].tolist(), "steps_warm": res["steps_warm"].tolist()}
-        log(json.dumps({k: v for k, v in report["heldout"].items()
-                        if not k.startswith(("rules", "steps_c", "steps_w"))}))
+        evaluate(a, ctx, net, report)
+        return
+    if a.report:
+        with open(a.report, "w") as f:
+            json.dump(report, f, indent=1, default=float)
+    log("done")
+
+
+def evaluate(a, ctx, net, report):
+    log(f"step: held-out comparison ({a.heldout_n} cavities)")
+    held = cavity_sweep(a.heldout_n, SEED_HELDOUT, max_ny=a.max_ny_eval or None)
+    T0h = [perturbation(c["nx"], c["ny"], c["seed"]) for c in held]
+    res = ws.compare(ctx, net, held, T0h, max_steps=a.max_steps, log=log)
+    dnu = np.abs(res["nu_warm"] - res["nu_cold"]) / np.abs(res["nu_cold"])
+    ratio = res["steps_warm"] / np.maximum(res["steps_cold"], 1)
+    report["heldout"] = {
+        "n": a.heldout_n, "max_ny": a.max_ny_eval or 512,
+        "seconds_cold": round(res["seconds_cold"], 2), "seconds_warm": round(res["seconds_warm"], 2),
+        "seconds_predict": round(res["seconds_predict"], 3),
+        "speedup_wall": round(res["seconds_cold"] / res["seconds_warm"], 3),
+        "step_ratio_median": round(float(np.median(ratio)), 3),
+        "step_ratio_min": round(float(ratio.min()), 3), "step_ratio_max": round(float(ratio.max()), 3),
+        "steps_cold_total": int(res["steps_cold"].sum()), "steps_warm_total": int(res["steps_warm"].sum()),
+        "dnu_rel_max": float(dnu.max()), "dnu_rel_median": float(np.median(dnu)),
+        "rules_cold": res["rules_cold"].tolist(), "rules_warm": res["rules_warm"].tolist(),
+        "steps_cold": res["steps_cold"].tolist(), "steps_warm": res["steps_warm"].tolist(),
+        "nu_cold": res["nu_cold"].tolist(), "nu_warm": res["nu_warm"].tolist()}
+    both = (res["rules_cold"] > 0) & (res["rules_warm"] > 0)
+    report["heldout"]["stopped_both"] = int(both.sum())
+    report["heldout"]["dnu_rel_max_stopped_both"] = float(dnu[both].max()) if both.any() else None
+    log(json.dumps({k: v for k, v in report["heldout"].items()
+                    if not k.startswith(("rules", "steps_c", "steps_w", "nu_"))}))
     if a.report:
         with open(a.report, "w") as f:
             json.dump(report, f, indent=1, default=float)
