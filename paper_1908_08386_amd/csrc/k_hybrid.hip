@@ -51,10 +51,6 @@ constexpr int kOut = 62;  // output columns per wave (lanes 1..62)
 #define LF_STEP_WAVES_F32 5
 #endif
 #define LF_STEP_WAVES(real) (sizeof(real) == 4 ? LF_STEP_WAVES_F32 : 2)
-// Rows of populations requested ahead of the row being computed (1 or 2).
-#ifndef LF_PREFETCH_ROWS
-#define LF_PREFETCH_ROWS 2
-#endif
 
 // D2Q9 (Eq 4, Eq 9): 0 rest, 1 E, 2 N, 3 W, 4 S, 5 NE, 6 NW, 7 SW, 8 SE.
 __host__ __device__ constexpr int ex(int q) {
@@ -141,56 +137,6 @@ __device__ __forceinline__ void moments(const real f[9], real& drho, real& ux, r
 // every non-periodic side by the wall's ghost value: 2 T_w - T_edge for a
 // fixed-temperature wall, T_edge for an adiabatic one.  Values further out
 // are clamped and never used.
-template <typename real>
-__device__ __forceinline__ real T_at(const StepArgs<real>& a, int c, int r) {
-  const int cc = a.xper ? wrap_any(c, a.nx) : clampi(c, 0, a.nx - 1);
-  const int rr = a.yper ? wrap_any(r, a.ny) : clampi(r, 0, a.ny - 1);
-  real t = a.Tin[rr * a.pitch + cc];
-  if (!a.xper) {
-    if (c < 0 && a.tfix[0]) t = real(2) * a.Tw[0] - t;
-    else if (c >= a.nx && a.tfix[1]) t = real(2) * a.Tw[1] - t;
-  }
-  if (!a.yper) {
-    if (r < 0 && a.tfix[2]) t = real(2) * a.Tw[2] - t;
-    else if (r >= a.ny && a.tfix[3]) t = real(2) * a.Tw[3] - t;
-  }
-  return t;
-}
-
-// Pull the 9 streamed populations of node (ic, r) (r is wrapped or clamped
-// into the grid) and form its moments.  A link whose upstream node lies
-// beyond a wall returns the node's own reversed population plus the moving
-// wall term 6 w_q (e_q . u_w); at a corner the south/north wall is taken.
-template <typename real>
-__device__ __forceinline__ void pull_row(const StepArgs<real>& a, int ic, int r,
-                                         real f[9], real& drho, real& ux,
-                                         real& uy) {
-  const int rr = a.yper ? wrap_any(r, a.ny) : clampi(r, 0, a.ny - 1);
-#pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    int sx = ic - ex(q), sy = rr - ey(q);
-    int side = -1;
-    if (a.xper) sx = wrap_one(sx, a.nx);
-    else if (sx < 0) side = 0;
-    else if (sx >= a.nx) side = 1;
-    if (a.yper) sy = wrap_one(sy, a.ny);
-    else if (sy < 0) side = 2;
-    else if (sy >= a.ny) side = 3;
-    real v;
-    if (side < 0) {
-      v = a.fin[q * a.plane + sy * a.pitch + sx];
-    } else {
-      // select, not an indexed load: keeps a locally built argument block
-      // in registers
-      const real uwall = side == 0 ? a.uw[0] : side == 1 ? a.uw[1] : side == 2 ? a.uw[2] : a.uw[3];
-      const real eu = side >= 2 ? real(ex(q)) * uwall : real(ey(q)) * uwall;
-      v = a.fin[opp(q) * a.plane + rr * a.pitch + ic] + real(6) * wq<real>(q) * eu;
-    }
-    f[q] = v;
-  }
-  moments(f, drho, ux, uy);
-}
-
 // Face value of the convected temperature between cells L and R; tll is
 // upstream of L, trr downstream of R.  QUICK: quadratic through the two
 // neighbours and the next upstream cell.
@@ -268,26 +214,103 @@ __device__ __forceinline__ void store_node(const StepArgs<real>& a, int o, const
 
 // General march: any wave, including those touching walls or periodic seams.
 // Each cell evaluates its four face fluxes (wall faces by the wall rule).
-template <typename real, int CONV>
+// Periodicity is a compile-time property of the instance, and every wall
+// rule is a select on per-lane flags computed once, so the wave's loads are
+// not split by branches: everything the first row needs is requested before
+// any arithmetic (one memory round trip for a short band) and later rows'
+// inputs one row ahead.
+//   Pull: a link whose upstream node lies beyond a wall takes the node's own
+//   reversed population plus the moving-wall term 6 w_q (e_q . u_w); at a
+//   corner the south/north wall is taken.  T beyond a wall is the ghost
+//   2 T_w - T_edge (fixed T) or T_edge (adiabatic).
+// Helpers of the general march.  They take scalars, not a struct: a select
+// between fields of a local struct would be turned into a load through a
+// selected address, which keeps the struct in scratch memory.
+template <bool YP>
+__device__ __forceinline__ int gen_row(int r, int ny) {
+  return YP ? wrap_one(r, ny) : clampi(r, 0, ny - 1);
+}
+
+// T of column c (wrapped or clamped) at row r, with the ghost rules: x-ghosts
+// by the lane's flags gW / gE, y-ghosts by the row
+template <typename real, bool YP>
+__device__ __forceinline__ real gen_T(const real* __restrict__ Tin, int P, int ny, int c, int r,
+                                      bool gW, bool gE, real TwW, real TwE, bool fixS,
+                                      bool fixN, real TwS, real TwN) {
+  real t = Tin[gen_row<YP>(r, ny) * P + c];
+  t = gW ? real(2) * TwW - t : t;
+  t = gE ? real(2) * TwE - t : t;
+  if (!YP) {
+    t = (r < 0 && fixS) ? real(2) * TwS - t : t;
+    t = (r >= ny && fixN) ? real(2) * TwN - t : t;
+  }
+  return t;
+}
+
+// the 9 streamed populations of node (ic, r) and its moments
+template <typename real, bool XP, bool YP>
+__device__ __forceinline__ void gen_pull(const real* __restrict__ fin, int nx, int ny, int P,
+                                         int plane, int ic, int r, real uwW, real uwE,
+                                         real uwS, real uwN, real f[9], real& drho, real& ux,
+                                         real& uy) {
+  const int rr = gen_row<YP>(r, ny);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    int sx = ic - ex(q), sy = rr - ey(q);
+    bool ox = false, oy = false;
+    if (XP) sx = wrap_one(sx, nx);
+    else ox = sx < 0 || sx >= nx;
+    if (YP) sy = wrap_one(sy, ny);
+    else oy = sy < 0 || sy >= ny;
+    const bool out = ox || oy;
+    const real raw = fin[out ? opp(q) * plane + rr * P + ic : q * plane + sy * P + sx];
+    const real uwall = oy ? (sy < 0 ? uwS : uwN) : (sx < 0 ? uwW : uwE);
+    const real eu = oy ? real(ex(q)) * uwall : real(ey(q)) * uwall;
+    f[q] = out ? raw + real(6) * wq<real>(q) * eu : raw;
+  }
+  moments(f, drho, ux, uy);
+}
+
+template <typename real, int CONV, bool XP, bool YP>
 __device__ void march_general(const StepArgs<real>& a, int lane, int i, int j0, int j1) {
-  const int ic = a.xper ? wrap_any(i, a.nx) : clampi(i, 0, a.nx - 1);
-  const bool act = lane >= 1 && lane <= kOut && i < a.nx;
+  const int nx = a.nx, ny = a.ny, P = a.pitch;
+  const bool act = lane >= 1 && lane <= kOut && i < nx;
   const int ix2 = lane < 32 ? i - 2 : i + 2;  // second T column (lanes 1, 62)
   const real al = a.alpha;
+  const real TwW = a.Tw[0], TwE = a.Tw[1], TwS = a.Tw[2], TwN = a.Tw[3];
+  const bool fixW = a.tfix[0], fixE = a.tfix[1], fixS = a.tfix[2], fixN = a.tfix[3];
+  const int plane = a.plane;
+  const int ic = XP ? wrap_any(i, nx) : clampi(i, 0, nx - 1);
+  const int ic2 = XP ? wrap_any(ix2, nx) : clampi(ix2, 0, nx - 1);
+  // x-ghost rules of the two T columns this lane reads
+  const bool g1W = !XP && i < 0 && fixW, g1E = !XP && i >= nx && fixE;
+  const bool g2W = !XP && ix2 < 0 && fixW, g2E = !XP && ix2 >= nx && fixE;
+  const real uwW = a.uw[0], uwE = a.uw[1], uwS = a.uw[2], uwN = a.uw[3];
+  const real* __restrict__ fin = a.fin;
+  const real* __restrict__ Tin = a.Tin;
+  // the low words of a compensated T are read from T itself (and ignored)
+  // when absent, which keeps the loads unconditional
+  const real* tlo = a.Tlo_in ? a.Tlo_in : a.Tin;
+#define LF_PULL(r, f, d, u, v) \
+  gen_pull<real, XP, YP>(fin, nx, ny, P, plane, ic, (r), uwW, uwE, uwS, uwN, f, d, u, v)
+#define LF_T1(r) gen_T<real, YP>(Tin, P, ny, ic, (r), g1W, g1E, TwW, TwE, fixS, fixN, TwS, TwN)
+#define LF_T2(r) gen_T<real, YP>(Tin, P, ny, ic2, (r), g2W, g2E, TwW, TwE, fixS, fixN, TwS, TwN)
 
   real fc[9], fn[9];
   real dr_c, ux_c, uy_c, dr_n, ux_n, uy_n, uy_p;
   {
     real ft[9], d, u;
-    pull_row(a, ic, j0 - 1, ft, d, u, uy_p);
+    LF_PULL(j0 - 1, ft, d, u, uy_p);
   }
-  pull_row(a, ic, j0, fc, dr_c, ux_c, uy_c);
-  real t0 = T_at(a, i, j0 - 2), t1 = T_at(a, i, j0 - 1), t2 = T_at(a, i, j0);
-  real t3 = T_at(a, i, j0 + 1), t4 = T_at(a, i, j0 + 2);
+  LF_PULL(j0, fc, dr_c, ux_c, uy_c);
+  LF_PULL(j0 + 1, fn, dr_n, ux_n, uy_n);
+  real t0 = LF_T1(j0 - 2), t1 = LF_T1(j0 - 1);
+  real t2 = LF_T1(j0), t3 = LF_T1(j0 + 1);
+  real t4 = LF_T1(j0 + 2);
+  real tx2 = LF_T2(j0);
+  real lo = tlo[j0 * P + ic];
 
   for (int j = j0; j < j1; ++j) {
-    pull_row(a, ic, j + 1, fn, dr_n, ux_n, uy_n);
-    const real tx2 = T_at(a, ix2, j);
     const real tW1 = __shfl_up(t2, 1, 64);
     const real tE1 = __shfl_down(t2, 1, 64);
     real tW2 = __shfl_up(t2, 2, 64);
@@ -296,18 +319,20 @@ __device__ void march_general(const StepArgs<real>& a, int lane, int i, int j0, 
     const real uE = __shfl_down(ux_c, 1, 64);
     if (lane == 1) tW2 = tx2;
     if (lane == kOut) tE2 = tx2;
-    real Fw, Fe, Fs, Fn;
-    if (!a.xper && i == 0) Fw = a.tfix[0] ? real(-2) * al * (t2 - a.Tw[0]) : real(0);
-    else Fw = face_flux<real, CONV>(al, uW, ux_c, tW2, tW1, t2, tE1);
-    if (!a.xper && i == a.nx - 1) Fe = a.tfix[1] ? real(-2) * al * (a.Tw[1] - t2) : real(0);
-    else Fe = face_flux<real, CONV>(al, ux_c, uE, tW1, t2, tE1, tE2);
-    if (!a.yper && j == 0) Fs = a.tfix[2] ? real(-2) * al * (t2 - a.Tw[2]) : real(0);
-    else Fs = face_flux<real, CONV>(al, uy_p, uy_c, t0, t1, t2, t3);
-    if (!a.yper && j == a.ny - 1) Fn = a.tfix[3] ? real(-2) * al * (a.Tw[3] - t2) : real(0);
-    else Fn = face_flux<real, CONV>(al, uy_c, uy_n, t1, t2, t3, t4);
+    const real fw = face_flux<real, CONV>(al, uW, ux_c, tW2, tW1, t2, tE1);
+    const real fe = face_flux<real, CONV>(al, ux_c, uE, tW1, t2, tE1, tE2);
+    const real fs = face_flux<real, CONV>(al, uy_p, uy_c, t0, t1, t2, t3);
+    const real fnn = face_flux<real, CONV>(al, uy_c, uy_n, t1, t2, t3, t4);
+    const real wW = fixW ? real(-2) * al * (t2 - TwW) : real(0);
+    const real wE = fixE ? real(-2) * al * (TwE - t2) : real(0);
+    const real wS = fixS ? real(-2) * al * (t2 - TwS) : real(0);
+    const real wN = fixN ? real(-2) * al * (TwN - t2) : real(0);
+    const real Fw = (!XP && i == 0) ? wW : fw;
+    const real Fe = (!XP && i == nx - 1) ? wE : fe;
+    const real Fs = (!YP && j == 0) ? wS : fs;
+    const real Fn = (!YP && j == ny - 1) ? wN : fnn;
     real Tnew, Tlo = real(0);
     if (a.Tlo_in) {
-      const real lo = a.Tlo_in[j * a.pitch + ic];
       t_update(t2, lo, -(Fe - Fw) - (Fn - Fs), Tnew, Tlo);
     } else {
       Tnew = t2 - (Fe - Fw) - (Fn - Fs);
@@ -315,9 +340,10 @@ __device__ void march_general(const StepArgs<real>& a, int lane, int i, int j0, 
     if (act) {
       real fo[9];
       collide(a, fc, dr_c, ux_c, uy_c, Tnew, fo);
-      store_node(a, j * a.pitch + i, fo, Tnew, dr_c, ux_c, uy_c);
-      if (a.Tlo_out) a.Tlo_out[j * a.pitch + i] = Tlo;
+      store_node(a, j * P + i, fo, Tnew, dr_c, ux_c, uy_c);
+      if (a.Tlo_out) a.Tlo_out[j * P + i] = Tlo;
     }
+    if (j + 1 == j1) break;
     uy_p = uy_c;
 #pragma unroll
     for (int q = 0; q < 9; ++q) fc[q] = fn[q];
@@ -328,8 +354,24 @@ __device__ void march_general(const StepArgs<real>& a, int lane, int i, int j0, 
     t1 = t2;
     t2 = t3;
     t3 = t4;
-    t4 = T_at(a, i, j + 3);
+    // inputs of row j + 1
+    LF_PULL(j + 2, fn, dr_n, ux_n, uy_n);
+    t4 = LF_T1(j + 3);
+    tx2 = LF_T2(j + 1);
+    lo = tlo[(j + 1) * P + ic];
   }
+#undef LF_PULL
+#undef LF_T1
+#undef LF_T2
+}
+
+template <typename real, int CONV>
+__device__ __forceinline__ void march_general_any(const StepArgs<real>& a, int lane, int i,
+                                                  int j0, int j1) {
+  if (!a.xper && !a.yper) march_general<real, CONV, false, false>(a, lane, i, j0, j1);
+  else if (a.xper && !a.yper) march_general<real, CONV, true, false>(a, lane, i, j0, j1);
+  else if (!a.xper) march_general<real, CONV, false, true>(a, lane, i, j0, j1);
+  else march_general<real, CONV, true, true>(a, lane, i, j0, j1);
 }
 
 // Buffer-resource access: one descriptor per array, a per-lane byte offset
@@ -384,6 +426,8 @@ __device__ void march_interior(const StepArgs<real>& a, int lane, int i, int j0,
   const __amdgpu_buffer_rsrc_t rT = make_rsrc(a.Tin, pbytes);
   const __amdgpu_buffer_rsrc_t wf = make_rsrc(a.fout, fbytes);
   const __amdgpu_buffer_rsrc_t wT = make_rsrc(a.Tout, pbytes);
+  // low words of a compensated T (read from T itself, and ignored, when absent)
+  const __amdgpu_buffer_rsrc_t rL = make_rsrc(a.Tlo_in ? a.Tlo_in : a.Tin, pbytes);
   int sq[9];  // uniform byte offset of direction q's upstream node
 #pragma unroll
   for (int q = 0; q < 9; ++q) sq[q] = (q * a.plane - ey(q) * P - ex(q)) * es;
@@ -398,7 +442,6 @@ __device__ void march_interior(const StepArgs<real>& a, int lane, int i, int j0,
   };
   auto T_row = [&](int r) { return bload<real>(rT, (r * P + i) * es, 0); };
 
-#if LF_PREFETCH_ROWS == 2
   // rows j0-1 .. j0+2 requested up front; row j+3 is requested while row j
   // is computed (two rows ahead).  Four arrays rotate by unrolling.
   real A[9], B[9], C[9], D[9];
@@ -410,33 +453,23 @@ __device__ void march_interior(const StepArgs<real>& a, int lane, int i, int j0,
   const real tm2 = T_row(j0 - 2);
   real t1 = T_row(j0 - 1), t2 = T_row(j0), t3 = T_row(j0 + 1), t4 = T_row(j0 + 2);
   real t5 = T_row(j0 + 3 < a.ny ? j0 + 3 : j0 + 2);
+  // the column beyond the halo lanes and the low words, one row ahead
+  auto tx_row = [&](int r) { return bload<real>(rT, (r * P + i) * es + xoff, 0); };
+  auto lo_row = [&](int r) { return bload<real>(rL, (r * P + i) * es, 0); };
+  real txa = tx_row(j0), loa = lo_row(j0);
   moments(D, d_unused, u_unused, uy_p);
   moments(A, dr_c, ux_c, uy_c);
   real Fs = face_flux<real, CONV>(al, uy_p, uy_c, tm2, t1, t2, t3);
 
   auto row = [&](int j, const real (&fc)[9], const real (&fn)[9], real (&fl)[9]) {
     if (j + 3 <= j1) load_row(j + 3, fl);  // prefetch two rows ahead
-#else
-  real A[9], B[9], C[9];
-  real dr_c, ux_c, uy_c, uy_p, d_unused, u_unused;
-  load_row(j0 - 1, C);
-  load_row(j0, A);
-  load_row(j0 + 1, B);
-  const real tm2 = T_row(j0 - 2);
-  real t1 = T_row(j0 - 1), t2 = T_row(j0), t3 = T_row(j0 + 1), t4 = T_row(j0 + 2);
-  moments(C, d_unused, u_unused, uy_p);
-  moments(A, dr_c, ux_c, uy_c);
-  // south face of the first row: the north face of row j0 - 1
-  real Fs = face_flux<real, CONV>(al, uy_p, uy_c, tm2, t1, t2, t3);
-
-  // one row: fc holds row j's streamed populations, fn row j + 1's; fl
-  // receives row j + 2's.  The three arrays rotate by unrolling (no copies).
-  auto row = [&](int j, const real (&fc)[9], const real (&fn)[9], real (&fl)[9]) {
-    if (j + 2 <= j1) load_row(j + 2, fl);  // prefetch
-#endif
     real dr_n, ux_n, uy_n;
     moments(fn, dr_n, ux_n, uy_n);
-    const real tx = bload<real>(rT, (j * P + i) * es + xoff, 0);
+    const real tx = txa, lo = loa;
+    if (j + 1 < j1) {
+      txa = tx_row(j + 1);
+      loa = lo_row(j + 1);
+    }
     real tW1 = __shfl_up(t2, 1, 64);
     const real tE1 = __shfl_down(t2, 1, 64);
     real tE2 = __shfl_down(t2, 2, 64);
@@ -448,7 +481,6 @@ __device__ void march_interior(const StepArgs<real>& a, int lane, int i, int j0,
     const real Fn = face_flux<real, CONV>(al, uy_c, uy_n, t1, t2, t3, t4);
     real Tnew, Tlo = real(0);
     if (a.Tlo_in) {
-      const real lo = a.Tlo_in[j * P + i];
       t_update(t2, lo, -(Fe - Fw) - (Fn - Fs), Tnew, Tlo);
     } else {
       Tnew = t2 - (Fe - Fw) - (Fn - Fs);
@@ -476,7 +508,6 @@ __device__ void march_interior(const StepArgs<real>& a, int lane, int i, int j0,
     t1 = t2;
     t2 = t3;
     t3 = t4;
-#if LF_PREFETCH_ROWS == 2
     t4 = t5;
     if (j + 4 < a.ny) t5 = T_row(j + 4);
   };
@@ -490,18 +521,6 @@ __device__ void march_interior(const StepArgs<real>& a, int lane, int i, int j0,
     row(j + 3, D, A, C);
   }
 }
-#else
-    if (j + 3 < a.ny) t4 = T_row(j + 3);
-  };
-  for (int j = j0; j < j1; j += 3) {
-    row(j, A, B, C);
-    if (j + 1 >= j1) break;
-    row(j + 1, B, C, A);
-    if (j + 2 >= j1) break;
-    row(j + 2, C, A, B);
-  }
-}
-#endif
 
 template <typename real, int CONV>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LF_STEP_WAVES(real))))
@@ -523,7 +542,7 @@ void k_hybrid_step(StepArgs<real> a) {
   const int j1 = min(j0 + a.band, a.ny);
   const bool interior = c0 - 1 >= 1 && c0 + kOut <= a.nx - 2 && j0 - 1 >= 2 && j1 <= a.ny - 2;
   if (interior) march_interior<real, CONV>(a, lane, i, j0, j1);
-  else march_general<real, CONV>(a, lane, i, j0, j1);
+  else march_general_any<real, CONV>(a, lane, i, j0, j1);
 }
 
 // ---------------------------------------------------------------------------
@@ -594,7 +613,7 @@ void k_batch_step(const TileDesc* __restrict__ tiles, const int* __restrict__ nt
   const int j0 = t.j0, j1 = t.j1;
   const bool interior = c0 - 1 >= 1 && c0 + kOut <= a.nx - 2 && j0 - 1 >= 2 && j1 <= a.ny - 2;
   if (interior) march_interior<real, CONV>(a, lane, i, j0, j1);
-  else march_general<real, CONV>(a, lane, i, j0, j1);
+  else march_general<real, CONV, false, false>(a, lane, i, j0, j1);  // batches: no periodic sides
 }
 
 // Batched residual, pass 1: one block per (cavity, row range); six FP64

@@ -10,8 +10,8 @@
 //              and the east wall face): u on x-faces [ny][pitch_F], v on
 //              y-faces [ny+1][pitch_F], p and T at centres [ny][pitch_F];
 //   shared columns c0, c0+1, c0+2 = ib.
-// One step is six launches on one stream:
-//   k_dd_ghost    ghost columns of the FV zone from the LBM moments of the
+// One step is eight launches on one stream:
+//   k_dd_ghost_rows, k_dd_ghost_fold  ghost columns of the FV zone from the LBM moments of the
 //                 previous step (two-point averages; the mean of the inflow
 //                 face is removed: global continuity of the FV zone) and
 //                 rho0 = mean LBM density over the shared columns (Eq 91-93);
@@ -19,7 +19,7 @@
 //                 gradient, buoyancy on v faces; Eq 74-75 explicit);
 //   k_dd_press_energy  p <- p - c_s^2 div u*, and the conservative QUICK
 //                 energy balance on u* (Eq 76);
-//   k_dd_pbar     mean FV pressure over the shared columns;
+//   k_dd_pbar_rows, k_dd_pbar_fold  mean FV pressure over the shared columns;
 //   k_dd_lbm      pull-stream + bounce-back / anti-bounce-back walls,
 //                 moments, BGK collision with buoyancy from T = sum g
 //                 (Eq 5, 18, 19-23) for nodes 0 .. ib-1; the streamed state
@@ -86,6 +86,8 @@ __device__ __forceinline__ real feq_s(int q, real drho, real ux, real uy) {
   return w9<real>(q) * fmad(rho, P, drho);
 }
 
+constexpr int kIfacePart = 8;
+
 template <typename real>
 struct SplitArgs {
   // LBM zone
@@ -105,7 +107,8 @@ struct SplitArgs {
   real* __restrict__ Tn;
   real* __restrict__ p;
   int pF;
-  // interface scalars (double): [0] rho0, [1] p_bar
+  // interface scalars (double): [0] rho0, [1] p_bar, from [kIfacePart] the
+  // per-block sums of the ghost kernel
   double* __restrict__ iface;
   int nx, ny, s, c0, ib;
   int conv, kind, mom_all;
@@ -154,28 +157,17 @@ __device__ __forceinline__ real P_at(const SplitArgs<real>& a, int x, int j) {
   return a.p[j * a.pF + fidx(a, x)];
 }
 
-// ---- block reduction helpers (one block of 1024 threads) ----------------
-__device__ __forceinline__ double block_sum1024(double v, double* sh) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) sh[w] = v;
-  __syncthreads();
-  double s = 0.0;
-  if (threadIdx.x == 0) {
-    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += sh[k];
-    sh[16] = s;
-  }
-  __syncthreads();
-  const double r = sh[16];
-  __syncthreads();
-  return r;
-}
+// 1. ghost columns from the LBM moments of the previous step; rho0.
+//    (a) one thread per row (and per y-face): ghost values, plus per-block
+//        sums of the inflow face and of rho over the shared columns,
+//        reduced in a fixed order;
+//    (b) one block folds the block sums in order, removes the inflow
+//        face's mean and stores rho0.
+constexpr int kGhostBlock = 256;
 
-// 1. ghost columns from the LBM moments of the previous step; rho0
 template <typename real>
-__global__ __launch_bounds__(1024) void k_dd_ghost(SplitArgs<real> a) {
-  __shared__ double sh[17];
+__global__ __launch_bounds__(kGhostBlock) void k_dd_ghost_rows(SplitArgs<real> a) {
+  __shared__ double sh[2][kGhostBlock];
   real* u = const_cast<real*>(a.u);
   real* v = const_cast<real*>(a.v);
   real* T = const_cast<real*>(a.T);
@@ -184,30 +176,59 @@ __global__ __launch_bounds__(1024) void k_dd_ghost(SplitArgs<real> a) {
   const real* uy = a.mom + 2 * a.planeL;
   const real* TL = a.mom + 3 * a.planeL;
   const int c0 = a.c0, ny = a.ny;
+  const int j = blockIdx.x * kGhostBlock + threadIdx.x;
   double su = 0.0, sr = 0.0;
-  for (int j = threadIdx.x; j < ny; j += blockDim.x) {
+  if (j < ny) {
     const int o = j * a.pL;
     const real uf0 = real(0.5) * (ux[o + c0 - 2] + ux[o + c0 - 1]);
     const real uf1 = real(0.5) * (ux[o + c0 - 1] + ux[o + c0]);
     u[j * a.pF + fidx(a, c0 - 1)] = uf0;
     u[j * a.pF + fidx(a, c0)] = uf1;
-    su += (double)uf1;
+    su = (double)uf1;
     T[j * a.pF + fidx(a, c0 - 2)] = TL[o + c0 - 2];
     T[j * a.pF + fidx(a, c0 - 1)] = TL[o + c0 - 1];
-    sr += (double)rho[o + c0] + (double)rho[o + c0 + 1] + (double)rho[o + c0 + 2];
+    sr = (double)rho[o + c0] + (double)rho[o + c0 + 1] + (double)rho[o + c0 + 2];
   }
-  for (int jf = threadIdx.x; jf <= ny; jf += blockDim.x) {
+  if (j <= ny) {
+    const int jf = j;
     for (int x = c0 - 2; x <= c0 - 1; ++x) {
       real vv = real(0);
       if (jf > 0 && jf < ny) vv = real(0.5) * (uy[(jf - 1) * a.pL + x] + uy[jf * a.pL + x]);
       v[jf * a.pF + fidx(a, x)] = vv;
     }
   }
-  const double tot_u = block_sum1024(su, sh);
-  const double tot_r = block_sum1024(sr, sh);
-  const real mean_u = (real)(tot_u / ny);
-  for (int j = threadIdx.x; j < ny; j += blockDim.x) u[j * a.pF + fidx(a, c0)] -= mean_u;
-  if (threadIdx.x == 0) a.iface[0] = tot_r / (3.0 * ny);
+  sh[0][threadIdx.x] = su;
+  sh[1][threadIdx.x] = sr;
+  __syncthreads();
+  for (int k = kGhostBlock / 2; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + k];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + k];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    a.iface[kIfacePart + 2 * blockIdx.x] = sh[0][0];
+    a.iface[kIfacePart + 2 * blockIdx.x + 1] = sh[1][0];
+  }
+}
+
+template <typename real>
+__global__ __launch_bounds__(1024) void k_dd_ghost_fold(SplitArgs<real> a, int nblocks) {
+  __shared__ real mean_sh;
+  if (threadIdx.x == 0) {
+    double tu = 0.0, tr = 0.0;
+    for (int b = 0; b < nblocks; ++b) {
+      tu += a.iface[kIfacePart + 2 * b];
+      tr += a.iface[kIfacePart + 2 * b + 1];
+    }
+    mean_sh = (real)(tu / a.ny);
+    a.iface[0] = tr / (3.0 * a.ny);
+  }
+  __syncthreads();
+  real* u = const_cast<real*>(a.u);
+  const real mean_u = mean_sh;
+  for (int j = threadIdx.x; j < a.ny; j += blockDim.x) u[j * a.pF + fidx(a, a.c0)] -= mean_u;
 }
 
 // 2. momentum: u* on x-faces c0+1 .. nx-1, v* on y-faces 1 .. ny-1 of the
@@ -319,15 +340,30 @@ __global__ __launch_bounds__(256) void k_dd_press_energy(SplitArgs<real> a) {
   a.Tn[o] = a.T[o] - (F[1] - F[0]) - (G[1] - G[0]);
 }
 
-// 4. p_bar: mean new FV pressure over the shared columns
+// 4. p_bar: mean new FV pressure over the shared columns; per-block sums
+//    (one thread per row) then an in-order fold by one thread
 template <typename real>
-__global__ __launch_bounds__(1024) void k_dd_pbar(SplitArgs<real> a) {
-  __shared__ double sh[17];
+__global__ __launch_bounds__(kGhostBlock) void k_dd_pbar_rows(SplitArgs<real> a) {
+  __shared__ double sh[kGhostBlock];
+  const int j = blockIdx.x * kGhostBlock + threadIdx.x;
   double s = 0.0;
-  for (int j = threadIdx.x; j < a.ny; j += blockDim.x)
+  if (j < a.ny)
     for (int x = a.c0; x <= a.ib; ++x) s += (double)a.p[j * a.pF + fidx(a, x)];
-  const double tot = block_sum1024(s, sh);
-  if (threadIdx.x == 0) a.iface[1] = tot / (3.0 * a.ny);
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = kGhostBlock / 2; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.iface[kIfacePart + blockIdx.x] = sh[0];
+}
+
+template <typename real>
+__global__ void k_dd_pbar_fold(SplitArgs<real> a, int nblocks) {
+  if (threadIdx.x != 0) return;
+  double t = 0.0;
+  for (int b = 0; b < nblocks; ++b) t += a.iface[kIfacePart + b];
+  a.iface[1] = t / (3.0 * a.ny);
 }
 
 // 5. LBM zone, nodes 0 .. ib-1: stream, moments, collide
@@ -599,10 +635,14 @@ hipError_t launch_split_step(const SplitGeom& G, const SplitPtrs<real>& P, const
                              int cur, int mom_all, hipStream_t s) {
   const SplitArgs<real> a = make_args<real>(G, P, S, cur, mom_all);
   const int nfc = G.nx - G.c0 + 1;  // FV columns c0 .. nx
-  hipLaunchKernelGGL(k_dd_ghost<real>, dim3(1), dim3(1024), 0, s, a);
+  const int ngb = (G.ny + 1 + kGhostBlock - 1) / kGhostBlock;  // rows and y-faces 0 .. ny
+  hipLaunchKernelGGL(k_dd_ghost_rows<real>, dim3(ngb), dim3(kGhostBlock), 0, s, a);
+  hipLaunchKernelGGL(k_dd_ghost_fold<real>, dim3(1), dim3(1024), 0, s, a, ngb);
   hipLaunchKernelGGL(k_dd_momentum<real>, dim3((nfc + 255) / 256, G.ny + 1), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_dd_press_energy<real>, dim3((nfc + 255) / 256, G.ny), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_dd_pbar<real>, dim3(1), dim3(1024), 0, s, a);
+  const int npb = (G.ny + kGhostBlock - 1) / kGhostBlock;
+  hipLaunchKernelGGL(k_dd_pbar_rows<real>, dim3(npb), dim3(kGhostBlock), 0, s, a);
+  hipLaunchKernelGGL(k_dd_pbar_fold<real>, dim3(1), dim3(64), 0, s, a, npb);
   hipLaunchKernelGGL(k_dd_lbm<real>, dim3((G.ib + 63) / 64, (G.ny + 3) / 4), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_dd_xb<real>, dim3((G.ny + 255) / 256), dim3(256), 0, s, a);
   return hipGetLastError();

@@ -77,7 +77,8 @@ static void layout_split(lf_case* c) {
   for (int k = 0; k < 2; ++k) { c->off_sv[k] = o; o += pbF; }
   for (int k = 0; k < 2; ++k) { c->off_sT[k] = o; o += pbF; }
   c->off_sp = o; o += pbF;
-  c->off_siface = o; o += 256;
+  // interface scalars, then two sums per 256-row block of the ghost kernel
+  c->off_siface = o; o += align_up((size_t)(8 + 2 * ((G.ny + 1 + 255) / 256)) * sizeof(double), 256);
   c->off_dense = o; o += 4 * pbD;
   c->off_dsnap = o; o += 3 * pbD;
   c->off_part = o; o += align_up((size_t)c->nblk * 8 * sizeof(double), 256);

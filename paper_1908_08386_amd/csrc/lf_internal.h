@@ -139,7 +139,7 @@ struct SplitPtrs {
   real* v[2];   // y-faces, (ny + 1) rows * pF
   real* T[2];   // centres
   real* p;      // centres
-  double* iface;  // [0] rho0, [1] p_bar
+  double* iface;  // [0] rho0, [1] p_bar, from [8] two sums per 256 rows
 };
 
 struct SplitParams {
