@@ -233,11 +233,13 @@ __global__ __launch_bounds__(1024) void k_dd_ghost_fold(SplitArgs<real> a, int n
 
 // 2. momentum: u* on x-faces c0+1 .. nx-1, v* on y-faces 1 .. ny-1 of the
 //    FV cells; wall and prescribed faces copied.
-template <typename real>
-__global__ __launch_bounds__(256) void k_dd_momentum(SplitArgs<real> a) {
-  const int x = a.c0 + blockIdx.x * blockDim.x + threadIdx.x;  // c0 .. nx
-  const int j = blockIdx.y;                                    // 0 .. ny
-  if (x > a.nx) return;
+template <typename real, bool FAST>
+__device__ __forceinline__ void momentum_at(const SplitArgs<real>& a, int x, int j) {
+  // FAST: the block's stencils stay inside the stored FV zone (no wall
+  // mirror or ghost rule applies), so the fields are indexed directly
+#define UA(arr, xx, jj) (FAST ? (arr)[(jj) * a.pF + fidx(a, xx)] : U_at(a, arr, xx, jj))
+#define VA(arr, xx, jj) (FAST ? (arr)[(jj) * a.pF + fidx(a, xx)] : V_at(a, arr, xx, jj))
+#define TA(arr, xx, jj) (FAST ? (arr)[(jj) * a.pF + fidx(a, xx)] : T_at(a, arr, xx, jj))
   const int conv = a.conv;
   const real nu = a.nu;
   // ---- u* at face (x, j)
@@ -252,19 +254,19 @@ __global__ __launch_bounds__(256) void k_dd_momentum(SplitArgs<real> a) {
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
         const int m = x - 1 + k;
-        const real ub = real(0.5) * (U_at(a, a.u, m, j) + U_at(a, a.u, m + 1, j));
-        const real uh = quick(conv, ub, U_at(a, a.u, m - 1, j), U_at(a, a.u, m, j),
-                              U_at(a, a.u, m + 1, j), U_at(a, a.u, m + 2, j));
+        const real ub = real(0.5) * (UA(a.u, m, j) + UA(a.u, m + 1, j));
+        const real uh = quick(conv, ub, UA(a.u, m - 1, j), UA(a.u, m, j),
+                              UA(a.u, m + 1, j), UA(a.u, m + 2, j));
         Fc[k] = ub * uh;
         const int jf = j + k;
-        const real vb = real(0.5) * (V_at(a, a.v, x - 1, jf) + V_at(a, a.v, x, jf));
-        const real uh2 = quick(conv, vb, U_at(a, a.u, x, jf - 2), U_at(a, a.u, x, jf - 1),
-                               U_at(a, a.u, x, jf), U_at(a, a.u, x, jf + 1));
+        const real vb = real(0.5) * (VA(a.v, x - 1, jf) + VA(a.v, x, jf));
+        const real uh2 = quick(conv, vb, UA(a.u, x, jf - 2), UA(a.u, x, jf - 1),
+                               UA(a.u, x, jf), UA(a.u, x, jf + 1));
         Gc[k] = vb * uh2;
       }
-      const real uc = U_at(a, a.u, x, j);
-      const real lap = U_at(a, a.u, x + 1, j) + U_at(a, a.u, x - 1, j) + U_at(a, a.u, x, j + 1) +
-                       U_at(a, a.u, x, j - 1) - real(4) * uc;
+      const real uc = UA(a.u, x, j);
+      const real lap = UA(a.u, x + 1, j) + UA(a.u, x - 1, j) + UA(a.u, x, j + 1) +
+                       UA(a.u, x, j - 1) - real(4) * uc;
       const real dp = P_at(a, x, j) - P_at(a, x - 1, j);
       out = uc - (Fc[1] - Fc[0]) - (Gc[1] - Gc[0]) + nu * lap - dp;
     }
@@ -279,38 +281,53 @@ __global__ __launch_bounds__(256) void k_dd_momentum(SplitArgs<real> a) {
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
         const int m = jf - 1 + k;
-        const real vb = real(0.5) * (V_at(a, a.v, x, m) + V_at(a, a.v, x, m + 1));
-        const real vh = quick(conv, vb, V_at(a, a.v, x, m - 1), V_at(a, a.v, x, m),
-                              V_at(a, a.v, x, m + 1), V_at(a, a.v, x, m + 2));
+        const real vb = real(0.5) * (VA(a.v, x, m) + VA(a.v, x, m + 1));
+        const real vh = quick(conv, vb, VA(a.v, x, m - 1), VA(a.v, x, m),
+                              VA(a.v, x, m + 1), VA(a.v, x, m + 2));
         Fc[k] = vb * vh;
         const int xc = x + k;
-        const real ub = real(0.5) * (U_at(a, a.u, xc, jf - 1) + U_at(a, a.u, xc, jf));
-        const real vh2 = quick(conv, ub, V_at(a, a.v, xc - 2, jf), V_at(a, a.v, xc - 1, jf),
-                               V_at(a, a.v, xc, jf), V_at(a, a.v, xc + 1, jf));
+        const real ub = real(0.5) * (UA(a.u, xc, jf - 1) + UA(a.u, xc, jf));
+        const real vh2 = quick(conv, ub, VA(a.v, xc - 2, jf), VA(a.v, xc - 1, jf),
+                               VA(a.v, xc, jf), VA(a.v, xc + 1, jf));
         Gc[k] = ub * vh2;
       }
-      const real vc = V_at(a, a.v, x, jf);
-      const real lap = V_at(a, a.v, x + 1, jf) + V_at(a, a.v, x - 1, jf) +
-                       V_at(a, a.v, x, jf + 1) + V_at(a, a.v, x, jf - 1) - real(4) * vc;
+      const real vc = VA(a.v, x, jf);
+      const real lap = VA(a.v, x + 1, jf) + VA(a.v, x - 1, jf) +
+                       VA(a.v, x, jf + 1) + VA(a.v, x, jf - 1) - real(4) * vc;
       const real dp = P_at(a, x, jf) - P_at(a, x, jf - 1);
-      const real Tf = real(0.5) * (T_at(a, a.T, x, jf - 1) + T_at(a, a.T, x, jf));
+      const real Tf = real(0.5) * (TA(a.T, x, jf - 1) + TA(a.T, x, jf));
       out = vc - (Gc[1] - Gc[0]) - (Fc[1] - Fc[0]) + nu * lap - dp + a.gbeta * (Tf - a.Tref);
     }
     a.vs[jf * a.pF + fidx(a, x)] = out;
   }
+#undef UA
+#undef VA
+#undef TA
+}
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_dd_momentum(SplitArgs<real> a) {
+  const int x0 = a.c0 + blockIdx.x * blockDim.x;
+  const int x = x0 + threadIdx.x;  // c0 .. nx
+  const int j = blockIdx.y;        // 0 .. ny
+  if (x > a.nx) return;
+  // u* reaches u, v two faces away and p, T one cell away in x and y
+  const bool fast = x0 > a.c0 && x0 + (int)blockDim.x + 2 < a.nx && j >= 2 && j + 3 <= a.ny - 1;
+  if (fast) momentum_at<real, true>(a, x, j);
+  else momentum_at<real, false>(a, x, j);
 }
 
 // 3. pressure (artificial compressibility, beta = c_s^2) and energy on u*
-template <typename real>
-__global__ __launch_bounds__(256) void k_dd_press_energy(SplitArgs<real> a) {
-  const int x = a.c0 + blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y;
-  if (x >= a.nx) return;
+template <typename real, bool FAST>
+__device__ __forceinline__ void press_energy_at(const SplitArgs<real>& a, int x, int j) {
+#define UA(arr, xx, jj) (FAST ? (arr)[(jj) * a.pF + fidx(a, xx)] : U_at(a, arr, xx, jj))
+#define VA(arr, xx, jj) (FAST ? (arr)[(jj) * a.pF + fidx(a, xx)] : V_at(a, arr, xx, jj))
+#define TA(arr, xx, jj) (FAST ? (arr)[(jj) * a.pF + fidx(a, xx)] : T_at(a, arr, xx, jj))
   const int conv = a.conv;
   const real al = a.alpha;
-  const real ue = x == a.nx - 1 ? real(0) : U_at(a, a.us, x + 1, j);
-  const real uw = U_at(a, a.us, x, j);
-  const real vn = V_at(a, a.vs, x, j + 1), vsd = V_at(a, a.vs, x, j);
+  const real ue = x == a.nx - 1 ? real(0) : UA(a.us, x + 1, j);
+  const real uw = UA(a.us, x, j);
+  const real vn = VA(a.vs, x, j + 1), vsd = VA(a.vs, x, j);
   const int o = j * a.pF + fidx(a, x);
   a.p[o] = a.p[o] - real(1) / real(3) * ((ue - uw) + (vn - vsd));
   real F[2], G[2];
@@ -320,10 +337,10 @@ __global__ __launch_bounds__(256) void k_dd_press_energy(SplitArgs<real> a) {
     if (xf == a.nx) {
       F[k] = a.tfix[1] ? real(-2) * al * (a.Tw[1] - a.T[o]) : real(0);
     } else {
-      const real uf = U_at(a, a.us, xf, j);
-      const real th = quick(conv, uf, T_at(a, a.T, xf - 2, j), T_at(a, a.T, xf - 1, j),
-                            T_at(a, a.T, xf, j), T_at(a, a.T, xf + 1, j));
-      F[k] = fmad(uf, th, -al * (T_at(a, a.T, xf, j) - T_at(a, a.T, xf - 1, j)));
+      const real uf = UA(a.us, xf, j);
+      const real th = quick(conv, uf, TA(a.T, xf - 2, j), TA(a.T, xf - 1, j),
+                            TA(a.T, xf, j), TA(a.T, xf + 1, j));
+      F[k] = fmad(uf, th, -al * (TA(a.T, xf, j) - TA(a.T, xf - 1, j)));
     }
     const int jf = j + k;
     if (jf == 0) {
@@ -331,13 +348,28 @@ __global__ __launch_bounds__(256) void k_dd_press_energy(SplitArgs<real> a) {
     } else if (jf == a.ny) {
       G[k] = a.tfix[3] ? real(-2) * al * (a.Tw[3] - a.T[o]) : real(0);
     } else {
-      const real vf = V_at(a, a.vs, x, jf);
-      const real th = quick(conv, vf, T_at(a, a.T, x, jf - 2), T_at(a, a.T, x, jf - 1),
-                            T_at(a, a.T, x, jf), T_at(a, a.T, x, jf + 1));
-      G[k] = fmad(vf, th, -al * (T_at(a, a.T, x, jf) - T_at(a, a.T, x, jf - 1)));
+      const real vf = VA(a.vs, x, jf);
+      const real th = quick(conv, vf, TA(a.T, x, jf - 2), TA(a.T, x, jf - 1),
+                            TA(a.T, x, jf), TA(a.T, x, jf + 1));
+      G[k] = fmad(vf, th, -al * (TA(a.T, x, jf) - TA(a.T, x, jf - 1)));
     }
   }
   a.Tn[o] = a.T[o] - (F[1] - F[0]) - (G[1] - G[0]);
+#undef UA
+#undef VA
+#undef TA
+}
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_dd_press_energy(SplitArgs<real> a) {
+  const int x0 = a.c0 + blockIdx.x * blockDim.x;
+  const int x = x0 + threadIdx.x;
+  const int j = blockIdx.y;
+  if (x >= a.nx) return;
+  // T reaches two cells away in x and y, u*, v* one face
+  const bool fast = x0 + (int)blockDim.x + 2 < a.nx && j >= 2 && j + 3 <= a.ny - 1;
+  if (fast) press_energy_at<real, true>(a, x, j);
+  else press_energy_at<real, false>(a, x, j);
 }
 
 // 4. p_bar: mean new FV pressure over the shared columns; per-block sums
