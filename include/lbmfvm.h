@@ -178,6 +178,16 @@ lf_status lf_case_fetch(lf_case* c, int field, void* dst, size_t dst_bytes,
 lf_status lf_case_mass(lf_case* c, double* sum_f, double* sum_T);
 /* Steps taken since init.                                                 */
 lf_status lf_case_steps(const lf_case* c, int64_t* steps);
+/* Checkpoint: the complete state of an initialised case (fields, moments,
+ * residual snapshot, step count, lattice parameters and walls) as a host
+ * blob.  With blob == NULL, *bytes receives the size needed; otherwise
+ * *bytes must hold at least that size and receives the size written
+ * (synchronises the stream).  lf_case_load restores such a blob into a
+ * case created with the same lf_case_desc and a bound workspace; stepping
+ * on continues bit for bit as the saved case would have (LF_EINVAL if the
+ * blob does not match).                                                   */
+lf_status lf_case_save(lf_case* c, void* blob, size_t* bytes);
+lf_status lf_case_load(lf_case* c, const void* blob, size_t bytes);
 /* Advance nsteps (1 .. 2^20) steps, launched back to back on the context
  * stream with a HIP event after every 64 launches; synchronises at the end
  * and returns the mean time per step kernel in milliseconds and the min /

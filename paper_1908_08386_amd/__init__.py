@@ -8,9 +8,12 @@ CPU fallback.
 
 Entry points mirror include/lbmfvm.h:
     ctx = Context(device=0)
-    c = Case(ctx, nx, ny, precision="f32")
+    c = Case(ctx, nx, ny, precision="f32")          # lf_case_*
     c.set_physics(Ra, Pr); c.set_cavity_walls(); c.init(T0)
-    c.step(n); c.residual(); c.nusselt(); c.fetch("T")
+    c.step(n); c.residual(); c.nusselt(); c.fetch("T"); c.save() / c.load(blob)
+    b = Batch(ctx, cases); b.init(T0s); b.run_to_steady()   # lf_batch_*
+    net = Net(ctx); net.train_step(...); net.forward(...)    # lf_net_*
+    resample(ctx, src, dst)                                   # lf_resample
 """
 from __future__ import annotations
 
@@ -133,6 +136,8 @@ _SIGS = {
     "lf_ctx_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(ctypes.c_int)]),
+    "lf_case_save": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "lf_case_load": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
     "lf_batch_init_device": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                             ctypes.POINTER(_vp)]),
     "lf_net_create": (ctypes.c_int, [_vp, ctypes.POINTER(lf_net_desc), ctypes.POINTER(_vp)]),
@@ -363,6 +368,19 @@ class Case:
                                   out.numel() * out.element_size(), 1, as64), "lf_case_fetch")
         self.ctx.leave()
         return out
+
+    def save(self) -> bytes:
+        """Checkpoint of the complete case state (see lf_case_save)."""
+        n = ctypes.c_size_t()
+        _check(_lib.lf_case_save(self._h, None, ctypes.byref(n)), "lf_case_save")
+        buf = ctypes.create_string_buffer(n.value)
+        _check(_lib.lf_case_save(self._h, buf, ctypes.byref(n)), "lf_case_save")
+        return buf.raw[:n.value]
+
+    def load(self, blob: bytes):
+        """Restore a checkpoint taken from a case of the same geometry."""
+        _check(_lib.lf_case_load(self._h, ctypes.c_char_p(blob), len(blob)), "lf_case_load")
+        return self
 
     def mass(self):
         a, b = ctypes.c_double(), ctypes.c_double()

@@ -705,6 +705,78 @@ lf_status lf_case_fetch(lf_case* c, int field, void* dst, size_t dst_bytes, int 
   return LF_OK;
 }
 
+// checkpoint blob: header, then the bound workspace's first `need` bytes
+namespace {
+struct CaseBlobHeader {
+  char magic[8];  // "LFCASE1"
+  int abi;
+  lf_case_desc desc;
+  size_t es, need;
+  int cur, have_params;
+  int64_t steps;
+  double params[8];
+  lf::WallSet w;
+  lf::HybridParams p;
+  lf::SplitParams sp;
+};
+}  // namespace
+
+lf_status lf_case_save(lf_case* c, void* blob, size_t* bytes) {
+  if (!c || !bytes) return fail(LF_EINVAL, "NULL argument");
+  if (!c->inited) return fail(LF_ESTATE, "init first");
+  const size_t total = sizeof(CaseBlobHeader) + c->need;
+  if (!blob) {
+    *bytes = total;
+    return LF_OK;
+  }
+  if (*bytes < total) return fail(LF_EINVAL, "blob holds %zu bytes, %zu needed", *bytes, total);
+  CaseBlobHeader h;
+  memset(&h, 0, sizeof(h));
+  memcpy(h.magic, "LFCASE1", 8);
+  h.abi = LF_ABI_VERSION;
+  h.desc = c->desc;
+  h.es = c->es;
+  h.need = c->need;
+  h.cur = c->cur;
+  h.have_params = c->have_params ? 1 : 0;
+  h.steps = c->steps;
+  memcpy(h.params, c->params, sizeof(h.params));
+  h.w = c->w;
+  h.p = c->p;
+  h.sp = c->sp;
+  memcpy(blob, &h, sizeof(h));
+  hipStream_t s = c->ctx->stream;
+  HIP_TRY(hipMemcpyAsync((char*)blob + sizeof(h), c->ws, c->need, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *bytes = total;
+  return LF_OK;
+}
+
+lf_status lf_case_load(lf_case* c, const void* blob, size_t bytes) {
+  if (!c || !blob) return fail(LF_EINVAL, "NULL argument");
+  if (!c->ws) return fail(LF_EWORKSPACE, "no workspace bound");
+  CaseBlobHeader h;
+  if (bytes < sizeof(h)) return fail(LF_EINVAL, "blob too short");
+  memcpy(&h, blob, sizeof(h));
+  if (memcmp(h.magic, "LFCASE1", 8) != 0 || h.abi != LF_ABI_VERSION)
+    return fail(LF_EINVAL, "not a checkpoint of this library");
+  if (memcmp(&h.desc, &c->desc, sizeof(lf_case_desc)) != 0 || h.es != c->es || h.need != c->need)
+    return fail(LF_EINVAL, "checkpoint of a different case geometry or precision");
+  if (bytes < sizeof(h) + h.need) return fail(LF_EINVAL, "blob truncated");
+  hipStream_t s = c->ctx->stream;
+  HIP_TRY(hipMemcpyAsync(c->ws, (const char*)blob + sizeof(h), h.need, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  c->cur = h.cur;
+  c->have_params = h.have_params != 0;
+  c->steps = h.steps;
+  memcpy(c->params, h.params, sizeof(h.params));
+  c->w = h.w;
+  c->p = h.p;
+  c->sp = h.sp;
+  c->inited = true;
+  return LF_OK;
+}
+
 lf_status lf_case_mass(lf_case* c, double* sum_f, double* sum_T) {
   if (!c || !sum_f || !sum_T) return fail(LF_EINVAL, "NULL argument");
   if (!c->inited) return fail(LF_ESTATE, "init first");
