@@ -1,0 +1,59 @@
+"""Host-side logic that needs no GPU: the package refuses to load without
+its compiled library, bench.py refuses more than one GPU, and the
+warm-start driver's schedules and sample orders are well formed."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_package_import_fails_loudly_without_library(tmp_path):
+    env = dict(os.environ, LBMFVM_LIB=str(tmp_path / "missing.so"))
+    r = subprocess.run([sys.executable, "-c", "import paper_1908_08386_amd"], cwd=ROOT, env=env,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0 and "no CPU fallback" in r.stderr
+
+
+def test_bench_refuses_several_gpus():
+    r = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], cwd=ROOT,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def _warmstart_module():
+    # warmstart imports the package, which loads the compiled library; the
+    # functions tested here are pure Python
+    pytest.importorskip("torch")
+    if not os.path.exists(os.path.join(ROOT, "paper_1908_08386_amd", "liblbmfvm.so")):
+        pytest.skip("library not built")
+    from paper_1908_08386_amd import train_warmstart, warmstart
+    return warmstart, train_warmstart
+
+
+def test_learning_rate_schedule():
+    ws, _ = _warmstart_module()
+    total, lr0 = 1000, 2e-3
+    lr = np.array([ws.lr_at(s, total, lr0) for s in range(total)])
+    assert lr[0] == pytest.approx(lr0 / 100) and lr[99] == pytest.approx(lr0)
+    assert np.all(np.diff(lr[:100]) > 0) and np.all(np.diff(lr[100:]) <= 1e-18)
+    assert lr[-1] == pytest.approx(lr0 * 0.02, rel=1e-3)
+
+
+def test_sample_orders_are_permutations():
+    _, tw = _warmstart_module()
+    o = tw.orders(100, 32, 3, 5)
+    assert o.shape == (9, 32) and o.dtype == np.int32
+    for e in range(3):
+        rows = o[3 * e:3 * e + 3].ravel()
+        assert len(set(rows.tolist())) == 96 and rows.min() >= 0 and rows.max() < 100
+    assert not np.array_equal(o[0], o[3])
+
+
+def test_features():
+    ws, _ = _warmstart_module()
+    f = ws.features([{"nx": 256, "ny": 64, "Ra": 1e5, "Pr": 7.0}])
+    np.testing.assert_allclose(f, [[5.0, 7.0, 4.0]], rtol=1e-6)
