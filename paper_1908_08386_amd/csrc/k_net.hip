@@ -70,38 +70,72 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
   const int cg = CK >> 3, G = 9 * cg;
   const int P = g.n * g.Ho * g.Wo;              // output pixels (BWD_WEIGHT)
 
+  // Everything a thread's loads depend on apart from the K chunk is worked
+  // out once: its tile rows' pixel coordinates and, along K, the tap and
+  // channel group it is at (advanced by four groups per chunk).
+  constexpr int AV = BM * 4 / 256;  // A vectors per thread (FWD / BWD_DATA; BWD_WEIGHT too)
+  static_assert(BM % 64 == 0 && BK == 32, "loader lanes assume 64-row A tiles, 32-wide K");
+  static_assert(MODE != BWD_WEIGHT || BN <= 64, "one B vector per thread");
+  const int q = tid & 3, rq = tid >> 2;   // FWD / BWD_DATA: K quarter and first A row
+  const int pl = tid % BK, grp = tid / BK;  // BWD_WEIGHT: pixel in the chunk, 8-row group
+  int pb[AV], p1[AV], p2[AV];
+  bool pok[AV];
+  if (MODE != BWD_WEIGHT) {
+#pragma unroll
+    for (int k = 0; k < AV; ++k) {
+      const int m = m0 + rq + 64 * k;
+      pok[k] = m < a.M;
+      const int W = MODE == FWD ? g.Wo : g.W, hw = (MODE == FWD ? g.Ho : g.H) * W;
+      const int mm = pok[k] ? m : 0;
+      pb[k] = mm / hw;
+      const int rm = mm - pb[k] * hw;
+      p1[k] = rm / W;            // FWD: oy; BWD_DATA: y
+      p2[k] = rm - p1[k] * W;    // FWD: ox; BWD_DATA: x
+    }
+  } else {
+    // pixel kc0 * BK + pl, advanced by BK per chunk
+    const int p = kc0 * BK + pl, hw = g.Ho * g.Wo;
+    pb[0] = p / hw;
+    const int rm = p - pb[0] * hw;
+    p1[0] = rm / g.Wo;
+    p2[0] = rm - p1[0] * g.Wo;
+    pok[0] = true;
+  }
+  int gi = kc0 * 4 + q;          // K group of this thread's quarter
+  int tap = gi / cg, cgp = gi - tap * cg;
+  // BWD_WEIGHT: the B rows' tap and channel group are fixed
+  const int bn8 = n0 + grp * 8;
+  const int wtap = bn8 / g.Cin, wci0 = bn8 - wtap * g.Cin;
+  const int wky = wtap / 3, wkx = wtap - wky * 3;
+
   for (int kc = kc0; kc < kc1; ++kc) {
     if (MODE != BWD_WEIGHT) {
-      for (int v = tid; v < BM * 4; v += 256) {
-        const int r = v >> 2, q = v & 3, gi = kc * 4 + q, m = m0 + r;
+      const bool gok = gi < G;
+      const int ky = tap >= 6 ? 2 : (tap >= 3 ? 1 : 0), kx = tap - 3 * ky, c0 = cgp << 3;
+#pragma unroll
+      for (int k = 0; k < AV; ++k) {
         uint4 val = {0u, 0u, 0u, 0u};
-        if (gi < G && m < a.M) {
-          const int tap = gi / cg, c0 = (gi - tap * cg) << 3;
-          const int ky = tap / 3, kx = tap - ky * 3;
+        if (gok && pok[k]) {
           if (MODE == FWD) {
-            const int hw = g.Ho * g.Wo, bi = m / hw, rm = m - bi * hw;
-            const int oy = rm / g.Wo, ox = rm - oy * g.Wo;
-            const int iy = oy * g.stride + ky - 1, ix = ox * g.stride + kx - 1;
+            const int iy = p1[k] * g.stride + ky - 1, ix = p2[k] * g.stride + kx - 1;
             if (iy >= 0 && iy < g.H && ix >= 0 && ix < g.W)
-              val = *(const uint4*)(a.x + ((size_t)(bi * g.H + iy) * g.W + ix) * g.Cin + c0);
+              val = *(const uint4*)(a.x + ((size_t)(pb[k] * g.H + iy) * g.W + ix) * g.Cin + c0);
           } else {
-            const int hw = g.H * g.W, bi = m / hw, rm = m - bi * hw;
-            const int y = rm / g.W, xx = rm - y * g.W;
-            const int ty = y + 1 - ky, tx = xx + 1 - kx;  // = stride * output index
-            if (ty >= 0 && tx >= 0 && ty % g.stride == 0 && tx % g.stride == 0) {
-              const int oy = ty / g.stride, ox = tx / g.stride;
+            const int ty = p1[k] + 1 - ky, tx = p2[k] + 1 - kx;  // = stride * output index
+            const bool even = g.stride == 1 || (((ty | tx) & 1) == 0);
+            if (ty >= 0 && tx >= 0 && even) {
+              const int oy = g.stride == 1 ? ty : ty >> 1, ox = g.stride == 1 ? tx : tx >> 1;
               if (oy < g.Ho && ox < g.Wo)
-                val = *(const uint4*)(a.dz + ((size_t)(bi * g.Ho + oy) * g.Wo + ox) * g.Cout + c0);
+                val = *(const uint4*)(a.dz + ((size_t)(pb[k] * g.Ho + oy) * g.Wo + ox) * g.Cout + c0);
             }
           }
         }
-        *(uint4*)&As[r * LDK + q * 8] = val;
+        *(uint4*)&As[(rq + 64 * k) * LDK + q * 8] = val;
       }
       for (int v = tid; v < BN * 4; v += 256) {
-        const int r = v >> 2, q = v & 3, gi = kc * 4 + q, nn = n0 + r;
+        const int r = v >> 2, nn = n0 + r;  // v & 3 == q
         uint4 val = {0u, 0u, 0u, 0u};
-        if (gi < G && nn < a.N) {
-          const int tap = gi / cg, c0 = (gi - tap * cg) << 3;
+        if (gok && nn < a.N) {
           if (MODE == FWD)
             val = *(const uint4*)(a.w + ((size_t)nn * 9 + tap) * g.Cin + c0);
           else
@@ -109,35 +143,48 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
         }
         *(uint4*)&Bs[r * LDK + q * 8] = val;
       }
+      gi += 4;
+      cgp += 4;
+      while (cgp >= cg) {
+        cgp -= cg;
+        ++tap;
+      }
     } else {
       // K = output pixels: 16-byte loads along channels, transposed into LDS
-      for (int v = tid; v < (BM / 8) * BK; v += 256) {
-        const int pl = v % BK, grp = v / BK, p = kc * BK + pl, co0 = m0 + grp * 8;
+      const bool pin = kc * BK + pl < P;
+#pragma unroll
+      for (int k = 0; k < AV; ++k) {
+        const int gk = grp + (256 / BK) * k, co0 = m0 + gk * 8;
         uint4 val = {0u, 0u, 0u, 0u};
-        if (p < P && co0 < g.Cout) val = *(const uint4*)(a.dz + (size_t)p * g.Cout + co0);
+        if (pin && co0 < g.Cout)
+          val = *(const uint4*)(a.dz + (size_t)(kc * BK + pl) * g.Cout + co0);
         const uint16_t* e = (const uint16_t*)&val;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) As[(grp * 8 + j) * LDK + pl] = e[j];
+        for (int jj = 0; jj < 8; ++jj) As[(gk * 8 + jj) * LDK + pl] = e[jj];
       }
-      for (int v = tid; v < (BN / 8) * BK; v += 256) {
-        const int pl = v % BK, grp = v / BK, p = kc * BK + pl, nn0 = n0 + grp * 8;
+      if (tid < (BN / 8) * BK) {
         uint4 val = {0u, 0u, 0u, 0u};
-        if (p < P) {
-          if (nn0 < 9 * g.Cin) {
-            const int tap = nn0 / g.Cin, ci0 = nn0 - tap * g.Cin;
-            const int ky = tap / 3, kx = tap - ky * 3;
-            const int hw = g.Ho * g.Wo, bi = p / hw, rm = p - bi * hw;
-            const int oy = rm / g.Wo, ox = rm - oy * g.Wo;
-            const int iy = oy * g.stride + ky - 1, ix = ox * g.stride + kx - 1;
+        if (pin) {
+          if (bn8 < 9 * g.Cin) {
+            const int iy = p1[0] * g.stride + wky - 1, ix = p2[0] * g.stride + wkx - 1;
             if (iy >= 0 && iy < g.H && ix >= 0 && ix < g.W)
-              val = *(const uint4*)(a.x + ((size_t)(bi * g.H + iy) * g.W + ix) * g.Cin + ci0);
-          } else if (nn0 == 9 * g.Cin) {
+              val = *(const uint4*)(a.x + ((size_t)(pb[0] * g.H + iy) * g.W + ix) * g.Cin + wci0);
+          } else if (bn8 == 9 * g.Cin) {
             val.x = 0x3F80u;  // bf16 1.0 in the first column: the bias gradient
           }
         }
         const uint16_t* e = (const uint16_t*)&val;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) Bs[(grp * 8 + j) * LDK + pl] = e[j];
+        for (int jj = 0; jj < 8; ++jj) Bs[(grp * 8 + jj) * LDK + pl] = e[jj];
+      }
+      // next chunk's pixel
+      p2[0] += BK;
+      while (p2[0] >= g.Wo) {
+        p2[0] -= g.Wo;
+        if (++p1[0] == g.Ho) {
+          p1[0] = 0;
+          ++pb[0];
+        }
       }
     }
     __syncthreads();
