@@ -231,145 +231,204 @@ __global__ __launch_bounds__(1024) void k_dd_ghost_fold(SplitArgs<real> a, int n
   for (int j = threadIdx.x; j < a.ny; j += blockDim.x) u[j * a.pF + fidx(a, a.c0)] -= mean_u;
 }
 
+// ---- field access relative to a thread's face / cell (x, j) ------------
+// GenAcc applies the wall mirror and ghost rules of U_at, V_at and T_at.
+// DirAcc serves blocks whose stencils stay inside the stored FV zone: all
+// FV arrays share one layout, so a lane keeps one byte offset (row j - 2,
+// column x - 2), the row shift is a wave-uniform SGPR offset and the column
+// shift is folded into the load instruction.
+template <typename real>
+struct GenAcc {
+  const SplitArgs<real>& a;
+  int x, j;
+  __device__ real u(int dx, int dy) const { return U_at(a, a.u, x + dx, j + dy); }
+  __device__ real v(int dx, int dy) const { return V_at(a, a.v, x + dx, j + dy); }
+  __device__ real us(int dx, int dy) const { return U_at(a, a.us, x + dx, j + dy); }
+  __device__ real vs(int dx, int dy) const { return V_at(a, a.vs, x + dx, j + dy); }
+  __device__ real T(int dx, int dy) const { return T_at(a, a.T, x + dx, j + dy); }
+  __device__ real p(int dx, int dy) const { return P_at(a, x + dx, j + dy); }
+};
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t fv_rsrc(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
+                                           0x00020000);
+}
+template <typename real>
+__device__ __forceinline__ real fv_load(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  if constexpr (sizeof(real) == 4) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  } else {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  }
+}
+
+template <typename real>
+struct DirAcc {
+  __amdgpu_buffer_rsrc_t ru, rv, rus, rvs, rT, rp;
+  int vo, rowb;
+  __device__ DirAcc(const SplitArgs<real>& a, int x, int j) {
+    const unsigned bytes = (unsigned)((size_t)(a.ny + 1) * a.pF * sizeof(real));
+    ru = fv_rsrc(a.u, bytes);
+    rv = fv_rsrc(a.v, bytes);
+    rus = fv_rsrc(a.us, bytes);
+    rvs = fv_rsrc(a.vs, bytes);
+    rT = fv_rsrc(a.T, bytes);
+    rp = fv_rsrc(a.p, bytes);
+    vo = ((j - 2) * a.pF + fidx(a, x) - 2) * (int)sizeof(real);
+    rowb = a.pF * (int)sizeof(real);
+  }
+  __device__ real ld(__amdgpu_buffer_rsrc_t r, int dx, int dy) const {
+    return fv_load<real>(r, vo + (dx + 2) * (int)sizeof(real), (dy + 2) * rowb);
+  }
+  __device__ real u(int dx, int dy) const { return ld(ru, dx, dy); }
+  __device__ real v(int dx, int dy) const { return ld(rv, dx, dy); }
+  __device__ real us(int dx, int dy) const { return ld(rus, dx, dy); }
+  __device__ real vs(int dx, int dy) const { return ld(rvs, dx, dy); }
+  __device__ real T(int dx, int dy) const { return ld(rT, dx, dy); }
+  __device__ real p(int dx, int dy) const { return ld(rp, dx, dy); }
+};
+
+// face value of the convection scheme (Eq 76's QUICK, or central / upwind),
+// both upwind candidates evaluated and one selected
+template <typename real, int CONV>
+__device__ __forceinline__ real face_value(real uf, real ll, real l, real r, real rr) {
+  if constexpr (CONV == 1) {
+    return real(0.5) * (l + r);
+  } else if constexpr (CONV == 2) {
+    return uf >= real(0) ? l : r;
+  } else {
+    const real up = fmad(real(0.75), l, fmad(real(0.375), r, real(-0.125) * ll));
+    const real dn = fmad(real(0.75), r, fmad(real(0.375), l, real(-0.125) * rr));
+    return uf >= real(0) ? up : dn;
+  }
+}
+
 // 2. momentum: u* on x-faces c0+1 .. nx-1, v* on y-faces 1 .. ny-1 of the
-//    FV cells; wall and prescribed faces copied.
-template <typename real, bool FAST>
-__device__ __forceinline__ void momentum_at(const SplitArgs<real>& a, int x, int j) {
-  // FAST: the block's stencils stay inside the stored FV zone (no wall
-  // mirror or ghost rule applies), so the fields are indexed directly
-#define UA(arr, xx, jj) (FAST ? (arr)[(jj) * a.pF + fidx(a, xx)] : U_at(a, arr, xx, jj))
-#define VA(arr, xx, jj) (FAST ? (arr)[(jj) * a.pF + fidx(a, xx)] : V_at(a, arr, xx, jj))
-#define TA(arr, xx, jj) (FAST ? (arr)[(jj) * a.pF + fidx(a, xx)] : T_at(a, arr, xx, jj))
-  const int conv = a.conv;
+//    FV cells; wall and prescribed faces copied.  INNER: no such face in
+//    the block.
+template <typename real, int CONV, bool INNER, typename Acc>
+__device__ __forceinline__ void momentum_at(const SplitArgs<real>& a, const Acc& F, int x,
+                                            int j) {
   const real nu = a.nu;
+  const int o = j * a.pF + fidx(a, x);
   // ---- u* at face (x, j)
-  if (j < a.ny) {
+  if (INNER || j < a.ny) {
     real out;
-    if (x == a.c0) {
-      out = a.u[j * a.pF + fidx(a, x)];  // prescribed inflow face
-    } else if (x == a.nx) {
-      out = real(0);                     // east wall
+    if (!INNER && x == a.c0) {
+      out = a.u[o];       // prescribed inflow face
+    } else if (!INNER && x == a.nx) {
+      out = real(0);      // east wall
     } else {
       real Fc[2], Gc[2];
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
-        const int m = x - 1 + k;
-        const real ub = real(0.5) * (UA(a.u, m, j) + UA(a.u, m + 1, j));
-        const real uh = quick(conv, ub, UA(a.u, m - 1, j), UA(a.u, m, j),
-                              UA(a.u, m + 1, j), UA(a.u, m + 2, j));
+        const int dm = k - 1;  // cell m = x - 1 + k
+        const real ub = real(0.5) * (F.u(dm, 0) + F.u(dm + 1, 0));
+        const real uh = face_value<real, CONV>(ub, F.u(dm - 1, 0), F.u(dm, 0), F.u(dm + 1, 0),
+                                               F.u(dm + 2, 0));
         Fc[k] = ub * uh;
-        const int jf = j + k;
-        const real vb = real(0.5) * (VA(a.v, x - 1, jf) + VA(a.v, x, jf));
-        const real uh2 = quick(conv, vb, UA(a.u, x, jf - 2), UA(a.u, x, jf - 1),
-                               UA(a.u, x, jf), UA(a.u, x, jf + 1));
+        const real vb = real(0.5) * (F.v(-1, k) + F.v(0, k));  // y-face j + k
+        const real uh2 = face_value<real, CONV>(vb, F.u(0, k - 2), F.u(0, k - 1), F.u(0, k),
+                                                F.u(0, k + 1));
         Gc[k] = vb * uh2;
       }
-      const real uc = UA(a.u, x, j);
-      const real lap = UA(a.u, x + 1, j) + UA(a.u, x - 1, j) + UA(a.u, x, j + 1) +
-                       UA(a.u, x, j - 1) - real(4) * uc;
-      const real dp = P_at(a, x, j) - P_at(a, x - 1, j);
+      const real uc = F.u(0, 0);
+      const real lap = F.u(1, 0) + F.u(-1, 0) + F.u(0, 1) + F.u(0, -1) - real(4) * uc;
+      const real dp = F.p(0, 0) - F.p(-1, 0);
       out = uc - (Fc[1] - Fc[0]) - (Gc[1] - Gc[0]) + nu * lap - dp;
     }
-    a.us[j * a.pF + fidx(a, x)] = out;
+    a.us[o] = out;
   }
-  // ---- v* at face (x, jf = j) for cells x < nx
-  if (x < a.nx) {
-    const int jf = j;
+  // ---- v* at face (x, j) for cells x < nx
+  if (INNER || x < a.nx) {
     real out = real(0);
-    if (jf > 0 && jf < a.ny) {
+    if (INNER || (j > 0 && j < a.ny)) {
       real Fc[2], Gc[2];
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
-        const int m = jf - 1 + k;
-        const real vb = real(0.5) * (VA(a.v, x, m) + VA(a.v, x, m + 1));
-        const real vh = quick(conv, vb, VA(a.v, x, m - 1), VA(a.v, x, m),
-                              VA(a.v, x, m + 1), VA(a.v, x, m + 2));
+        const int dm = k - 1;  // cell row m = j - 1 + k
+        const real vb = real(0.5) * (F.v(0, dm) + F.v(0, dm + 1));
+        const real vh = face_value<real, CONV>(vb, F.v(0, dm - 1), F.v(0, dm), F.v(0, dm + 1),
+                                               F.v(0, dm + 2));
         Fc[k] = vb * vh;
-        const int xc = x + k;
-        const real ub = real(0.5) * (UA(a.u, xc, jf - 1) + UA(a.u, xc, jf));
-        const real vh2 = quick(conv, ub, VA(a.v, xc - 2, jf), VA(a.v, xc - 1, jf),
-                               VA(a.v, xc, jf), VA(a.v, xc + 1, jf));
+        const real ub = real(0.5) * (F.u(k, -1) + F.u(k, 0));  // x-face x + k
+        const real vh2 = face_value<real, CONV>(ub, F.v(k - 2, 0), F.v(k - 1, 0), F.v(k, 0),
+                                                F.v(k + 1, 0));
         Gc[k] = ub * vh2;
       }
-      const real vc = VA(a.v, x, jf);
-      const real lap = VA(a.v, x + 1, jf) + VA(a.v, x - 1, jf) +
-                       VA(a.v, x, jf + 1) + VA(a.v, x, jf - 1) - real(4) * vc;
-      const real dp = P_at(a, x, jf) - P_at(a, x, jf - 1);
-      const real Tf = real(0.5) * (TA(a.T, x, jf - 1) + TA(a.T, x, jf));
+      const real vc = F.v(0, 0);
+      const real lap = F.v(1, 0) + F.v(-1, 0) + F.v(0, 1) + F.v(0, -1) - real(4) * vc;
+      const real dp = F.p(0, 0) - F.p(0, -1);
+      const real Tf = real(0.5) * (F.T(0, -1) + F.T(0, 0));
       out = vc - (Gc[1] - Gc[0]) - (Fc[1] - Fc[0]) + nu * lap - dp + a.gbeta * (Tf - a.Tref);
     }
-    a.vs[jf * a.pF + fidx(a, x)] = out;
+    a.vs[o] = out;
   }
-#undef UA
-#undef VA
-#undef TA
 }
 
-template <typename real>
+template <typename real, int CONV>
 __global__ __launch_bounds__(256) void k_dd_momentum(SplitArgs<real> a) {
   const int x0 = a.c0 + blockIdx.x * blockDim.x;
   const int x = x0 + threadIdx.x;  // c0 .. nx
   const int j = blockIdx.y;        // 0 .. ny
   if (x > a.nx) return;
-  // u* reaches u, v two faces away and p, T one cell away in x and y
-  const bool fast = x0 > a.c0 && x0 + (int)blockDim.x + 2 < a.nx && j >= 2 && j + 3 <= a.ny - 1;
-  if (fast) momentum_at<real, true>(a, x, j);
-  else momentum_at<real, false>(a, x, j);
+  // u* reaches u, v two faces away and p, T one cell away in x and y:
+  // the wave's faces are inner when they are clear of the inflow face, the
+  // east wall's mirror and the walls' ghost rows (uniform per wave)
+  const int xw = x0 + (int)(threadIdx.x & ~63u);
+  const bool inner = xw > a.c0 && xw + 63 <= a.nx - 3 && j >= 2 && j <= a.ny - 3;
+  if (inner) momentum_at<real, CONV, true>(a, DirAcc<real>(a, x, j), x, j);
+  else momentum_at<real, CONV, false>(a, GenAcc<real>{a, x, j}, x, j);
 }
 
 // 3. pressure (artificial compressibility, beta = c_s^2) and energy on u*
-template <typename real, bool FAST>
-__device__ __forceinline__ void press_energy_at(const SplitArgs<real>& a, int x, int j) {
-#define UA(arr, xx, jj) (FAST ? (arr)[(jj) * a.pF + fidx(a, xx)] : U_at(a, arr, xx, jj))
-#define VA(arr, xx, jj) (FAST ? (arr)[(jj) * a.pF + fidx(a, xx)] : V_at(a, arr, xx, jj))
-#define TA(arr, xx, jj) (FAST ? (arr)[(jj) * a.pF + fidx(a, xx)] : T_at(a, arr, xx, jj))
-  const int conv = a.conv;
+template <typename real, int CONV, bool INNER, typename Acc>
+__device__ __forceinline__ void press_energy_at(const SplitArgs<real>& a, const Acc& F, int x,
+                                                int j) {
   const real al = a.alpha;
-  const real ue = x == a.nx - 1 ? real(0) : UA(a.us, x + 1, j);
-  const real uw = UA(a.us, x, j);
-  const real vn = VA(a.vs, x, j + 1), vsd = VA(a.vs, x, j);
+  const real ue = (!INNER && x == a.nx - 1) ? real(0) : F.us(1, 0);
+  const real uw = F.us(0, 0);
+  const real vn = F.vs(0, 1), vsd = F.vs(0, 0);
   const int o = j * a.pF + fidx(a, x);
   a.p[o] = a.p[o] - real(1) / real(3) * ((ue - uw) + (vn - vsd));
-  real F[2], G[2];
+  const real Tc = a.T[o];
+  real Fx[2], Gy[2];
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
-    const int xf = x + k;
-    if (xf == a.nx) {
-      F[k] = a.tfix[1] ? real(-2) * al * (a.Tw[1] - a.T[o]) : real(0);
+    if (!INNER && x + k == a.nx) {
+      Fx[k] = a.tfix[1] ? real(-2) * al * (a.Tw[1] - Tc) : real(0);
     } else {
-      const real uf = UA(a.us, xf, j);
-      const real th = quick(conv, uf, TA(a.T, xf - 2, j), TA(a.T, xf - 1, j),
-                            TA(a.T, xf, j), TA(a.T, xf + 1, j));
-      F[k] = fmad(uf, th, -al * (TA(a.T, xf, j) - TA(a.T, xf - 1, j)));
+      const real uf = F.us(k, 0);  // x-face x + k
+      const real th = face_value<real, CONV>(uf, F.T(k - 2, 0), F.T(k - 1, 0), F.T(k, 0),
+                                             F.T(k + 1, 0));
+      Fx[k] = fmad(uf, th, -al * (F.T(k, 0) - F.T(k - 1, 0)));
     }
     const int jf = j + k;
-    if (jf == 0) {
-      G[k] = a.tfix[2] ? real(-2) * al * (a.T[o] - a.Tw[2]) : real(0);
-    } else if (jf == a.ny) {
-      G[k] = a.tfix[3] ? real(-2) * al * (a.Tw[3] - a.T[o]) : real(0);
+    if (!INNER && jf == 0) {
+      Gy[k] = a.tfix[2] ? real(-2) * al * (Tc - a.Tw[2]) : real(0);
+    } else if (!INNER && jf == a.ny) {
+      Gy[k] = a.tfix[3] ? real(-2) * al * (a.Tw[3] - Tc) : real(0);
     } else {
-      const real vf = VA(a.vs, x, jf);
-      const real th = quick(conv, vf, TA(a.T, x, jf - 2), TA(a.T, x, jf - 1),
-                            TA(a.T, x, jf), TA(a.T, x, jf + 1));
-      G[k] = fmad(vf, th, -al * (TA(a.T, x, jf) - TA(a.T, x, jf - 1)));
+      const real vf = F.vs(0, k);  // y-face j + k
+      const real th = face_value<real, CONV>(vf, F.T(0, k - 2), F.T(0, k - 1), F.T(0, k),
+                                             F.T(0, k + 1));
+      Gy[k] = fmad(vf, th, -al * (F.T(0, k) - F.T(0, k - 1)));
     }
   }
-  a.Tn[o] = a.T[o] - (F[1] - F[0]) - (G[1] - G[0]);
-#undef UA
-#undef VA
-#undef TA
+  a.Tn[o] = Tc - (Fx[1] - Fx[0]) - (Gy[1] - Gy[0]);
 }
 
-template <typename real>
+template <typename real, int CONV>
 __global__ __launch_bounds__(256) void k_dd_press_energy(SplitArgs<real> a) {
   const int x0 = a.c0 + blockIdx.x * blockDim.x;
   const int x = x0 + threadIdx.x;
   const int j = blockIdx.y;
   if (x >= a.nx) return;
-  // T reaches two cells away in x and y, u*, v* one face
-  const bool fast = x0 + (int)blockDim.x + 2 < a.nx && j >= 2 && j + 3 <= a.ny - 1;
-  if (fast) press_energy_at<real, true>(a, x, j);
-  else press_energy_at<real, false>(a, x, j);
+  // T reaches two cells away in x and y, u*, v* one face (uniform per wave)
+  const int xw = x0 + (int)(threadIdx.x & ~63u);
+  const bool inner = xw + 63 <= a.nx - 3 && j >= 2 && j <= a.ny - 3;
+  if (inner) press_energy_at<real, CONV, true>(a, DirAcc<real>(a, x, j), x, j);
+  else press_energy_at<real, CONV, false>(a, GenAcc<real>{a, x, j}, x, j);
 }
 
 // 4. p_bar: mean new FV pressure over the shared columns; per-block sums
@@ -666,12 +725,23 @@ template <typename real>
 hipError_t launch_split_step(const SplitGeom& G, const SplitPtrs<real>& P, const SplitParams& S,
                              int cur, int mom_all, hipStream_t s) {
   const SplitArgs<real> a = make_args<real>(G, P, S, cur, mom_all);
+  // interior FV blocks address their arrays with 32-bit byte offsets
+  if ((size_t)(G.ny + 1) * G.pF * sizeof(real) >= ((size_t)1 << 31)) return hipErrorInvalidValue;
   const int nfc = G.nx - G.c0 + 1;  // FV columns c0 .. nx
   const int ngb = (G.ny + 1 + kGhostBlock - 1) / kGhostBlock;  // rows and y-faces 0 .. ny
   hipLaunchKernelGGL(k_dd_ghost_rows<real>, dim3(ngb), dim3(kGhostBlock), 0, s, a);
   hipLaunchKernelGGL(k_dd_ghost_fold<real>, dim3(1), dim3(1024), 0, s, a, ngb);
-  hipLaunchKernelGGL(k_dd_momentum<real>, dim3((nfc + 255) / 256, G.ny + 1), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_dd_press_energy<real>, dim3((nfc + 255) / 256, G.ny), dim3(256), 0, s, a);
+  const dim3 gm((nfc + 255) / 256, G.ny + 1), ge((nfc + 255) / 256, G.ny);
+  if (S.conv == 1) {
+    hipLaunchKernelGGL((k_dd_momentum<real, 1>), gm, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_dd_press_energy<real, 1>), ge, dim3(256), 0, s, a);
+  } else if (S.conv == 2) {
+    hipLaunchKernelGGL((k_dd_momentum<real, 2>), gm, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_dd_press_energy<real, 2>), ge, dim3(256), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_dd_momentum<real, 0>), gm, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_dd_press_energy<real, 0>), ge, dim3(256), 0, s, a);
+  }
   const int npb = (G.ny + kGhostBlock - 1) / kGhostBlock;
   hipLaunchKernelGGL(k_dd_pbar_rows<real>, dim3(npb), dim3(kGhostBlock), 0, s, a);
   hipLaunchKernelGGL(k_dd_pbar_fold<real>, dim3(1), dim3(64), 0, s, a, npb);

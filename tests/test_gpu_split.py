@@ -71,6 +71,25 @@ def test_split_parity_ragged_fp64(lf, ctx):
     check(g, o, 1e-10)
 
 
+@pytest.mark.parametrize("conv,prec,tol", [(0, "f64", 1e-10), (1, "f64", 1e-10), (2, "f64", 1e-10),
+                                           (0, "f32", 1e-4)])
+def test_split_parity_inner_waves(lf, ctx, conv, prec, tol):
+    """A FV zone wide enough for the interior (direct-addressed) path: 201 FV
+    columns, of which the waves starting at columns 263 and 327 take it, with
+    ragged rows; each convection scheme against the oracle."""
+    oracle.set_threads(8)
+    nx, ny = 400, 70
+    T0 = perturbation(nx, ny, 33, amp=0.1)
+    g = lf.Case(ctx, nx, ny, prec, mode=lf.MODE_SPLIT, iface=0)
+    g.set_physics(1e5, 0.71, conv=conv).set_cavity_walls().init(T0)
+    o = oracle.DDCase(nx, ny, oracle.SPLIT, 0).set_physics(1e5, 0.71).set_cavity_walls()
+    o.set_lattice(o.params["nu"], o.params["alpha"], o.params["gbeta"], 0.0, conv=conv)
+    o.init(T0)
+    g.step(400)
+    o.step(400)
+    check(g, o, tol)
+
+
 def test_split_128_fp32_2000_steps(lf, ctx):
     oracle.set_threads(8)
     n = 128
