@@ -416,8 +416,16 @@ __device__ __forceinline__ void bstore<double>(double v, __amdgpu_buffer_rsrc_t 
 // east face of its cell (the west face is the east face of the lane to the
 // left) and the north face (the south face is the previous row's north
 // face), and the next row's populations are requested one row ahead.
-template <typename real, int CONV>
+//
+// DIR is the march direction: +1 up from j0, -1 down from j1 - 1.  Bands
+// alternate, so the two waves on either side of a band boundary pull its
+// shared rows at the same time (both at their start or both at their end)
+// and the second pull hits in L2.  A node's arithmetic does not depend on
+// the direction: the face between rows r and r + 1 is always evaluated
+// from (v_r, v_r+1, T_r-1 .. T_r+2) in that order.
+template <typename real, int CONV, int DIR>
 __device__ void march_interior(const StepArgs<real>& a, int lane, int i, int j0, int j1) {
+  static_assert(DIR == 1 || DIR == -1, "march direction");
   constexpr int es = sizeof(real);
   const int P = a.pitch;
   const bool act = lane >= 1 && lane <= kOut;
@@ -441,34 +449,42 @@ __device__ void march_interior(const StepArgs<real>& a, int lane, int i, int j0,
     for (int q = 0; q < 9; ++q) f[q] = bload<real>(rf, vo, sq[q]);
   };
   auto T_row = [&](int r) { return bload<real>(rT, (r * P + i) * es, 0); };
+  // first output row; rows "behind" it are r - DIR, rows "ahead" r + DIR
+  const int js = DIR > 0 ? j0 : j1 - 1;
+  auto inside = [&](int r) { return DIR > 0 ? r < j1 : r >= j0; };
+  // rows whose populations are pulled: the band and one row beyond each end
+  auto pulled = [&](int r) { return DIR > 0 ? r <= j1 : r >= j0 - 1; };
 
-  // rows j0-1 .. j0+2 requested up front; row j+3 is requested while row j
+  // rows js-D .. js+2D requested up front; row j+3D is requested while row j
   // is computed (two rows ahead).  Four arrays rotate by unrolling.
   real A[9], B[9], C[9], D[9];
   real dr_c, ux_c, uy_c, uy_p, d_unused, u_unused;
-  load_row(j0 - 1, D);
-  load_row(j0, A);
-  load_row(j0 + 1, B);
-  if (j0 + 2 <= j1) load_row(j0 + 2, C);
-  const real tm2 = T_row(j0 - 2);
-  real t1 = T_row(j0 - 1), t2 = T_row(j0), t3 = T_row(j0 + 1), t4 = T_row(j0 + 2);
-  real t5 = T_row(j0 + 3 < a.ny ? j0 + 3 : j0 + 2);
+  load_row(js - DIR, D);
+  load_row(js, A);
+  load_row(js + DIR, B);
+  if (pulled(js + 2 * DIR)) load_row(js + 2 * DIR, C);
+  const real tm2 = T_row(js - 2 * DIR);
+  real t1 = T_row(js - DIR), t2 = T_row(js), t3 = T_row(js + DIR), t4 = T_row(js + 2 * DIR);
+  const int r5 = js + 3 * DIR;
+  real t5 = T_row((DIR > 0 ? r5 < a.ny : r5 >= 0) ? r5 : js + 2 * DIR);
   // the column beyond the halo lanes and the low words, one row ahead
   auto tx_row = [&](int r) { return bload<real>(rT, (r * P + i) * es + xoff, 0); };
   auto lo_row = [&](int r) { return bload<real>(rL, (r * P + i) * es, 0); };
-  real txa = tx_row(j0), loa = lo_row(j0);
+  real txa = tx_row(js), loa = lo_row(js);
   moments(D, d_unused, u_unused, uy_p);
   moments(A, dr_c, ux_c, uy_c);
-  real Fs = face_flux<real, CONV>(al, uy_p, uy_c, tm2, t1, t2, t3);
+  // the face behind the first row
+  real Fb = DIR > 0 ? face_flux<real, CONV>(al, uy_p, uy_c, tm2, t1, t2, t3)
+                    : face_flux<real, CONV>(al, uy_c, uy_p, t3, t2, t1, tm2);
 
   auto row = [&](int j, const real (&fc)[9], const real (&fn)[9], real (&fl)[9]) {
-    if (j + 3 <= j1) load_row(j + 3, fl);  // prefetch two rows ahead
+    if (pulled(j + 3 * DIR)) load_row(j + 3 * DIR, fl);  // two rows ahead
     real dr_n, ux_n, uy_n;
     moments(fn, dr_n, ux_n, uy_n);
     const real tx = txa, lo = loa;
-    if (j + 1 < j1) {
-      txa = tx_row(j + 1);
-      loa = lo_row(j + 1);
+    if (inside(j + DIR)) {
+      txa = tx_row(j + DIR);
+      loa = lo_row(j + DIR);
     }
     real tW1 = __shfl_up(t2, 1, 64);
     const real tE1 = __shfl_down(t2, 1, 64);
@@ -478,12 +494,15 @@ __device__ void march_interior(const StepArgs<real>& a, int lane, int i, int j0,
     if (lane == kOut) tE2 = tx;
     const real Fe = face_flux<real, CONV>(al, ux_c, uE, tW1, t2, tE1, tE2);
     const real Fw = __shfl_up(Fe, 1, 64);
-    const real Fn = face_flux<real, CONV>(al, uy_c, uy_n, t1, t2, t3, t4);
+    // the face ahead; north minus south either way
+    const real Fa = DIR > 0 ? face_flux<real, CONV>(al, uy_c, uy_n, t1, t2, t3, t4)
+                            : face_flux<real, CONV>(al, uy_n, uy_c, t4, t3, t2, t1);
+    const real dFy = DIR > 0 ? Fa - Fb : Fb - Fa;
     real Tnew, Tlo = real(0);
     if (a.Tlo_in) {
-      t_update(t2, lo, -(Fe - Fw) - (Fn - Fs), Tnew, Tlo);
+      t_update(t2, lo, -(Fe - Fw) - dFy, Tnew, Tlo);
     } else {
-      Tnew = t2 - (Fe - Fw) - (Fn - Fs);
+      Tnew = t2 - (Fe - Fw) - dFy;
     }
     if (act) {
       real fo[9];
@@ -500,7 +519,7 @@ __device__ void march_interior(const StepArgs<real>& a, int lane, int i, int j0,
         a.mom[2 * a.plane + o] = uy_c;
       }
     }
-    Fs = Fn;
+    Fb = Fa;
     uy_p = uy_c;
     dr_c = dr_n;
     ux_c = ux_n;
@@ -509,16 +528,17 @@ __device__ void march_interior(const StepArgs<real>& a, int lane, int i, int j0,
     t2 = t3;
     t3 = t4;
     t4 = t5;
-    if (j + 4 < a.ny) t5 = T_row(j + 4);
+    const int r4 = j + 4 * DIR;
+    if (DIR > 0 ? r4 < a.ny : r4 >= 0) t5 = T_row(r4);
   };
-  for (int j = j0; j < j1; j += 4) {
+  for (int j = js; inside(j); j += 4 * DIR) {
     row(j, A, B, D);
-    if (j + 1 >= j1) break;
-    row(j + 1, B, C, A);
-    if (j + 2 >= j1) break;
-    row(j + 2, C, D, B);
-    if (j + 3 >= j1) break;
-    row(j + 3, D, A, C);
+    if (!inside(j + DIR)) break;
+    row(j + DIR, B, C, A);
+    if (!inside(j + 2 * DIR)) break;
+    row(j + 2 * DIR, C, D, B);
+    if (!inside(j + 3 * DIR)) break;
+    row(j + 3 * DIR, D, A, C);
   }
 }
 
@@ -531,8 +551,9 @@ void k_hybrid_step(StepArgs<real> a) {
   const int nb = gridDim.x, b = blockIdx.x;
   const int per = nb / 8, rem = nb % 8, x = b % 8;
   const int lb = x * per + (x < rem ? x : rem) + b / 8;
-  const int wave = lb * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (wave >= a.nwaves) return;  // uniform per wave
+  // uniform per wave: held in an SGPR, so are the strip, band and row bounds
+  const int wave = __builtin_amdgcn_readfirstlane(lb * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  if (wave >= a.nwaves) return;
   const int lane = threadIdx.x & 63;
   const int strip = wave % a.nstrips;
   const int bnd = wave / a.nstrips;
@@ -541,8 +562,12 @@ void k_hybrid_step(StepArgs<real> a) {
   const int j0 = bnd * a.band;
   const int j1 = min(j0 + a.band, a.ny);
   const bool interior = c0 - 1 >= 1 && c0 + kOut <= a.nx - 2 && j0 - 1 >= 2 && j1 <= a.ny - 2;
-  if (interior) march_interior<real, CONV>(a, lane, i, j0, j1);
-  else march_general_any<real, CONV>(a, lane, i, j0, j1);
+  if (interior) {
+    if (bnd & 1) march_interior<real, CONV, -1>(a, lane, i, j0, j1);
+    else march_interior<real, CONV, 1>(a, lane, i, j0, j1);
+  } else {
+    march_general_any<real, CONV>(a, lane, i, j0, j1);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -612,8 +637,14 @@ void k_batch_step(const TileDesc* __restrict__ tiles, const int* __restrict__ nt
   const int i = c0 + lane - 1;
   const int j0 = t.j0, j1 = t.j1;
   const bool interior = c0 - 1 >= 1 && c0 + kOut <= a.nx - 2 && j0 - 1 >= 2 && j1 <= a.ny - 2;
-  if (interior) march_interior<real, CONV>(a, lane, i, j0, j1);
-  else march_general<real, CONV, false, false>(a, lane, i, j0, j1);  // batches: no periodic sides
+  // march direction alternates with the band index (a cavity's last, shorter
+  // band may share its neighbour's direction; only cache reuse depends on it)
+  if (interior) {
+    if ((j0 / (j1 - j0)) & 1) march_interior<real, CONV, -1>(a, lane, i, j0, j1);
+    else march_interior<real, CONV, 1>(a, lane, i, j0, j1);
+  } else {
+    march_general<real, CONV, false, false>(a, lane, i, j0, j1);  // batches: no periodic sides
+  }
 }
 
 // Batched residual, pass 1: one block per (cavity, row range); six FP64
