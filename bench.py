@@ -258,6 +258,22 @@ def main():
                               "frac_of_8TBs": round(ach / HBM_PEAK_GBS, 4),
                               "U_char": sp.params()["U_char"]}
         del sp
+        # the single methods of the same comparison on the whole cavity
+        # (algorithmic bytes: FV 32 B/cell, LBM 112 B/node)
+        for key, mode, bpn, what in (("pure_fv_point", lf.MODE_PURE_FV, 32.0, "FV only"),
+                                     ("pure_lbm_point", lf.MODE_PURE_LBM, 112.0,
+                                      "LBM only (D2Q9 + D2Q5)")):
+            pc = lf.Case(ctx, m, m, "f32", mode=mode).set_physics(1e6, 0.71)
+            pc.set_cavity_walls().init(perturbation(m, m, SEED_C2))
+            pc.step(10)
+            a_ms, _, _ = pc.profile_steps(200)
+            ach = bpn * m * m / (a_ms * 1e-3) / 1e9
+            out[key] = {"workload": f"{m}x{m} cavity, {what}, Ra 1e6, Pr 0.71, FP32",
+                        "ms_per_step": round(a_ms, 5),
+                        "mlups": round(m * m / (a_ms * 1e-3) / 1e6, 1),
+                        f"achieved_GBs_at_{int(bpn)}B": round(ach, 1),
+                        "frac_of_8TBs": round(ach / HBM_PEAK_GBS, 4)}
+            del pc
 
     if args.batch_point:
         from synth_inputs import cavity_sweep

@@ -14,6 +14,10 @@
  *     through non-equilibrium extrapolation (Eq 60, Eq 94-95) or the
  *     finite-difference velocity-gradient reconstruction (Eq 70-72) with the
  *     density transfer of Eq 91-93.
+ *   - The two single methods of the Sec. 4.2 comparison on the whole cavity,
+ *     with the zone kernels of Mode DD: LF_MODE_PURE_FV (staggered FVM,
+ *     explicit momentum with artificial compressibility, Eq 74-76) and
+ *     LF_MODE_PURE_LBM (D2Q9 flow + D2Q5 heat, Eq 19-23).
  *
  * Conventions (all entry points):
  *   - Every call returns lf_status; LF_OK is 0.  On failure
@@ -62,7 +66,7 @@ typedef enum {
 } lf_status;
 
 enum { LF_F32 = 0, LF_F64 = 1 };
-enum { LF_MODE_HYBRID = 0, LF_MODE_SPLIT = 1 };
+enum { LF_MODE_HYBRID = 0, LF_MODE_SPLIT = 1, LF_MODE_PURE_FV = 2, LF_MODE_PURE_LBM = 3 };
 enum { LF_IFACE_NEQ_EXTRAP = 0, LF_IFACE_FD_GRADIENT = 1 };
 enum { LF_CONV_QUICK = 0, LF_CONV_CENTRAL = 1, LF_CONV_UPWIND = 2 };
 enum { LF_WALL_NOSLIP = 0, LF_WALL_PERIODIC = 1 };
@@ -80,7 +84,9 @@ typedef struct lf_case lf_case;
 typedef struct {
   int nx, ny;
   int precision; /* LF_F32 or LF_F64                                        */
-  int mode;      /* LF_MODE_HYBRID or LF_MODE_SPLIT                         */
+  int mode;      /* LF_MODE_HYBRID, LF_MODE_SPLIT, LF_MODE_PURE_FV or
+                    LF_MODE_PURE_LBM (the last three: walls at rest,
+                    no periodic sides, start from rest)                    */
   int split_col; /* Mode DD: first FV cell is split_col - 1; 0 => nx/2      */
   int overlap;   /* Mode DD: shared columns; 0 => 3 (the only value)        */
   int iface;     /* Mode DD: LF_IFACE_NEQ_EXTRAP or LF_IFACE_FD_GRADIENT    */

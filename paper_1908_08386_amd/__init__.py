@@ -38,7 +38,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 LF_OK, LF_EINVAL, LF_ENOMEM, LF_EWORKSPACE, LF_EDEVICE, LF_EUNSTABLE, LF_EDIVERGED, \
     LF_ENOTCONV, LF_ESTATE, LF_ENOTIMPL = range(10)
 F32, F64 = 0, 1
-MODE_HYBRID, MODE_SPLIT = 0, 1
+MODE_HYBRID, MODE_SPLIT, MODE_PURE_FV, MODE_PURE_LBM = 0, 1, 2, 3
 IFACE_NEQ_EXTRAP, IFACE_FD_GRADIENT = 0, 1
 CONV_QUICK, CONV_CENTRAL, CONV_UPWIND = 0, 1, 2
 WALL_NOSLIP, WALL_PERIODIC = 0, 1
@@ -245,7 +245,8 @@ class Context:
 
 
 class Case:
-    """One cavity (Mode H).  Fields are numpy arrays of shape (ny, nx)."""
+    """One cavity: Mode H, the split LBM|FV mode, or one of the single methods
+    (MODE_PURE_FV, MODE_PURE_LBM).  Fields are numpy arrays of shape (ny, nx)."""
 
     def __init__(self, ctx: Context, nx: int, ny: int, precision: str = "f32",
                  mode: int = MODE_HYBRID, split_col: int = 0, iface: int = IFACE_NEQ_EXTRAP,

@@ -31,6 +31,10 @@
 //                 then its collision.
 // The LBM zone is 112 B per node (FP32) and the FV zone streams u, v, p, T
 // twice; the interface work is O(ny).
+// The single-method cavities of the Sec. 4.2 comparison run the same zone
+// kernels on the whole box: FV only (momentum + pressure/energy, with the
+// west wall's mirror and ghost rules) or LBM only (k_dd_lbm with an east
+// wall), without the interface launches.
 #include "lf_internal.h"
 
 #pragma clang fp contract(off)
@@ -111,6 +115,8 @@ struct SplitArgs {
   // per-block sums of the ghost kernel
   double* __restrict__ iface;
   int nx, ny, s, c0, ib;
+  int west_wall;  // FV zone closed by a wall at x = 0 (FV-only cavity)
+  int east_wall;  // LBM zone closed by a wall at x = nx (LBM-only cavity)
   int conv, kind, mom_all;
   real omega, omegaT, tau, nu, alpha, gbeta, Tref;
   int tfix[4];
@@ -128,6 +134,7 @@ __device__ __forceinline__ real U_at(const SplitArgs<real>& a, const real* u, in
   if (j < 0) { j = -1 - j; sg = -sg; }
   else if (j >= a.ny) { j = 2 * a.ny - 1 - j; sg = -sg; }
   if (x > a.nx) { x = 2 * a.nx - x; sg = -sg; }
+  else if (x < 0 && a.west_wall) { x = -x; sg = -sg; }
   return sg * u[j * a.pF + fidx(a, x)];
 }
 template <typename real>
@@ -136,6 +143,7 @@ __device__ __forceinline__ real V_at(const SplitArgs<real>& a, const real* v, in
   if (jf < 0) { jf = -jf; sg = -sg; }
   else if (jf > a.ny) { jf = 2 * a.ny - jf; sg = -sg; }
   if (x >= a.nx) { x = 2 * a.nx - 1 - x; sg = -sg; }
+  else if (x < 0 && a.west_wall) { x = -1 - x; sg = -sg; }
   return sg * v[jf * a.pF + fidx(a, x)];
 }
 template <typename real>
@@ -145,6 +153,9 @@ __device__ __forceinline__ real T_at(const SplitArgs<real>& a, const real* T, in
   if (x >= a.nx) {
     t = T[jj * a.pF + fidx(a, a.nx - 1)];
     if (a.tfix[1]) t = real(2) * a.Tw[1] - t;
+  } else if (x < 0 && a.west_wall) {
+    t = T[jj * a.pF + fidx(a, 0)];
+    if (a.tfix[0]) t = real(2) * a.Tw[0] - t;
   } else {
     t = T[jj * a.pF + fidx(a, x)];
   }
@@ -233,7 +244,7 @@ __global__ __launch_bounds__(1024) void k_dd_ghost_fold(SplitArgs<real> a, int n
 
 // ---- field access relative to a thread's face / cell (x, j) ------------
 // GenAcc applies the wall mirror and ghost rules of U_at, V_at and T_at.
-// DirAcc serves blocks whose stencils stay inside the stored FV zone: all
+// DirAcc serves waves whose stencils stay inside the stored FV zone: all
 // FV arrays share one layout, so a lane keeps one byte offset (row j - 2,
 // column x - 2), the row shift is a wave-uniform SGPR offset and the column
 // shift is folded into the load instruction.
@@ -304,8 +315,9 @@ __device__ __forceinline__ real face_value(real uf, real ll, real l, real r, rea
 }
 
 // 2. momentum: u* on x-faces c0+1 .. nx-1, v* on y-faces 1 .. ny-1 of the
-//    FV cells; wall and prescribed faces copied.  INNER: no such face in
-//    the block.
+//    FV cells; wall and prescribed faces copied (face c0: the inflow face
+//    of the split cavity, or the west wall).  INNER: no such face in the
+//    wave.
 template <typename real, int CONV, bool INNER, typename Acc>
 __device__ __forceinline__ void momentum_at(const SplitArgs<real>& a, const Acc& F, int x,
                                             int j) {
@@ -376,7 +388,8 @@ __global__ __launch_bounds__(256) void k_dd_momentum(SplitArgs<real> a) {
   // the wave's faces are inner when they are clear of the inflow face, the
   // east wall's mirror and the walls' ghost rows (uniform per wave)
   const int xw = x0 + (int)(threadIdx.x & ~63u);
-  const bool inner = xw > a.c0 && xw + 63 <= a.nx - 3 && j >= 2 && j <= a.ny - 3;
+  const bool inner = xw >= a.c0 + (a.west_wall ? 2 : 1) && xw + 63 <= a.nx - 3 && j >= 2 &&
+                     j <= a.ny - 3;
   if (inner) momentum_at<real, CONV, true>(a, DirAcc<real>(a, x, j), x, j);
   else momentum_at<real, CONV, false>(a, GenAcc<real>{a, x, j}, x, j);
 }
@@ -397,6 +410,8 @@ __device__ __forceinline__ void press_energy_at(const SplitArgs<real>& a, const 
   for (int k = 0; k < 2; ++k) {
     if (!INNER && x + k == a.nx) {
       Fx[k] = a.tfix[1] ? real(-2) * al * (a.Tw[1] - Tc) : real(0);
+    } else if (!INNER && a.west_wall && x + k == 0) {
+      Fx[k] = a.tfix[0] ? real(-2) * al * (Tc - a.Tw[0]) : real(0);
     } else {
       const real uf = F.us(k, 0);  // x-face x + k
       const real th = face_value<real, CONV>(uf, F.T(k - 2, 0), F.T(k - 1, 0), F.T(k, 0),
@@ -426,7 +441,8 @@ __global__ __launch_bounds__(256) void k_dd_press_energy(SplitArgs<real> a) {
   if (x >= a.nx) return;
   // T reaches two cells away in x and y, u*, v* one face (uniform per wave)
   const int xw = x0 + (int)(threadIdx.x & ~63u);
-  const bool inner = xw + 63 <= a.nx - 3 && j >= 2 && j <= a.ny - 3;
+  const bool inner = xw >= a.c0 + (a.west_wall ? 2 : 0) && xw + 63 <= a.nx - 3 && j >= 2 &&
+                     j <= a.ny - 3;
   if (inner) press_energy_at<real, CONV, true>(a, DirAcc<real>(a, x, j), x, j);
   else press_energy_at<real, CONV, false>(a, GenAcc<real>{a, x, j}, x, j);
 }
@@ -501,13 +517,14 @@ __global__ __launch_bounds__(256) void k_dd_lbm(SplitArgs<real> a) {
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
     const int sx = i - ex9(q), sy = j - ey9(q);
-    if (sx >= 0 && sy >= 0 && sy < a.ny) f[q] = a.fin[q * PL + sy * pL + sx];
+    if (sx >= 0 && !(a.east_wall && sx >= a.nx) && sy >= 0 && sy < a.ny)
+      f[q] = a.fin[q * PL + sy * pL + sx];
     else f[q] = a.fin[opp9(q) * PL + j * pL + i];  // walls at rest: bounce-back
   }
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
     const int sx = i - ex5(q), sy = j - ey5(q);
-    const int side = sy < 0 ? 2 : sy >= a.ny ? 3 : sx < 0 ? 0 : -1;
+    const int side = sy < 0 ? 2 : sy >= a.ny ? 3 : sx < 0 ? 0 : (a.east_wall && sx >= a.nx) ? 1 : -1;
     if (side < 0) g[q] = a.gin[q * PL + sy * pL + sx];
     else if (a.tfix[side])  // anti-bounce-back: fixed temperature
       g[q] = -a.gin[opp5(q) * PL + j * pL + i] + real(2) * w5<real>(q) * a.Tw[side];
@@ -518,7 +535,7 @@ __global__ __launch_bounds__(256) void k_dd_lbm(SplitArgs<real> a) {
   moments9(f, drho, ux, uy);
   const real T = ((g[0] + g[1]) + (g[2] + g[3])) + g[4];
   const int o = j * pL + i;
-  if (i == a.ib - 1) {  // keep x_f's streamed state for the boundary node
+  if (!a.east_wall && i == a.ib - 1) {  // keep x_f's streamed state for the boundary node
     real* xf = a.xf + j * 18;
 #pragma unroll
     for (int q = 0; q < 9; ++q) xf[q] = f[q];
@@ -655,7 +672,7 @@ __global__ __launch_bounds__(256) void k_dd_init(SplitArgs<real> a, const double
     a.mom[3 * a.planeL + o] = real(t0);
   }
   const int xf = x + a.c0 - 2;  // stored FV column
-  if (xf <= a.nx) {
+  if (a.pF > 0 && xf <= a.nx) {
     const int o = j * a.pF + (xf - (a.c0 - 2));
     real* u = const_cast<real*>(a.u);
     real* v = const_cast<real*>(a.v);
@@ -689,7 +706,7 @@ static SplitArgs<real> make_args(const SplitGeom& G, const SplitPtrs<real>& P, c
   a.xf = P.xf;
   a.pL = G.pL;
   a.planeL = G.pL * G.ny;
-  a.nl = G.ib + 1;
+  a.nl = G.fv_only ? 0 : G.lbm_only ? G.nx : G.ib + 1;
   a.u = P.u[cur];
   a.v = P.v[cur];
   a.T = P.T[cur];
@@ -704,6 +721,8 @@ static SplitArgs<real> make_args(const SplitGeom& G, const SplitPtrs<real>& P, c
   a.s = G.s;
   a.c0 = G.c0;
   a.ib = G.ib;
+  a.west_wall = G.fv_only;
+  a.east_wall = G.lbm_only;
   a.conv = S.conv;
   a.kind = S.kind;
   a.mom_all = mom_all;
@@ -728,10 +747,18 @@ hipError_t launch_split_step(const SplitGeom& G, const SplitPtrs<real>& P, const
   // interior FV blocks address their arrays with 32-bit byte offsets
   if ((size_t)(G.ny + 1) * G.pF * sizeof(real) >= ((size_t)1 << 31)) return hipErrorInvalidValue;
   const int nfc = G.nx - G.c0 + 1;  // FV columns c0 .. nx
-  const int ngb = (G.ny + 1 + kGhostBlock - 1) / kGhostBlock;  // rows and y-faces 0 .. ny
-  hipLaunchKernelGGL(k_dd_ghost_rows<real>, dim3(ngb), dim3(kGhostBlock), 0, s, a);
-  hipLaunchKernelGGL(k_dd_ghost_fold<real>, dim3(1), dim3(1024), 0, s, a, ngb);
   const dim3 gm((nfc + 255) / 256, G.ny + 1), ge((nfc + 255) / 256, G.ny);
+  const dim3 gl((a.nl + 63) / 64, (G.ny + 3) / 4);
+  if (G.lbm_only) {  // one zone kernel per step
+    hipLaunchKernelGGL(k_dd_lbm<real>, gl, dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+  const bool split = !G.fv_only;
+  const int ngb = (G.ny + 1 + kGhostBlock - 1) / kGhostBlock;  // rows and y-faces 0 .. ny
+  if (split) {
+    hipLaunchKernelGGL(k_dd_ghost_rows<real>, dim3(ngb), dim3(kGhostBlock), 0, s, a);
+    hipLaunchKernelGGL(k_dd_ghost_fold<real>, dim3(1), dim3(1024), 0, s, a, ngb);
+  }
   if (S.conv == 1) {
     hipLaunchKernelGGL((k_dd_momentum<real, 1>), gm, dim3(256), 0, s, a);
     hipLaunchKernelGGL((k_dd_press_energy<real, 1>), ge, dim3(256), 0, s, a);
@@ -742,11 +769,13 @@ hipError_t launch_split_step(const SplitGeom& G, const SplitPtrs<real>& P, const
     hipLaunchKernelGGL((k_dd_momentum<real, 0>), gm, dim3(256), 0, s, a);
     hipLaunchKernelGGL((k_dd_press_energy<real, 0>), ge, dim3(256), 0, s, a);
   }
-  const int npb = (G.ny + kGhostBlock - 1) / kGhostBlock;
-  hipLaunchKernelGGL(k_dd_pbar_rows<real>, dim3(npb), dim3(kGhostBlock), 0, s, a);
-  hipLaunchKernelGGL(k_dd_pbar_fold<real>, dim3(1), dim3(64), 0, s, a, npb);
-  hipLaunchKernelGGL(k_dd_lbm<real>, dim3((G.ib + 63) / 64, (G.ny + 3) / 4), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_dd_xb<real>, dim3((G.ny + 255) / 256), dim3(256), 0, s, a);
+  if (split) {
+    const int npb = (G.ny + kGhostBlock - 1) / kGhostBlock;
+    hipLaunchKernelGGL(k_dd_pbar_rows<real>, dim3(npb), dim3(kGhostBlock), 0, s, a);
+    hipLaunchKernelGGL(k_dd_pbar_fold<real>, dim3(1), dim3(64), 0, s, a, npb);
+    hipLaunchKernelGGL(k_dd_lbm<real>, dim3((G.ib + 63) / 64, (G.ny + 3) / 4), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_dd_xb<real>, dim3((G.ny + 255) / 256), dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -754,7 +783,9 @@ template <typename real>
 hipError_t launch_split_init(const SplitGeom& G, const SplitPtrs<real>& P, const SplitParams& S,
                              const double* T0, hipStream_t s) {
   const SplitArgs<real> a = make_args<real>(G, P, S, 0, 1);
-  const int w = G.nx + 2 > G.ib + 1 ? G.nx + 2 : G.ib + 1;
+  // LBM nodes 0 .. nl-1 and stored FV columns c0-2 .. nx
+  const int wf = G.pF > 0 ? G.nx - G.c0 + 3 : 0;
+  const int w = wf > a.nl ? wf : a.nl;
   hipLaunchKernelGGL(k_dd_init<real>, dim3((w + 255) / 256, G.ny), dim3(256), 0, s, a, T0);
   // the second FV buffers start equal to the first (prescribed/wall faces)
   const SplitArgs<real> b = make_args<real>(G, P, S, 1, 1);

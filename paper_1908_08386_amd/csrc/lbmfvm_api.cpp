@@ -211,7 +211,8 @@ lf_status lf_case_create(lf_ctx* ctx, const lf_case_desc* d, lf_case** out) {
   if (d->nx < 8 || d->ny < 8) return fail(LF_EINVAL, "nx, ny must be >= 8 (got %d, %d)", d->nx, d->ny);
   if (d->precision != LF_F32 && d->precision != LF_F64)
     return fail(LF_EINVAL, "precision must be LF_F32 or LF_F64");
-  if (d->mode != LF_MODE_HYBRID && d->mode != LF_MODE_SPLIT)
+  if (d->mode != LF_MODE_HYBRID && d->mode != LF_MODE_SPLIT && d->mode != LF_MODE_PURE_FV &&
+      d->mode != LF_MODE_PURE_LBM)
     return fail(LF_EINVAL, "mode %d unknown", d->mode);
   if (d->mode == LF_MODE_SPLIT) {
     if (d->nx % 2 || d->nx < 12)
@@ -241,16 +242,29 @@ lf_status lf_case_create(lf_ctx* ctx, const lf_case_desc* d, lf_case** out) {
   c->w.tfix[LF_SIDE_W] = 1; c->w.Tw[LF_SIDE_W] = 0.5;
   c->w.tfix[LF_SIDE_E] = 1; c->w.Tw[LF_SIDE_E] = -0.5;
   c->p.omega = 1.0;
-  if (d->mode == LF_MODE_SPLIT) {
+  if (d->mode != LF_MODE_HYBRID) {
     c->split = true;
     lf::SplitGeom& G = c->sg;
     G.nx = d->nx;
     G.ny = d->ny;
-    G.s = d->nx / 2;
-    G.c0 = G.s - 1;
-    G.ib = G.s + 1;
-    G.pL = (G.ib + 1 + 63) / 64 * 64;
-    G.pF = (G.nx - G.c0 + 3 + 63) / 64 * 64;
+    G.fv_only = d->mode == LF_MODE_PURE_FV;
+    G.lbm_only = d->mode == LF_MODE_PURE_LBM;
+    if (G.fv_only) {  // FV cells 0 .. nx-1, wall faces 0 and nx
+      G.s = G.c0 = G.ib = 0;
+      G.pL = 0;
+      G.pF = (G.nx + 3 + 63) / 64 * 64;
+    } else if (G.lbm_only) {  // LBM nodes 0 .. nx-1
+      G.s = G.ib = G.nx;
+      G.c0 = G.nx + 2;  // no FV cell
+      G.pL = (G.nx + 63) / 64 * 64;
+      G.pF = 0;
+    } else {
+      G.s = d->nx / 2;
+      G.c0 = G.s - 1;
+      G.ib = G.s + 1;
+      G.pL = (G.ib + 1 + 63) / 64 * 64;
+      G.pF = (G.nx - G.c0 + 3 + 63) / 64 * 64;
+    }
     c->sp.kind = d->iface;
     c->sp.tau = c->sp.tauT = 1.0;
     c->sp.tfix[LF_SIDE_W] = 1; c->sp.Tw[LF_SIDE_W] = 0.5;
@@ -299,7 +313,7 @@ static lf_status apply_lattice(lf_case* c, double nu, double alpha, double gbeta
   const double tau = 3.0 * nu + 0.5;  // Eq 15 with c_s^2 = 1/3, Eq 42
   lf_status st = check_stable(tau, alpha);
   if (st != LF_OK) return st;
-  if (c->split && nu > 1.0 / 12.0)
+  if (c->split && !c->sg.lbm_only && nu > 1.0 / 12.0)
     return fail(LF_EUNSTABLE, "nu = %.6g: the explicit artificial-compressibility FV zone is "
                 "linearly stable only for nu <= 1/12", nu);
   if (c->split && (gx != 0.0 || gy != 0.0))
@@ -384,7 +398,7 @@ extern "C" {
 lf_status lf_case_set_physics(lf_case* c, const lf_physics* ph) {
   if (!c || !ph) return fail(LF_EINVAL, "NULL argument");
   double prm[8];
-  lf_status st = lf_derive_params(ph, c->g.ny, c->desc.mode == LF_MODE_SPLIT, prm);
+  lf_status st = lf_derive_params(ph, c->g.ny, c->split, prm);
   if (st != LF_OK) return st;
   st = apply_lattice(c, prm[1], prm[3], prm[5], prm[6], ph->body_gx, ph->body_gy, ph->conv);
   if (st != LF_OK) return st;
@@ -783,11 +797,27 @@ lf_status lf_case_mass(lf_case* c, double* sum_f, double* sum_T) {
   hipStream_t s = c->ctx->stream;
   double* out = (double*)(c->ws + c->off_out) + 32;
   double* part = (double*)(c->ws + c->off_part);
+  if (c->split && c->sg.fv_only) {
+    // no populations: the FV density 1 + 3 p and T summed over the cells
+    const size_t n = (size_t)c->sg.nx * c->sg.ny;
+    std::vector<double> r(n), T(n);
+    lf_status st = lf_case_fetch(c, LF_FIELD_RHO, r.data(), n * sizeof(double), 0, 1);
+    if (st == LF_OK) st = lf_case_fetch(c, LF_FIELD_T, T.data(), n * sizeof(double), 0, 1);
+    if (st != LF_OK) return st;
+    double sr = 0.0, sT = 0.0;
+    for (size_t k = 0; k < n; ++k) {
+      sr += r[k];
+      sT += T[k];
+    }
+    *sum_f = sr;
+    *sum_T = sT;
+    return LF_OK;
+  }
   if (c->split) {
-    // populations of the LBM zone (nodes 0 .. ib); T summed over the whole
-    // cavity from the output field
+    // populations of the LBM zone (nodes 0 .. ib, all nx nodes without an FV
+    // zone); T summed over the whole cavity from the output field
     lf::Grid gl;
-    gl.nx = c->sg.ib + 1;
+    gl.nx = c->sg.lbm_only ? c->sg.nx : c->sg.ib + 1;
     gl.ny = c->sg.ny;
     gl.pitch = c->sg.pL;
     gl.plane = (long long)c->sg.pL * c->sg.ny;

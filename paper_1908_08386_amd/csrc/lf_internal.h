@@ -125,8 +125,12 @@ namespace lf {
 // ---- domain-decomposed mode ---------------------------------------------
 // Geometry: nx even, s = nx / 2, FV cells from c0 = s - 1, LBM nodes up to
 // ib = s + 1; pL / pF are the row pitches of the LBM and FV arrays.
+// Single-method cavities use the same zone kernels: fv_only (s = c0 = 0, a
+// wall on the FV zone's west side, no LBM zone) or lbm_only (s = ib = nx, a
+// wall on the LBM zone's east side, no FV zone).
 struct SplitGeom {
   int nx, ny, s, c0, ib, pL, pF;
+  int fv_only, lbm_only;
 };
 
 template <typename real>

@@ -136,3 +136,85 @@ def test_split_full_size_first_steps(lf, ctx):
     for f in ("u", "v"):
         a, b = g.fetch(f), o.fetch(f)
         assert np.abs(a - b).max() <= 1e-4 * max(np.abs(b).max(), 1e-12) + 1e-12, f
+
+
+def pure_pair(lf, ctx, nx, ny, prec, mode, omode, Ra=1e5, Pr=0.71, T0=None, conv=0):
+    g = lf.Case(ctx, nx, ny, prec, mode=mode)
+    g.set_physics(Ra, Pr, conv=conv).set_cavity_walls().init(T0)
+    o = oracle.DDCase(nx, ny, omode).set_physics(Ra, Pr).set_cavity_walls()
+    o.set_lattice(o.params["nu"], o.params["alpha"], o.params["gbeta"], 0.0, conv=conv)
+    o.init(T0)
+    assert abs(g.params()["nu"] - o.params["nu"]) < 1e-15
+    return g, o
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+@pytest.mark.parametrize("nx,ny", [(40, 24), (203, 70)])
+def test_pure_fv_parity(lf, ctx, prec, tol, nx, ny):
+    """The FV-only cavity (the single FV method of Sec. 4.2) against the
+    oracle: 40 x 24 runs on wall waves only; 203 x 70 also on the interior
+    (direct-addressed) path, with ragged rows and columns."""
+    oracle.set_threads(8)
+    T0 = perturbation(nx, ny, 41, amp=0.1)
+    g, o = pure_pair(lf, ctx, nx, ny, prec, lf.MODE_PURE_FV, oracle.PURE_FV, T0=T0)
+    g.step(500)
+    o.step(500)
+    check(g, o, tol)
+    ng, no = g.nusselt(), o.nusselt()
+    for k in ("nu_hot", "nu_cold", "nu_hot_max"):
+        assert abs(ng[k] - no[k]) <= tol * abs(no[k]), k
+
+
+@pytest.mark.parametrize("conv", [1, 2])
+def test_pure_fv_central_and_upwind(lf, ctx, conv):
+    oracle.set_threads(8)
+    nx, ny = 150, 40
+    T0 = perturbation(nx, ny, 42, amp=0.1)
+    g, o = pure_pair(lf, ctx, nx, ny, "f64", lf.MODE_PURE_FV, oracle.PURE_FV, T0=T0, conv=conv)
+    g.step(300)
+    o.step(300)
+    check(g, o, 1e-10)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+@pytest.mark.parametrize("nx,ny", [(40, 24), (130, 70)])
+def test_pure_lbm_parity(lf, ctx, prec, tol, nx, ny):
+    """The LBM-only cavity (D2Q9 flow + D2Q5 heat on the whole box, the single
+    LBM method of Sec. 4.2) against the oracle."""
+    oracle.set_threads(8)
+    T0 = perturbation(nx, ny, 43, amp=0.1)
+    g, o = pure_pair(lf, ctx, nx, ny, prec, lf.MODE_PURE_LBM, oracle.PURE_LBM, T0=T0)
+    g.step(500)
+    o.step(500)
+    check(g, o, tol)
+    ng, no = g.nusselt(), o.nusselt()
+    for k in ("nu_hot", "nu_cold", "nu_hot_max"):
+        assert abs(ng[k] - no[k]) <= tol * abs(no[k]), k
+
+
+def test_pure_modes_conserve(lf, ctx):
+    """Closed boxes: the LBM-only cavity keeps sum f to rounding; the FV-only
+    cavity keeps its mean pressure (sum of 1 + 3 p) at its initial level."""
+    n = 48
+    T0 = perturbation(n, n, 44, amp=0.2)
+    for mode in (lf.MODE_PURE_LBM, lf.MODE_PURE_FV):
+        g = lf.Case(ctx, n, n, "f64", mode=mode).set_physics(1e5, 0.71).set_cavity_walls()
+        g.init(T0)
+        m0, _ = g.mass()
+        g.step(700)
+        m1, _ = g.mass()
+        assert abs(m1 - m0) <= 1e-10 * n * n, (mode, m0, m1)
+
+
+def test_pure_mode_errors(lf, ctx):
+    for mode in (lf.MODE_PURE_FV, lf.MODE_PURE_LBM):
+        g = lf.Case(ctx, 32, 32, mode=mode)
+        with pytest.raises(lf.LFError) as e:
+            g.set_wall(lf.W, lf.WALL_PERIODIC, 0.0, lf.T_PERIODIC, 0.0)
+        assert e.value.status == lf.LF_ENOTIMPL
+        with pytest.raises(lf.LFError) as e:
+            g.set_wall(lf.N, lf.WALL_NOSLIP, 0.05, lf.T_ADIABATIC, 0.0)
+        assert e.value.status == lf.LF_ENOTIMPL
+    with pytest.raises(lf.LFError) as e:
+        lf.Case(ctx, 32, 32, mode=4)
+    assert e.value.status == lf.LF_EINVAL
