@@ -224,15 +224,31 @@ __global__ __launch_bounds__(kGhostBlock) void k_dd_ghost_rows(SplitArgs<real> a
   }
 }
 
+// In-order sum of n per-block partials spaced `stride` doubles apart, from
+// `base` on: the block stages up to 1024 of them at a time in LDS with
+// parallel loads, then thread 0 adds them in index order (the same order,
+// hence the same bits, as one thread reading them one by one).
+__device__ __forceinline__ double ordered_sum(const double* __restrict__ base, int n, int stride,
+                                              double* stage) {
+  double t = 0.0;
+  for (int b0 = 0; b0 < n; b0 += 1024) {
+    const int m = n - b0 < 1024 ? n - b0 : 1024;
+    for (int k = threadIdx.x; k < m; k += blockDim.x) stage[k] = base[(size_t)(b0 + k) * stride];
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int k = 0; k < m; ++k) t += stage[k];
+    __syncthreads();
+  }
+  return t;  // valid in thread 0
+}
+
 template <typename real>
 __global__ __launch_bounds__(1024) void k_dd_ghost_fold(SplitArgs<real> a, int nblocks) {
+  __shared__ double stage[1024];
   __shared__ real mean_sh;
+  const double tu = ordered_sum(a.iface + kIfacePart, nblocks, 2, stage);
+  const double tr = ordered_sum(a.iface + kIfacePart + 1, nblocks, 2, stage);
   if (threadIdx.x == 0) {
-    double tu = 0.0, tr = 0.0;
-    for (int b = 0; b < nblocks; ++b) {
-      tu += a.iface[kIfacePart + 2 * b];
-      tr += a.iface[kIfacePart + 2 * b + 1];
-    }
     mean_sh = (real)(tu / a.ny);
     a.iface[0] = tr / (3.0 * a.ny);
   }
@@ -466,11 +482,10 @@ __global__ __launch_bounds__(kGhostBlock) void k_dd_pbar_rows(SplitArgs<real> a)
 }
 
 template <typename real>
-__global__ void k_dd_pbar_fold(SplitArgs<real> a, int nblocks) {
-  if (threadIdx.x != 0) return;
-  double t = 0.0;
-  for (int b = 0; b < nblocks; ++b) t += a.iface[kIfacePart + b];
-  a.iface[1] = t / (3.0 * a.ny);
+__global__ __launch_bounds__(256) void k_dd_pbar_fold(SplitArgs<real> a, int nblocks) {
+  __shared__ double stage[1024];
+  const double t = ordered_sum(a.iface + kIfacePart, nblocks, 1, stage);
+  if (threadIdx.x == 0) a.iface[1] = t / (3.0 * a.ny);
 }
 
 // 5. LBM zone, nodes 0 .. ib-1: stream, moments, collide
@@ -772,7 +787,7 @@ hipError_t launch_split_step(const SplitGeom& G, const SplitPtrs<real>& P, const
   if (split) {
     const int npb = (G.ny + kGhostBlock - 1) / kGhostBlock;
     hipLaunchKernelGGL(k_dd_pbar_rows<real>, dim3(npb), dim3(kGhostBlock), 0, s, a);
-    hipLaunchKernelGGL(k_dd_pbar_fold<real>, dim3(1), dim3(64), 0, s, a, npb);
+    hipLaunchKernelGGL(k_dd_pbar_fold<real>, dim3(1), dim3(256), 0, s, a, npb);
     hipLaunchKernelGGL(k_dd_lbm<real>, dim3((G.ib + 63) / 64, (G.ny + 3) / 4), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_dd_xb<real>, dim3((G.ny + 255) / 256), dim3(256), 0, s, a);
   }
