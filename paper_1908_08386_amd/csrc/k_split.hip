@@ -73,14 +73,6 @@ __device__ __forceinline__ float fmad<float>(float a, float b, float c) {
   return __builtin_fmaf(a, b, c);
 }
 
-template <typename real>
-__device__ __forceinline__ real quick(int conv, real uf, real ll, real l, real r, real rr) {
-  if (conv == 1) return real(0.5) * (l + r);
-  if (conv == 2) return uf >= real(0) ? l : r;
-  return uf >= real(0) ? fmad(real(0.75), l, fmad(real(0.375), r, real(-0.125) * ll))
-                       : fmad(real(0.75), r, fmad(real(0.375), l, real(-0.125) * rr));
-}
-
 // shifted f_eq: f_eq - w = w (drho + rho P), P = 3 e.u + 9/2 (e.u)^2 - 3/2 u.u
 template <typename real>
 __device__ __forceinline__ real feq_s(int q, real drho, real ux, real uy) {
@@ -117,7 +109,7 @@ struct SplitArgs {
   int nx, ny, s, c0, ib;
   int west_wall;  // FV zone closed by a wall at x = 0 (FV-only cavity)
   int east_wall;  // LBM zone closed by a wall at x = nx (LBM-only cavity)
-  int conv, kind, mom_all;
+  int kind, mom_all;
   real omega, omegaT, tau, nu, alpha, gbeta, Tref;
   int tfix[4];
   real Tw[4];
@@ -738,7 +730,6 @@ static SplitArgs<real> make_args(const SplitGeom& G, const SplitPtrs<real>& P, c
   a.ib = G.ib;
   a.west_wall = G.fv_only;
   a.east_wall = G.lbm_only;
-  a.conv = S.conv;
   a.kind = S.kind;
   a.mom_all = mom_all;
   a.omega = real(1.0 / S.tau);
