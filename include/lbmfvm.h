@@ -89,7 +89,8 @@ typedef struct {
                     no periodic sides, start from rest)                    */
   int split_col; /* Mode DD: first FV cell is split_col - 1; 0 => nx/2      */
   int overlap;   /* Mode DD: shared columns; 0 => 3 (the only value)        */
-  int iface;     /* Mode DD: LF_IFACE_NEQ_EXTRAP or LF_IFACE_FD_GRADIENT    */
+  int iface;     /* Mode DD: LF_IFACE_NEQ_EXTRAP or LF_IFACE_FD_GRADIENT
+                    (split_col, overlap, iface: ignored by the other modes) */
   int tcomp;     /* Mode H, FP32: 1 = temperature kept as a compensated
                     pair hi + lo (FP32 words; increments below ulp(T) are
                     not lost near steady state; +8 B per node), 0 = plain  */
@@ -97,8 +98,9 @@ typedef struct {
 
 /* Physical groups (Eq 82-89).  Ra > 0, Pr > 0.  U_char is the buoyancy
  * velocity sqrt(g beta dT H) in lattice units; 0 selects 0.1, lowered where
- * the explicit updates need it (alpha <= 0.2, U^2 <= 2 alpha; Mode DD also
- * nu <= 0.2).  T_ref NaN selects 0 (the mid value of walls at +-1/2).
+ * the explicit updates need it (alpha <= 0.2, U^2 <= 2 alpha; the split
+ * mode and the single-method cavities, whose parameters follow the split
+ * mode's, also nu <= 0.08).  T_ref NaN selects 0 (the mid value of walls at +-1/2).
  * body_gx, body_gy add a constant body acceleration (test hook).           */
 typedef struct {
   double Ra, Pr, U_char, T_ref;
@@ -140,8 +142,11 @@ lf_status lf_ctx_set_band(lf_ctx* ctx, int rows);
 
 /* ---- single cavity ---------------------------------------------------- */
 /* Mode H: the whole cavity is LBM velocity + FV temperature (Sec. 5.1,
- * grid setting 1).  Defaults after create: side-heated cavity walls (west
- * T = +1/2, east T = -1/2, south/north adiabatic, all no-slip at rest).    */
+ * grid setting 1); the split mode and the single-method cavities as listed
+ * at the top.  Defaults after create: side-heated cavity walls (west
+ * T = +1/2, east T = -1/2, south/north adiabatic, all no-slip at rest).
+ * LF_EINVAL for an unknown mode, nx or ny < 8, an odd nx or nx < 12 in the
+ * split mode, or a grid too large for 32-bit plane indexing.              */
 lf_status lf_case_create(lf_ctx* ctx, const lf_case_desc* desc, lf_case** out);
 lf_status lf_case_destroy(lf_case* c);
 lf_status lf_case_workspace_bytes(const lf_case* c, size_t* bytes);
