@@ -220,3 +220,21 @@ def test_c2_size_500_steps_fp32(lf, ctx):
     g.step(500)
     o.step(500)
     compare(g, o, 1e-4)
+
+
+def test_full_size_4096_in_bench_configuration(lf, ctx):
+    """4096 x 4096, Ra 1e6, FP32 (the HBM-bound size the benchmark also times),
+    with the automatic band height (4 rows, alternating march directions):
+    element-wise parity with the oracle over the first 40 steps.  Velocities
+    start from rest, so u and v are compared against the oracle's field scale
+    plus a floor."""
+    oracle.set_threads(16)
+    n = 4096
+    T0 = perturbation(n, n, 1908083860)
+    g, o = make_pair(lf, ctx, n, n, "f32", physics=(1e6, 0.71), T0=T0)
+    g.step(40)
+    o.step(40)
+    compare(g, o, 1e-4, ("T",))
+    for f in ("u", "v"):
+        a, b = g.fetch(f), o.fetch(f)
+        assert np.abs(a - b).max() <= 1e-4 * max(np.abs(b).max(), 1e-12) + 1e-12, f
