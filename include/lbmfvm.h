@@ -18,6 +18,10 @@
  *     with the zone kernels of Mode DD: LF_MODE_PURE_FV (staggered FVM,
  *     explicit momentum with artificial compressibility, Eq 74-76) and
  *     LF_MODE_PURE_LBM (D2Q9 flow + D2Q5 heat, Eq 19-23).
+ *   - Mode H on grid setting 2 (LF_MODE_HYBRID_GS2, Sec. 5.1, Fig. 30): the
+ *     lattice on all nx x ny nodes, the temperature on nx/2 x ny/2 control
+ *     volumes of 2 x 2 nodes, one implicit energy step per S lattice steps
+ *     (S = nx, i.e. 2NX, by default; lf_case_set_subcycle).
  *
  * Conventions (all entry points):
  *   - Every call returns lf_status; LF_OK is 0.  On failure
@@ -66,7 +70,13 @@ typedef enum {
 } lf_status;
 
 enum { LF_F32 = 0, LF_F64 = 1 };
-enum { LF_MODE_HYBRID = 0, LF_MODE_SPLIT = 1, LF_MODE_PURE_FV = 2, LF_MODE_PURE_LBM = 3 };
+enum {
+  LF_MODE_HYBRID = 0,
+  LF_MODE_SPLIT = 1,
+  LF_MODE_PURE_FV = 2,
+  LF_MODE_PURE_LBM = 3,
+  LF_MODE_HYBRID_GS2 = 4
+};
 enum { LF_IFACE_NEQ_EXTRAP = 0, LF_IFACE_FD_GRADIENT = 1 };
 enum { LF_CONV_QUICK = 0, LF_CONV_CENTRAL = 1, LF_CONV_UPWIND = 2 };
 enum { LF_WALL_NOSLIP = 0, LF_WALL_PERIODIC = 1 };
@@ -84,9 +94,10 @@ typedef struct lf_case lf_case;
 typedef struct {
   int nx, ny;
   int precision; /* LF_F32 or LF_F64                                        */
-  int mode;      /* LF_MODE_HYBRID, LF_MODE_SPLIT, LF_MODE_PURE_FV or
-                    LF_MODE_PURE_LBM (the last three: walls at rest,
-                    no periodic sides, start from rest)                    */
+  int mode;      /* LF_MODE_HYBRID, LF_MODE_SPLIT, LF_MODE_PURE_FV,
+                    LF_MODE_PURE_LBM or LF_MODE_HYBRID_GS2 (all but the
+                    first: walls at rest, no periodic sides, start from
+                    rest; LF_MODE_HYBRID_GS2 needs even nx and ny)         */
   int split_col; /* Mode DD: first FV cell is split_col - 1; 0 => nx/2      */
   int overlap;   /* Mode DD: shared columns; 0 => 3 (the only value)        */
   int iface;     /* Mode DD: LF_IFACE_NEQ_EXTRAP or LF_IFACE_FD_GRADIENT
@@ -161,6 +172,18 @@ lf_status lf_case_set_lattice(lf_case* c, double nu, double alpha,
 lf_status lf_case_set_wall(lf_case* c, int side, const lf_wall* w);
 /* out = {U_char, nu, tau, alpha, tau_T, g beta, T_ref, Ma}               */
 lf_status lf_case_get_params(const lf_case* c, double out[8]);
+/* LF_MODE_HYBRID_GS2 only: lattice steps per energy step (0 = nx, the
+ * paper's 2NX) and alternating line sweeps that relax each energy step's
+ * implicit system (0 = 4).  The energy step follows every lattice step
+ * whose count since init is a multiple of lattice_steps; its upwind and
+ * diffusion terms are implicit (backward Euler over lattice_steps), QUICK
+ * enters as a deferred correction from the old temperature, and each sweep
+ * solves all x-lines, then all y-lines, by the Thomas algorithm.  lf_case_
+ * init takes T0 on the nodes and starts each control volume at the mean of
+ * its 2 x 2 nodes; fetch returns the node temperatures (bilinear in the
+ * control-volume values, ghosts 2 T_w - T at fixed walls, T at adiabatic
+ * ones).  LF_EINVAL in the other modes or for negative counts.             */
+lf_status lf_case_set_subcycle(lf_case* c, int lattice_steps, int sweeps);
 /* Initial state from host arrays of ny*nx doubles (NULL = 0): rho = 1,
  * f = f_eq(1, (u0, v0)), T = T0; the residual snapshot starts here.        */
 lf_status lf_case_init(lf_case* c, const double* T0, const double* u0,

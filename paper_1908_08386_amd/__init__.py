@@ -38,7 +38,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 LF_OK, LF_EINVAL, LF_ENOMEM, LF_EWORKSPACE, LF_EDEVICE, LF_EUNSTABLE, LF_EDIVERGED, \
     LF_ENOTCONV, LF_ESTATE, LF_ENOTIMPL = range(10)
 F32, F64 = 0, 1
-MODE_HYBRID, MODE_SPLIT, MODE_PURE_FV, MODE_PURE_LBM = 0, 1, 2, 3
+MODE_HYBRID, MODE_SPLIT, MODE_PURE_FV, MODE_PURE_LBM, MODE_HYBRID_GS2 = 0, 1, 2, 3, 4
 IFACE_NEQ_EXTRAP, IFACE_FD_GRADIENT = 0, 1
 CONV_QUICK, CONV_CENTRAL, CONV_UPWIND = 0, 1, 2
 WALL_NOSLIP, WALL_PERIODIC = 0, 1
@@ -99,6 +99,7 @@ _SIGS = {
     "lf_case_set_lattice": (ctypes.c_int, [_vp] + [ctypes.c_double] * 6 + [ctypes.c_int]),
     "lf_case_set_wall": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(lf_wall)]),
     "lf_case_get_params": (ctypes.c_int, [_vp, _dp]),
+    "lf_case_set_subcycle": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
     "lf_case_init": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
     "lf_case_step": (ctypes.c_int, [_vp, _i64]),
     "lf_case_residual": (ctypes.c_int, [_vp, _dp]),
@@ -245,8 +246,9 @@ class Context:
 
 
 class Case:
-    """One cavity: Mode H, the split LBM|FV mode, or one of the single methods
-    (MODE_PURE_FV, MODE_PURE_LBM).  Fields are numpy arrays of shape (ny, nx)."""
+    """One cavity: Mode H (grid setting 1, or 2 with MODE_HYBRID_GS2), the split
+    LBM|FV mode, or one of the single methods (MODE_PURE_FV, MODE_PURE_LBM).
+    Fields are numpy arrays of shape (ny, nx)."""
 
     def __init__(self, ctx: Context, nx: int, ny: int, precision: str = "f32",
                  mode: int = MODE_HYBRID, split_col: int = 0, iface: int = IFACE_NEQ_EXTRAP,
@@ -292,6 +294,13 @@ class Case:
     def set_wall(self, side, vel=WALL_NOSLIP, u_wall=0.0, thermal=T_ADIABATIC, T_wall=0.0):
         w = lf_wall(int(vel), float(u_wall), int(thermal), float(T_wall))
         _check(_lib.lf_case_set_wall(self._h, int(side), ctypes.byref(w)), "lf_case_set_wall")
+        return self
+
+    def set_subcycle(self, lattice_steps=0, sweeps=0):
+        """Grid setting 2: lattice steps per energy step (0: nx) and line
+        sweeps per energy step (0: 4)."""
+        _check(_lib.lf_case_set_subcycle(self._h, int(lattice_steps), int(sweeps)),
+               "lf_case_set_subcycle")
         return self
 
     def set_cavity_walls(self, T_hot=0.5, T_cold=-0.5):

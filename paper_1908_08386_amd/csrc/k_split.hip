@@ -107,6 +107,9 @@ struct SplitArgs {
   // per-block sums of the ghost kernel
   double* __restrict__ iface;
   int nx, ny, s, c0, ib;
+  // grid setting 2: coarse planes (see SplitPtrs::gc), sizes and pitch
+  real* __restrict__ gc[10];
+  int NXc, NYc, pC;
   int west_wall;  // FV zone closed by a wall at x = 0 (FV-only cavity)
   int east_wall;  // LBM zone closed by a wall at x = nx (LBM-only cavity)
   int kind, mom_all;
@@ -482,8 +485,8 @@ __global__ __launch_bounds__(256) void k_dd_pbar_fold(SplitArgs<real> a, int nbl
 
 // 5. LBM zone, nodes 0 .. ib-1: stream, moments, collide
 template <typename real>
-__device__ __forceinline__ void collide_fg(const SplitArgs<real>& a, real f[9], real g[5],
-                                           real drho, real ux, real uy, real T) {
+__device__ __forceinline__ void collide_f(const SplitArgs<real>& a, real f[9], real drho, real ux,
+                                          real uy, real T) {
   const real rho = real(1) + drho;
   const real Gy = a.gbeta * (T - a.Tref);
   const real Gu = Gy * uy;
@@ -496,6 +499,12 @@ __device__ __forceinline__ void collide_fg(const SplitArgs<real>& a, real f[9], 
     const real c = (real(3) * w9<real>(q)) * (real(ey9(q)) * Gy - Gu);
     f[q] = fmad(a.omega, fe - f[q], f[q]) + fmad(c, P, c);
   }
+}
+
+template <typename real>
+__device__ __forceinline__ void collide_fg(const SplitArgs<real>& a, real f[9], real g[5],
+                                           real drho, real ux, real uy, real T) {
+  collide_f(a, f, drho, ux, uy, T);
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
     const real ge = T * w5<real>(q) * (real(1) + real(3) * (real(ex5(q)) * ux + real(ey5(q)) * uy));
@@ -698,6 +707,241 @@ __global__ __launch_bounds__(256) void k_dd_init(SplitArgs<real> a, const double
   }
 }
 
+// ---- grid setting 2 (Sec. 5.1, Fig. 30) -------------------------------
+// The lattice covers all nx x ny nodes; the temperature lives on NXc x NYc
+// control volumes of 2 x 2 nodes (h = 2).  Every lattice step takes its
+// buoyancy from the node temperatures (mom plane 3), which are the coarse
+// field interpolated bilinearly and are refreshed after each energy step.
+// One energy step of length dt lattice steps is backward Euler: upwind
+// convection and central diffusion in the matrix, QUICK minus upwind from
+// the old field as a deferred correction, face velocities the mean of the
+// four node velocities straddling each coarse face; its system is relaxed
+// by K sweeps of x-lines then y-lines, each line solved by the Thomas
+// algorithm with the other direction's neighbours from the previous iterate.
+enum { G2_TA = 0, G2_TB, G2_AP, G2_AW, G2_AE, G2_AS, G2_AN, G2_B, G2_CP, G2_RP };
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_gs2_lbm(SplitArgs<real> a) {
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (i >= a.nx || j >= a.ny) return;
+  const int pL = a.pL, PL = a.planeL;
+  real f[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const int sx = i - ex9(q), sy = j - ey9(q);
+    if (sx >= 0 && sx < a.nx && sy >= 0 && sy < a.ny) f[q] = a.fin[q * PL + sy * pL + sx];
+    else f[q] = a.fin[opp9(q) * PL + j * pL + i];  // walls at rest: bounce-back
+  }
+  real drho, ux, uy;
+  moments9(f, drho, ux, uy);
+  const int o = j * pL + i;
+  if (a.mom_all) {
+    a.mom[o] = real(1) + drho;
+    a.mom[PL + o] = ux;
+    a.mom[2 * PL + o] = uy;
+  }
+  collide_f(a, f, drho, ux, uy, a.mom[3 * PL + o]);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) a.fout[q * PL + o] = f[q];
+}
+
+// coarse temperature with one ghost layer: the x rule on the (clamped) row,
+// then the y rule (2 T_w - T for a fixed wall, T for an adiabatic one)
+template <typename real>
+__device__ __forceinline__ real tc_at(const SplitArgs<real>& a, const real* T, int I, int J) {
+  const int Jc = J < 0 ? 0 : (J >= a.NYc ? a.NYc - 1 : J);
+  real t;
+  if (I < 0) {
+    t = T[Jc * a.pC];
+    if (a.tfix[0]) t = real(2) * a.Tw[0] - t;
+  } else if (I >= a.NXc) {
+    t = T[Jc * a.pC + a.NXc - 1];
+    if (a.tfix[1]) t = real(2) * a.Tw[1] - t;
+  } else {
+    t = T[Jc * a.pC + I];
+  }
+  if (J < 0 && a.tfix[2]) t = real(2) * a.Tw[2] - t;
+  if (J >= a.NYc && a.tfix[3]) t = real(2) * a.Tw[3] - t;
+  return t;
+}
+
+// node temperatures: node i sits at coarse coordinate (2i - 1) / 4, between
+// coarse cells (i - 1) >> 1 and the next with weight 3/4 (i even) or 1/4
+template <typename real>
+__global__ __launch_bounds__(256) void k_gs2_interp(SplitArgs<real> a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+  if (i >= a.nx) return;
+  const real* T = a.gc[G2_TA];
+  const int I0 = (i - 1) >> 1, J0 = (j - 1) >> 1;
+  const real wx = (i & 1) ? real(0.25) : real(0.75), wy = (j & 1) ? real(0.25) : real(0.75);
+  const real t00 = tc_at(a, T, I0, J0), t10 = tc_at(a, T, I0 + 1, J0);
+  const real t01 = tc_at(a, T, I0, J0 + 1), t11 = tc_at(a, T, I0 + 1, J0 + 1);
+  a.mom[3 * a.planeL + j * a.pL + i] =
+      (real(1) - wy) * ((real(1) - wx) * t00 + wx * t10) + wy * ((real(1) - wx) * t01 + wx * t11);
+}
+
+template <typename real>
+__device__ __forceinline__ real quick8(real w, real ll, real l, real r, real rr) {
+  return w >= real(0) ? (real(6) * l + real(3) * r - ll) / real(8)
+                      : (real(6) * r + real(3) * l - rr) / real(8);
+}
+
+// x-face I (between coarse cells I-1 and I) of coarse row J: face velocity
+// from the lattice and the deferred-correction flux h w (T_QUICK - T_up)
+template <typename real>
+__device__ __forceinline__ void xface(const SplitArgs<real>& a, int I, int J, real& w, real& dc) {
+  const real* ux = a.mom + a.planeL;
+  const int r0 = 2 * J * a.pL, r1 = r0 + a.pL, c = 2 * I;
+  w = real(0.25) * ((ux[r0 + c - 1] + ux[r0 + c]) + (ux[r1 + c - 1] + ux[r1 + c]));
+  const real* T = a.gc[G2_TA];
+  const real tl = T[J * a.pC + I - 1], tr = T[J * a.pC + I];
+  const real q = quick8(w, tc_at(a, T, I - 2, J), tl, tr, tc_at(a, T, I + 1, J));
+  dc = real(2) * w * (q - (w >= real(0) ? tl : tr));
+}
+template <typename real>
+__device__ __forceinline__ void yface(const SplitArgs<real>& a, int I, int J, real& w, real& dc) {
+  const real* uy = a.mom + 2 * a.planeL;
+  const int r0 = (2 * J - 1) * a.pL, r1 = r0 + a.pL, c = 2 * I;
+  w = real(0.25) * ((uy[r0 + c] + uy[r1 + c]) + (uy[r0 + c + 1] + uy[r1 + c + 1]));
+  const real* T = a.gc[G2_TA];
+  const real tl = T[(J - 1) * a.pC + I], tr = T[J * a.pC + I];
+  const real q = quick8(w, tc_at(a, T, I, J - 2), tl, tr, tc_at(a, T, I, J + 1));
+  dc = real(2) * w * (q - (w >= real(0) ? tl : tr));
+}
+
+// coefficients of a_P T_P - a_W T_W - a_E T_E - a_S T_S - a_N T_N = b
+template <typename real>
+__global__ __launch_bounds__(256) void k_gs2_assemble(SplitArgs<real> a, int dt) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x, J = blockIdx.y;
+  if (I >= a.NXc) return;
+  const real al = a.alpha, h = real(2), zero = real(0);
+  const int o = J * a.pC + I;
+  real aW = zero, aE = zero, aS = zero, aN = zero;
+  real cW = zero, cE = zero, cS = zero, cN = zero;
+  real sW = zero, sE = zero, sS = zero, sN = zero;
+  real w, dc;
+  if (I >= 1) {
+    xface(a, I, J, w, dc);
+    aW = al + h * fmax(w, zero);
+    cW = al + h * fmax(-w, zero);
+    sW = dc;
+  } else if (a.tfix[0]) {
+    cW = real(2) * al;
+    sW = real(2) * al * a.Tw[0];
+  }
+  if (I <= a.NXc - 2) {
+    xface(a, I + 1, J, w, dc);
+    aE = al + h * fmax(-w, zero);
+    cE = al + h * fmax(w, zero);
+    sE = -dc;
+  } else if (a.tfix[1]) {
+    cE = real(2) * al;
+    sE = real(2) * al * a.Tw[1];
+  }
+  if (J >= 1) {
+    yface(a, I, J, w, dc);
+    aS = al + h * fmax(w, zero);
+    cS = al + h * fmax(-w, zero);
+    sS = dc;
+  } else if (a.tfix[2]) {
+    cS = real(2) * al;
+    sS = real(2) * al * a.Tw[2];
+  }
+  if (J <= a.NYc - 2) {
+    yface(a, I, J + 1, w, dc);
+    aN = al + h * fmax(-w, zero);
+    cN = al + h * fmax(w, zero);
+    sN = -dc;
+  } else if (a.tfix[3]) {
+    cN = real(2) * al;
+    sN = real(2) * al * a.Tw[3];
+  }
+  const real ct = h * h / real(dt);
+  a.gc[G2_AP][o] = (((ct + cW) + cE) + cS) + cN;
+  a.gc[G2_AW][o] = aW;
+  a.gc[G2_AE][o] = aE;
+  a.gc[G2_AS][o] = aS;
+  a.gc[G2_AN][o] = aN;
+  a.gc[G2_B][o] = ((((ct * a.gc[G2_TA][o]) + sW) + sE) + sS) + sN;
+}
+
+// One line of a sweep by the Thomas algorithm: n unknowns at X + k * step,
+// lower -lo, diagonal aP, upper -up; the right-hand side b + c1 * Y1 + c2 * Y2
+// with the other direction's neighbours Y1, Y2 (zero-weighted at walls) read
+// from the previous iterate X0.
+template <typename real>
+__device__ __forceinline__ void thomas_line(const SplitArgs<real>& a, int base, int step, int n,
+                                            int lo_k, int up_k, int c1_k, int c2_k, int d1, int d2,
+                                            const real* X0, real* X) {
+  const real* aP = a.gc[G2_AP];
+  const real* L = a.gc[lo_k];
+  const real* U = a.gc[up_k];
+  const real* C1 = a.gc[c1_k];
+  const real* C2 = a.gc[c2_k];
+  const real* b = a.gc[G2_B];
+  real* cp = a.gc[G2_CP];
+  real* rp = a.gc[G2_RP];
+  real cprev = real(0), rprev = real(0);
+  for (int k = 0; k < n; ++k) {
+    const int o = base + k * step;
+    const real c1 = C1[o], c2 = C2[o];
+    const real y1 = c1 != real(0) ? X0[o + d1] : real(0);
+    const real y2 = c2 != real(0) ? X0[o + d2] : real(0);
+    const real rhs = (b[o] + c1 * y1) + c2 * y2;
+    const real lo = -L[o], up = -U[o];
+    real cpk, rpk;
+    if (k == 0) {
+      cpk = up / aP[o];
+      rpk = rhs / aP[o];
+    } else {
+      const real m = aP[o] - lo * cprev;
+      cpk = up / m;
+      rpk = (rhs - lo * rprev) / m;
+    }
+    cp[o] = cpk;
+    rp[o] = rpk;
+    cprev = cpk;
+    rprev = rpk;
+  }
+  real x = rprev;
+  X[base + (n - 1) * step] = x;
+  for (int k = n - 2; k >= 0; --k) {
+    const int o = base + k * step;
+    x = rp[o] - cp[o] * x;
+    X[o] = x;
+  }
+}
+
+// x-lines: one thread per coarse row, iterate A -> B
+template <typename real>
+__global__ __launch_bounds__(64) void k_gs2_xlines(SplitArgs<real> a) {
+  const int J = blockIdx.x * blockDim.x + threadIdx.x;
+  if (J >= a.NYc) return;
+  thomas_line(a, J * a.pC, 1, a.NXc, G2_AW, G2_AE, G2_AS, G2_AN, -a.pC, a.pC, a.gc[G2_TA],
+              a.gc[G2_TB]);
+}
+// y-lines: one thread per coarse column, iterate B -> A
+template <typename real>
+__global__ __launch_bounds__(64) void k_gs2_ylines(SplitArgs<real> a) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= a.NXc) return;
+  thomas_line(a, I, a.pC, a.NYc, G2_AS, G2_AN, G2_AW, G2_AE, -1, 1, a.gc[G2_TB], a.gc[G2_TA]);
+}
+
+// coarse temperature from a dense T0 (mean of each 2 x 2 block), or 0
+template <typename real>
+__global__ __launch_bounds__(256) void k_gs2_init(SplitArgs<real> a, const double* __restrict__ T0) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x, J = blockIdx.y;
+  if (I >= a.NXc) return;
+  double t = 0.0;
+  if (T0) {
+    const int r0 = 2 * J * a.nx, r1 = r0 + a.nx, c = 2 * I;
+    t = 0.25 * ((T0[r0 + c] + T0[r0 + c + 1]) + (T0[r1 + c] + T0[r1 + c + 1]));
+  }
+  a.gc[G2_TA][J * a.pC + I] = real(t);
+}
+
 }  // namespace
 
 template <typename real>
@@ -713,7 +957,7 @@ static SplitArgs<real> make_args(const SplitGeom& G, const SplitPtrs<real>& P, c
   a.xf = P.xf;
   a.pL = G.pL;
   a.planeL = G.pL * G.ny;
-  a.nl = G.fv_only ? 0 : G.lbm_only ? G.nx : G.ib + 1;
+  a.nl = G.fv_only ? 0 : (G.lbm_only || G.gs2) ? G.nx : G.ib + 1;
   a.u = P.u[cur];
   a.v = P.v[cur];
   a.T = P.T[cur];
@@ -728,6 +972,10 @@ static SplitArgs<real> make_args(const SplitGeom& G, const SplitPtrs<real>& P, c
   a.s = G.s;
   a.c0 = G.c0;
   a.ib = G.ib;
+  for (int k = 0; k < 10; ++k) a.gc[k] = P.gc[k];
+  a.NXc = G.NXc;
+  a.NYc = G.NYc;
+  a.pC = G.pC;
   a.west_wall = G.fv_only;
   a.east_wall = G.lbm_only;
   a.kind = S.kind;
@@ -807,13 +1055,53 @@ hipError_t launch_split_output(const SplitGeom& G, const SplitPtrs<real>& P, con
   return hipGetLastError();
 }
 
+template <typename real>
+hipError_t launch_gs2_lbm(const SplitGeom& G, const SplitPtrs<real>& P, const SplitParams& S,
+                          int cur, int mom_all, hipStream_t s) {
+  const SplitArgs<real> a = make_args<real>(G, P, S, cur, mom_all);
+  hipLaunchKernelGGL(k_gs2_lbm<real>, dim3((G.nx + 63) / 64, (G.ny + 3) / 4), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_gs2_energy(const SplitGeom& G, const SplitPtrs<real>& P, const SplitParams& S,
+                             int dt, int K, hipStream_t s) {
+  const SplitArgs<real> a = make_args<real>(G, P, S, 0, 0);
+  hipLaunchKernelGGL(k_gs2_assemble<real>, dim3((G.NXc + 255) / 256, G.NYc), dim3(256), 0, s, a,
+                     dt);
+  for (int k = 0; k < K; ++k) {
+    hipLaunchKernelGGL(k_gs2_xlines<real>, dim3((G.NYc + 63) / 64), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_gs2_ylines<real>, dim3((G.NXc + 63) / 64), dim3(64), 0, s, a);
+  }
+  hipLaunchKernelGGL(k_gs2_interp<real>, dim3((G.nx + 255) / 256, G.ny), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_gs2_init(const SplitGeom& G, const SplitPtrs<real>& P, const SplitParams& S,
+                           const double* T0, hipStream_t s) {
+  const SplitArgs<real> a = make_args<real>(G, P, S, 0, 1);
+  hipLaunchKernelGGL(k_dd_init<real>, dim3((G.nx + 255) / 256, G.ny), dim3(256), 0, s, a, T0);
+  const SplitArgs<real> b = make_args<real>(G, P, S, 1, 1);
+  hipLaunchKernelGGL(k_dd_init<real>, dim3((G.nx + 255) / 256, G.ny), dim3(256), 0, s, b, T0);
+  hipLaunchKernelGGL(k_gs2_init<real>, dim3((G.NXc + 255) / 256, G.NYc), dim3(256), 0, s, a, T0);
+  hipLaunchKernelGGL(k_gs2_interp<real>, dim3((G.nx + 255) / 256, G.ny), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 #define LF_SPLIT_INST(real)                                                                   \
   template hipError_t launch_split_step<real>(const SplitGeom&, const SplitPtrs<real>&,        \
                                               const SplitParams&, int, int, hipStream_t);      \
   template hipError_t launch_split_init<real>(const SplitGeom&, const SplitPtrs<real>&,        \
                                               const SplitParams&, const double*, hipStream_t); \
   template hipError_t launch_split_output<real>(const SplitGeom&, const SplitPtrs<real>&,      \
-                                                const SplitParams&, int, real*, hipStream_t);
+                                                const SplitParams&, int, real*, hipStream_t);  \
+  template hipError_t launch_gs2_lbm<real>(const SplitGeom&, const SplitPtrs<real>&,           \
+                                           const SplitParams&, int, int, hipStream_t);         \
+  template hipError_t launch_gs2_energy<real>(const SplitGeom&, const SplitPtrs<real>&,        \
+                                              const SplitParams&, int, int, hipStream_t);      \
+  template hipError_t launch_gs2_init<real>(const SplitGeom&, const SplitPtrs<real>&,          \
+                                            const SplitParams&, const double*, hipStream_t);
 LF_SPLIT_INST(float)
 LF_SPLIT_INST(double)
 #undef LF_SPLIT_INST

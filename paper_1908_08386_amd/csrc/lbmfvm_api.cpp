@@ -54,6 +54,10 @@ struct lf_case {
   lf::SplitParams sp;
   size_t off_sf[2], off_sg[2], off_smom, off_sxf, off_su[2], off_sv[2], off_sT[2], off_sp,
       off_siface, off_dense, off_dsnap;
+  // grid setting 2: the coarse planes, lattice steps per energy step and
+  // line sweeps per energy step
+  size_t off_gs2[10];
+  int gs2_S, gs2_K;
 };
 
 template <typename real>
@@ -79,6 +83,10 @@ static void layout_split(lf_case* c) {
   c->off_sp = o; o += pbF;
   // interface scalars, then two sums per 256-row block of the ghost kernel
   c->off_siface = o; o += align_up((size_t)(8 + 2 * ((G.ny + 1 + 255) / 256)) * sizeof(double), 256);
+  for (int k = 0; k < 10; ++k) {
+    c->off_gs2[k] = o;
+    if (G.gs2) o += align_up((size_t)G.pC * G.NYc * c->es, 256);
+  }
   c->off_dense = o; o += 4 * pbD;
   c->off_dsnap = o; o += 3 * pbD;
   c->off_part = o; o += align_up((size_t)c->nblk * 8 * sizeof(double), 256);
@@ -104,6 +112,7 @@ static lf::SplitPtrs<real> split_ptrs(lf_case* c) {
   P.xf = (real*)(c->ws + c->off_sxf);
   P.p = (real*)(c->ws + c->off_sp);
   P.iface = (double*)(c->ws + c->off_siface);
+  for (int k = 0; k < 10; ++k) P.gc[k] = (real*)(c->ws + c->off_gs2[k]);
   return P;
 }
 
@@ -121,7 +130,10 @@ template <typename real>
 static lf_status split_init(lf_case* c, const double* dT) {
   hipStream_t s = c->ctx->stream;
   const lf::SplitPtrs<real> P = split_ptrs<real>(c);
-  HIP_TRY(lf::launch_split_init<real>(c->sg, P, c->sp, dT, s));
+  if (c->sg.gs2)
+    HIP_TRY(lf::launch_gs2_init<real>(c->sg, P, c->sp, dT, s));
+  else
+    HIP_TRY(lf::launch_split_init<real>(c->sg, P, c->sp, dT, s));
   real* dense = (real*)(c->ws + c->off_dense);
   HIP_TRY(lf::launch_split_output<real>(c->sg, P, c->sp, 0, dense, s));
   const size_t n = (size_t)c->sg.nx * c->sg.ny;
@@ -135,6 +147,18 @@ template <typename real>
 static lf_status split_steps(lf_case* c, int64_t n) {
   hipStream_t s = c->ctx->stream;
   const lf::SplitPtrs<real> P = split_ptrs<real>(c);
+  if (c->sg.gs2) {
+    // lattice steps; after every S-th (counted since init) one energy step,
+    // which reads the moments of that lattice step
+    for (int64_t k = 0; k < n; ++k) {
+      const bool energy = (c->steps + k + 1) % c->gs2_S == 0;
+      HIP_TRY(lf::launch_gs2_lbm<real>(c->sg, P, c->sp, c->cur, (energy || k == n - 1) ? 1 : 0, s));
+      c->cur ^= 1;
+      if (energy) HIP_TRY(lf::launch_gs2_energy<real>(c->sg, P, c->sp, c->gs2_S, c->gs2_K, s));
+    }
+    c->steps += n;
+    return LF_OK;
+  }
   for (int64_t k = 0; k < n; ++k) {
     HIP_TRY(lf::launch_split_step<real>(c->sg, P, c->sp, c->cur, k == n - 1 ? 1 : 0, s));
     c->cur ^= 1;
@@ -212,8 +236,10 @@ lf_status lf_case_create(lf_ctx* ctx, const lf_case_desc* d, lf_case** out) {
   if (d->precision != LF_F32 && d->precision != LF_F64)
     return fail(LF_EINVAL, "precision must be LF_F32 or LF_F64");
   if (d->mode != LF_MODE_HYBRID && d->mode != LF_MODE_SPLIT && d->mode != LF_MODE_PURE_FV &&
-      d->mode != LF_MODE_PURE_LBM)
+      d->mode != LF_MODE_PURE_LBM && d->mode != LF_MODE_HYBRID_GS2)
     return fail(LF_EINVAL, "mode %d unknown", d->mode);
+  if (d->mode == LF_MODE_HYBRID_GS2 && (d->nx % 2 || d->ny % 2))
+    return fail(LF_EINVAL, "grid setting 2 needs even nx, ny (got %d, %d)", d->nx, d->ny);
   if (d->mode == LF_MODE_SPLIT) {
     if (d->nx % 2 || d->nx < 12)
       return fail(LF_EINVAL, "split mode needs an even nx >= 12 (got %d)", d->nx);
@@ -249,7 +275,18 @@ lf_status lf_case_create(lf_ctx* ctx, const lf_case_desc* d, lf_case** out) {
     G.ny = d->ny;
     G.fv_only = d->mode == LF_MODE_PURE_FV;
     G.lbm_only = d->mode == LF_MODE_PURE_LBM;
-    if (G.fv_only) {  // FV cells 0 .. nx-1, wall faces 0 and nx
+    G.gs2 = d->mode == LF_MODE_HYBRID_GS2;
+    if (G.gs2) {  // lattice on all nodes, temperature on 2 x 2 blocks
+      G.s = G.ib = G.nx;
+      G.c0 = G.nx + 2;
+      G.pL = (G.nx + 63) / 64 * 64;
+      G.pF = 0;
+      G.NXc = G.nx / 2;
+      G.NYc = G.ny / 2;
+      G.pC = (G.NXc + 63) / 64 * 64;
+      c->gs2_S = G.nx;  // 2NX lattice steps per energy step
+      c->gs2_K = 4;
+    } else if (G.fv_only) {  // FV cells 0 .. nx-1, wall faces 0 and nx
       G.s = G.c0 = G.ib = 0;
       G.pL = 0;
       G.pF = (G.nx + 3 + 63) / 64 * 64;
@@ -313,7 +350,7 @@ static lf_status apply_lattice(lf_case* c, double nu, double alpha, double gbeta
   const double tau = 3.0 * nu + 0.5;  // Eq 15 with c_s^2 = 1/3, Eq 42
   lf_status st = check_stable(tau, alpha);
   if (st != LF_OK) return st;
-  if (c->split && !c->sg.lbm_only && nu > 1.0 / 12.0)
+  if (c->split && !c->sg.lbm_only && !c->sg.gs2 && nu > 1.0 / 12.0)
     return fail(LF_EUNSTABLE, "nu = %.6g: the explicit artificial-compressibility FV zone is "
                 "linearly stable only for nu <= 1/12", nu);
   if (c->split && (gx != 0.0 || gy != 0.0))
@@ -398,7 +435,7 @@ extern "C" {
 lf_status lf_case_set_physics(lf_case* c, const lf_physics* ph) {
   if (!c || !ph) return fail(LF_EINVAL, "NULL argument");
   double prm[8];
-  lf_status st = lf_derive_params(ph, c->g.ny, c->split, prm);
+  lf_status st = lf_derive_params(ph, c->g.ny, c->split && !c->sg.gs2, prm);
   if (st != LF_OK) return st;
   st = apply_lattice(c, prm[1], prm[3], prm[5], prm[6], ph->body_gx, ph->body_gy, ph->conv);
   if (st != LF_OK) return st;
@@ -437,6 +474,16 @@ lf_status lf_case_set_wall(lf_case* c, int side, const lf_wall* w) {
     c->w.tfix[side] = w->thermal == LF_T_DIRICHLET;
     c->w.Tw[side] = w->T_wall;
   }
+  return LF_OK;
+}
+
+lf_status lf_case_set_subcycle(lf_case* c, int lattice_steps, int sweeps) {
+  if (!c) return fail(LF_EINVAL, "NULL case");
+  if (!c->split || !c->sg.gs2) return fail(LF_EINVAL, "set_subcycle applies to LF_MODE_HYBRID_GS2");
+  if (lattice_steps < 0 || sweeps < 0 || sweeps > 4096)
+    return fail(LF_EINVAL, "lattice_steps >= 0 and 0 <= sweeps <= 4096 (0: default)");
+  c->gs2_S = lattice_steps > 0 ? lattice_steps : c->sg.nx;
+  c->gs2_K = sweeps > 0 ? sweeps : 4;
   return LF_OK;
 }
 
@@ -817,7 +864,7 @@ lf_status lf_case_mass(lf_case* c, double* sum_f, double* sum_T) {
     // populations of the LBM zone (nodes 0 .. ib, all nx nodes without an FV
     // zone); T summed over the whole cavity from the output field
     lf::Grid gl;
-    gl.nx = c->sg.lbm_only ? c->sg.nx : c->sg.ib + 1;
+    gl.nx = (c->sg.lbm_only || c->sg.gs2) ? c->sg.nx : c->sg.ib + 1;
     gl.ny = c->sg.ny;
     gl.pitch = c->sg.pL;
     gl.plane = (long long)c->sg.pL * c->sg.ny;

@@ -128,9 +128,13 @@ namespace lf {
 // Single-method cavities use the same zone kernels: fv_only (s = c0 = 0, a
 // wall on the FV zone's west side, no LBM zone) or lbm_only (s = ib = nx, a
 // wall on the LBM zone's east side, no FV zone).
+// gs2: grid setting 2 of the coupled method (lattice on all nx x ny nodes,
+// temperature on the NXc x NYc coarse control volumes of 2 x 2 nodes, row
+// pitch pC), with s = ib = nx like lbm_only.
 struct SplitGeom {
   int nx, ny, s, c0, ib, pL, pF;
   int fv_only, lbm_only;
+  int gs2, NXc, NYc, pC;
 };
 
 template <typename real>
@@ -144,6 +148,9 @@ struct SplitPtrs {
   real* T[2];   // centres
   real* p;      // centres
   double* iface;  // [0] rho0, [1] p_bar, from [8] two sums per 256 rows
+  // grid setting 2, NYc rows * pC each: T (iterate A), T (iterate B),
+  // a_P, a_W, a_E, a_S, a_N, b, and the Thomas sweep's c', r'
+  real* gc[10];
 };
 
 struct SplitParams {
@@ -164,6 +171,20 @@ hipError_t launch_split_step(const SplitGeom& G, const SplitPtrs<real>& P, const
 template <typename real>
 hipError_t launch_split_init(const SplitGeom& G, const SplitPtrs<real>& P, const SplitParams& S,
                              const double* T0, hipStream_t s);
+// Grid setting 2: one lattice step (mom_all: write rho, u, v of every node,
+// which the energy step and the output read); one energy step of length dt
+// lattice steps with K line sweeps, then the node temperatures; the coarse
+// temperature from T0 (dense [ny][nx] doubles in device memory, or null)
+// as the mean of each 2 x 2 block, then the node temperatures.
+template <typename real>
+hipError_t launch_gs2_lbm(const SplitGeom& G, const SplitPtrs<real>& P, const SplitParams& S,
+                          int cur, int mom_all, hipStream_t s);
+template <typename real>
+hipError_t launch_gs2_energy(const SplitGeom& G, const SplitPtrs<real>& P, const SplitParams& S,
+                             int dt, int K, hipStream_t s);
+template <typename real>
+hipError_t launch_gs2_init(const SplitGeom& G, const SplitPtrs<real>& P, const SplitParams& S,
+                           const double* T0, hipStream_t s);
 // Dense rho, u, v, T planes ([4][ny][nx]) of the current state.
 template <typename real>
 hipError_t launch_split_output(const SplitGeom& G, const SplitPtrs<real>& P, const SplitParams& S,

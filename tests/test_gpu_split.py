@@ -216,5 +216,5 @@ def test_pure_mode_errors(lf, ctx):
             g.set_wall(lf.N, lf.WALL_NOSLIP, 0.05, lf.T_ADIABATIC, 0.0)
         assert e.value.status == lf.LF_ENOTIMPL
     with pytest.raises(lf.LFError) as e:
-        lf.Case(ctx, 32, 32, mode=4)
+        lf.Case(ctx, 32, 32, mode=5)
     assert e.value.status == lf.LF_EINVAL
