@@ -873,16 +873,21 @@ __global__ __launch_bounds__(256) void k_gs2_assemble(SplitArgs<real> a, int dt)
 template <typename real>
 __device__ __forceinline__ void thomas_line(const SplitArgs<real>& a, int base, int step, int n,
                                             int lo_k, int up_k, int c1_k, int c2_k, int d1, int d2,
-                                            const real* X0, real* X) {
-  const real* aP = a.gc[G2_AP];
-  const real* L = a.gc[lo_k];
-  const real* U = a.gc[up_k];
-  const real* C1 = a.gc[c1_k];
-  const real* C2 = a.gc[c2_k];
-  const real* b = a.gc[G2_B];
-  real* cp = a.gc[G2_CP];
-  real* rp = a.gc[G2_RP];
+                                            const real* __restrict__ X0, real* __restrict__ X) {
+  // distinct planes: restrict lets the unrolled loop issue later unknowns'
+  // loads before earlier unknowns' stores
+  const real* __restrict__ aP = a.gc[G2_AP];
+  const real* __restrict__ L = a.gc[lo_k];
+  const real* __restrict__ U = a.gc[up_k];
+  const real* __restrict__ C1 = a.gc[c1_k];
+  const real* __restrict__ C2 = a.gc[c2_k];
+  const real* __restrict__ b = a.gc[G2_B];
+  real* __restrict__ cp = a.gc[G2_CP];
+  real* __restrict__ rp = a.gc[G2_RP];
   real cprev = real(0), rprev = real(0);
+  // unrolled so that the loads of several unknowns are in flight at once:
+  // only c' and r' carry from one unknown to the next
+#pragma unroll 8
   for (int k = 0; k < n; ++k) {
     const int o = base + k * step;
     const real c1 = C1[o], c2 = C2[o];
@@ -906,6 +911,7 @@ __device__ __forceinline__ void thomas_line(const SplitArgs<real>& a, int base, 
   }
   real x = rprev;
   X[base + (n - 1) * step] = x;
+#pragma unroll 8
   for (int k = n - 2; k >= 0; --k) {
     const int o = base + k * step;
     x = rp[o] - cp[o] * x;
