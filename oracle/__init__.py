@@ -100,6 +100,7 @@ def lib() -> ctypes.CDLL:
             L.dd_steps.argtypes = [vp]
             L.dd_init_uniform_flow.argtypes = [vp, dp, ctypes.c_double, ctypes.c_double]
             L.dd_set_fv.argtypes = [vp, dp, dp, dp]
+            L.dd_set_gdir.argtypes = [vp, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -291,6 +292,12 @@ class DDCase:
         p = physics_params(Ra, Pr, self.ny, U_char, split=True)
         self.params = p
         return self.set_lattice(p["nu"], p["alpha"], p["gbeta"], T_ref)
+
+    def set_gravity_axis(self, axis: str):
+        """'y' (default: gravity along -y) or 'x' (gravity along -x, buoyancy
+        on the x-faces): the horizontally divided cavity stored transposed."""
+        lib().dd_set_gdir(self._h, 1 if axis == "x" else 0)
+        return self
 
     def set_thermal(self, side, fixed: bool, T_wall=0.0):
         lib().dd_set_wall(self._h, int(side), 0.0, 1 if fixed else 0, float(T_wall))

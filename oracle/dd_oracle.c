@@ -76,6 +76,8 @@ typedef struct dd_case {
   double nu, alpha, gbeta, T_ref, tau, tauT, gx;
   int tfix[4];
   double Tw[4];
+  int gdir; /* buoyancy along +y (0, gravity -y) or along +x (1, gravity -x):
+               the horizontally divided cavity of Fig. 17b, stored transposed */
   int conv;
   /* LBM zone, [q][j][i] / [j][i] with nl columns */
   double *f, *fpre, *g, *gpre;
@@ -354,6 +356,10 @@ static void fv_step(dd_case* c) {
                    U_at(c, c->u, x, j + 1) + U_at(c, c->u, x, j - 1) - 4.0 * uc;
       double dp = P_at(c, c->p, x, j) - P_at(c, c->p, x - 1, j);
       FC(c, c->us, j, x) = uc - (Fc[1] - Fc[0]) - (Gc[1] - Gc[0]) + nu * lap - dp + c->gx;
+      if (c->gdir) { /* buoyancy on the x-face from the two adjacent cells */
+        double Tfx = 0.5 * (T_at(c, c->T, x - 1, j) + T_at(c, c->T, x, j));
+        FC(c, c->us, j, x) += c->gbeta * (Tfx - c->T_ref);
+      }
     }
     if (!c->xper) {
       FC(c, c->us, j, c->c0) = FC(c, c->u, j, c->c0); /* wall 0 or prescribed */
@@ -385,8 +391,8 @@ static void fv_step(dd_case* c) {
                    V_at(c, c->v, x, jf + 1) + V_at(c, c->v, x, jf - 1) - 4.0 * vc;
       double dp = P_at(c, c->p, x, jf) - P_at(c, c->p, x, jf - 1);
       double Tf = 0.5 * (T_at(c, c->T, x, jf - 1) + T_at(c, c->T, x, jf));
-      FVF(c, c->vs, jf, x) = vc - (Gc[1] - Gc[0]) - (Fc[1] - Fc[0]) + nu * lap - dp +
-                             c->gbeta * (Tf - c->T_ref);
+      FVF(c, c->vs, jf, x) = vc - (Gc[1] - Gc[0]) - (Fc[1] - Fc[0]) + nu * lap - dp;
+      if (!c->gdir) FVF(c, c->vs, jf, x) += c->gbeta * (Tf - c->T_ref);
     }
   }
   if (!c->yper)
@@ -494,6 +500,10 @@ static void lbm_collide(dd_case* c) {
       feq9(r, ux, uy, fe);
       geq5(t, ux, uy, ge);
       double Gx = c->gx, Gy = c->gbeta * (t - c->T_ref);
+      if (c->gdir) {
+        Gx = c->gx + c->gbeta * (t - c->T_ref);
+        Gy = 0.0;
+      }
       for (int q = 0; q < Q9; ++q) {
         double F = 3.0 * ((DX9[q] - ux) * Gx + (DY9[q] - uy) * Gy) * fe[q] / r;
         double fp = FL(c, c->fpre, q, j, i);
@@ -773,6 +783,12 @@ int dd_set_fv(dd_case* c, const double* p, const double* u, const double* v) {
 int dd_set_iface(dd_case* c, int kind) {
   if (kind != DD_NEQ && kind != DD_FDGRAD) return -1;
   c->iface = kind;
+  return 0;
+}
+
+int dd_set_gdir(dd_case* c, int gdir) {
+  if (gdir < 0 || gdir > 1) return -1;
+  c->gdir = gdir;
   return 0;
 }
 
