@@ -258,6 +258,16 @@ def main():
                               "frac_of_8TBs": round(ach / HBM_PEAK_GBS, 4),
                               "U_char": sp.params()["U_char"]}
         del sp
+        # the horizontal division of the same cavity (Fig. 17b)
+        sh = lf.Case(ctx, m, m, "f32", mode=lf.MODE_SPLIT_H).set_physics(1e6, 0.71)
+        sh.set_cavity_walls().init(perturbation(m, m, SEED_C2))
+        sh.step(10)
+        a_ms, _, _ = sh.profile_steps(200)
+        out["split_h_point"] = {"workload": f"{m}x{m} cavity divided horizontally (LBM lower half, "
+                                            "FV upper half), Ra 1e6, Pr 0.71, FP32, NEE interface",
+                                "ms_per_step": round(a_ms, 5),
+                                "mlups": round(m * m / (a_ms * 1e-3) / 1e6, 1)}
+        del sh
         # the single methods of the same comparison on the whole cavity
         # (algorithmic bytes: FV 32 B/cell, LBM 112 B/node)
         for key, mode, bpn, what in (("pure_fv_point", lf.MODE_PURE_FV, 32.0, "FV only"),

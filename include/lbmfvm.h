@@ -13,7 +13,11 @@
  *     on the west part, FVM on the east part, three shared columns, coupled
  *     through non-equilibrium extrapolation (Eq 60, Eq 94-95) or the
  *     finite-difference velocity-gradient reconstruction (Eq 70-72) with the
- *     density transfer of Eq 91-93.
+ *     density transfer of Eq 91-93.  LF_MODE_SPLIT_H divides the cavity
+ *     horizontally instead (Fig. 17b: LBM in the lower half, FVM in the
+ *     upper half; stored transposed with gravity along the stored -x, so
+ *     the same kernels run it; fields, walls and Nusselt numbers keep the
+ *     caller's orientation).
  *   - The two single methods of the Sec. 4.2 comparison on the whole cavity,
  *     with the zone kernels of Mode DD: LF_MODE_PURE_FV (staggered FVM,
  *     explicit momentum with artificial compressibility, Eq 74-76) and
@@ -75,7 +79,8 @@ enum {
   LF_MODE_SPLIT = 1,
   LF_MODE_PURE_FV = 2,
   LF_MODE_PURE_LBM = 3,
-  LF_MODE_HYBRID_GS2 = 4
+  LF_MODE_HYBRID_GS2 = 4,
+  LF_MODE_SPLIT_H = 5
 };
 enum { LF_IFACE_NEQ_EXTRAP = 0, LF_IFACE_FD_GRADIENT = 1 };
 enum { LF_CONV_QUICK = 0, LF_CONV_CENTRAL = 1, LF_CONV_UPWIND = 2 };
@@ -94,10 +99,11 @@ typedef struct lf_case lf_case;
 typedef struct {
   int nx, ny;
   int precision; /* LF_F32 or LF_F64                                        */
-  int mode;      /* LF_MODE_HYBRID, LF_MODE_SPLIT, LF_MODE_PURE_FV,
-                    LF_MODE_PURE_LBM or LF_MODE_HYBRID_GS2 (all but the
-                    first: walls at rest, no periodic sides, start from
-                    rest; LF_MODE_HYBRID_GS2 needs even nx and ny)         */
+  int mode;      /* LF_MODE_HYBRID, LF_MODE_SPLIT, LF_MODE_SPLIT_H,
+                    LF_MODE_PURE_FV, LF_MODE_PURE_LBM or LF_MODE_HYBRID_GS2
+                    (all but the first: walls at rest, no periodic sides,
+                    start from rest; LF_MODE_HYBRID_GS2 needs even nx and
+                    ny, the split modes an even divided extent >= 12)      */
   int split_col; /* Mode DD: first FV cell is split_col - 1; 0 => nx/2      */
   int overlap;   /* Mode DD: shared columns; 0 => 3 (the only value)        */
   int iface;     /* Mode DD: LF_IFACE_NEQ_EXTRAP or LF_IFACE_FD_GRADIENT
@@ -156,8 +162,9 @@ lf_status lf_ctx_set_band(lf_ctx* ctx, int rows);
  * grid setting 1); the split mode and the single-method cavities as listed
  * at the top.  Defaults after create: side-heated cavity walls (west
  * T = +1/2, east T = -1/2, south/north adiabatic, all no-slip at rest).
- * LF_EINVAL for an unknown mode, nx or ny < 8, an odd nx or nx < 12 in the
- * split mode, or a grid too large for 32-bit plane indexing.              */
+ * LF_EINVAL for an unknown mode, nx or ny < 8, an odd or < 12 divided
+ * extent (nx for LF_MODE_SPLIT, ny for LF_MODE_SPLIT_H), odd nx or ny for
+ * LF_MODE_HYBRID_GS2, or a grid too large for 32-bit plane indexing.      */
 lf_status lf_case_create(lf_ctx* ctx, const lf_case_desc* desc, lf_case** out);
 lf_status lf_case_destroy(lf_case* c);
 lf_status lf_case_workspace_bytes(const lf_case* c, size_t* bytes);

@@ -38,7 +38,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 LF_OK, LF_EINVAL, LF_ENOMEM, LF_EWORKSPACE, LF_EDEVICE, LF_EUNSTABLE, LF_EDIVERGED, \
     LF_ENOTCONV, LF_ESTATE, LF_ENOTIMPL = range(10)
 F32, F64 = 0, 1
-MODE_HYBRID, MODE_SPLIT, MODE_PURE_FV, MODE_PURE_LBM, MODE_HYBRID_GS2 = 0, 1, 2, 3, 4
+MODE_HYBRID, MODE_SPLIT, MODE_PURE_FV, MODE_PURE_LBM, MODE_HYBRID_GS2, MODE_SPLIT_H = range(6)
 IFACE_NEQ_EXTRAP, IFACE_FD_GRADIENT = 0, 1
 CONV_QUICK, CONV_CENTRAL, CONV_UPWIND = 0, 1, 2
 WALL_NOSLIP, WALL_PERIODIC = 0, 1
@@ -247,7 +247,8 @@ class Context:
 
 class Case:
     """One cavity: Mode H (grid setting 1, or 2 with MODE_HYBRID_GS2), the split
-    LBM|FV mode, or one of the single methods (MODE_PURE_FV, MODE_PURE_LBM).
+    LBM|FV mode divided vertically (MODE_SPLIT) or horizontally (MODE_SPLIT_H),
+    or one of the single methods (MODE_PURE_FV, MODE_PURE_LBM).
     Fields are numpy arrays of shape (ny, nx)."""
 
     def __init__(self, ctx: Context, nx: int, ny: int, precision: str = "f32",

@@ -110,6 +110,8 @@ struct SplitArgs {
   // grid setting 2: coarse planes (see SplitPtrs::gc), sizes and pitch
   real* __restrict__ gc[10];
   int NXc, NYc, pC;
+  int gdir;        // gravity along -y (0) or along -x (1, the transposed horizontal division)
+  int transposed;  // fields are handed in and out transposed (user x = stored y)
   int west_wall;  // FV zone closed by a wall at x = 0 (FV-only cavity)
   int east_wall;  // LBM zone closed by a wall at x = nx (LBM-only cavity)
   int kind, mom_all;
@@ -359,6 +361,10 @@ __device__ __forceinline__ void momentum_at(const SplitArgs<real>& a, const Acc&
       const real lap = F.u(1, 0) + F.u(-1, 0) + F.u(0, 1) + F.u(0, -1) - real(4) * uc;
       const real dp = F.p(0, 0) - F.p(-1, 0);
       out = uc - (Fc[1] - Fc[0]) - (Gc[1] - Gc[0]) + nu * lap - dp;
+      if (a.gdir) {  // buoyancy on the x-face from the two adjacent cells
+        const real Tfx = real(0.5) * (F.T(-1, 0) + F.T(0, 0));
+        out = out + a.gbeta * (Tfx - a.Tref);
+      }
     }
     a.us[o] = out;
   }
@@ -383,7 +389,8 @@ __device__ __forceinline__ void momentum_at(const SplitArgs<real>& a, const Acc&
       const real lap = F.v(1, 0) + F.v(-1, 0) + F.v(0, 1) + F.v(0, -1) - real(4) * vc;
       const real dp = F.p(0, 0) - F.p(0, -1);
       const real Tf = real(0.5) * (F.T(0, -1) + F.T(0, 0));
-      out = vc - (Gc[1] - Gc[0]) - (Fc[1] - Fc[0]) + nu * lap - dp + a.gbeta * (Tf - a.Tref);
+      out = vc - (Gc[1] - Gc[0]) - (Fc[1] - Fc[0]) + nu * lap - dp;
+      if (!a.gdir) out = out + a.gbeta * (Tf - a.Tref);
     }
     a.vs[o] = out;
   }
@@ -488,15 +495,17 @@ template <typename real>
 __device__ __forceinline__ void collide_f(const SplitArgs<real>& a, real f[9], real drho, real ux,
                                           real uy, real T) {
   const real rho = real(1) + drho;
-  const real Gy = a.gbeta * (T - a.Tref);
-  const real Gu = Gy * uy;
+  // buoyancy G along +y, or along +x when gravity points along -x
+  const real G = a.gbeta * (T - a.Tref);
+  const real Gu = G * (a.gdir ? ux : uy);
   const real usq = real(1.5) * fmad(ux, ux, uy * uy);
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
     const real eu = real(ex9(q)) * ux + real(ey9(q)) * uy;
     const real P = fmad(real(4.5) * eu, eu, real(3) * eu) - usq;
     const real fe = w9<real>(q) * fmad(rho, P, drho);
-    const real c = (real(3) * w9<real>(q)) * (real(ey9(q)) * Gy - Gu);
+    const real eG = real(a.gdir ? ex9(q) : ey9(q)) * G;
+    const real c = (real(3) * w9<real>(q)) * (eG - Gu);
     f[q] = fmad(a.omega, fe - f[q], f[q]) + fmad(c, P, c);
   }
 }
@@ -646,7 +655,9 @@ __global__ __launch_bounds__(256) void k_dd_output(SplitArgs<real> a, real* __re
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (x >= a.nx) return;
-  const int n = a.nx * a.ny, d = j * a.nx + x;
+  const int n = a.nx * a.ny;
+  // transposed: the caller's (x, y) is the stored (j, x), its u the stored v
+  const int d = a.transposed ? x * a.ny + j : j * a.nx + x;
   real r, u, v, t;
   if (x < a.s) {
     const int o = j * a.pL + x;
@@ -663,8 +674,8 @@ __global__ __launch_bounds__(256) void k_dd_output(SplitArgs<real> a, real* __re
     r = real(1) + real(3) * a.p[o];
   }
   out[d] = r;
-  out[n + d] = u;
-  out[2 * n + d] = v;
+  out[n + d] = a.transposed ? v : u;
+  out[2 * n + d] = a.transposed ? u : v;
   out[3 * n + d] = t;
 }
 
@@ -673,7 +684,8 @@ __global__ __launch_bounds__(256) void k_dd_init(SplitArgs<real> a, const double
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (j >= a.ny) return;
-  const double t0 = (x < a.nx && T0) ? T0[j * a.nx + x] : 0.0;
+  const auto t0_at = [&](int xx) { return a.transposed ? T0[xx * a.ny + j] : T0[j * a.nx + xx]; };
+  const double t0 = (x < a.nx && T0) ? t0_at(x) : 0.0;
   if (x < a.nl) {
     const int o = j * a.pL + x;
     real* f = const_cast<real*>(a.fin);
@@ -696,7 +708,7 @@ __global__ __launch_bounds__(256) void k_dd_init(SplitArgs<real> a, const double
     u[o] = real(0);
     a.us[o] = real(0);
     a.p[o] = real(0);
-    T[o] = real((xf < a.nx && xf >= 0 && T0) ? T0[j * a.nx + xf] : 0.0);
+    T[o] = real((xf < a.nx && xf >= 0 && T0) ? t0_at(xf) : 0.0);
     a.Tn[o] = T[o];
     v[o] = real(0);
     a.vs[o] = real(0);
@@ -982,6 +994,8 @@ static SplitArgs<real> make_args(const SplitGeom& G, const SplitPtrs<real>& P, c
   a.NXc = G.NXc;
   a.NYc = G.NYc;
   a.pC = G.pC;
+  a.gdir = G.gdir;
+  a.transposed = G.transposed;
   a.west_wall = G.fv_only;
   a.east_wall = G.lbm_only;
   a.kind = S.kind;

@@ -118,11 +118,11 @@ static lf::SplitPtrs<real> split_ptrs(lf_case* c) {
 
 // dense [ny][nx] planes used by the reductions in the split mode
 static lf::Grid dense_grid(const lf_case* c) {
-  lf::Grid g;
-  g.nx = c->sg.nx;
-  g.ny = c->sg.ny;
-  g.pitch = c->sg.nx;
-  g.plane = (long long)c->sg.nx * c->sg.ny;
+  lf::Grid g;  // the caller's orientation
+  g.nx = c->g.nx;
+  g.ny = c->g.ny;
+  g.pitch = c->g.nx;
+  g.plane = (long long)c->g.nx * c->g.ny;
   return g;
 }
 
@@ -236,15 +236,17 @@ lf_status lf_case_create(lf_ctx* ctx, const lf_case_desc* d, lf_case** out) {
   if (d->precision != LF_F32 && d->precision != LF_F64)
     return fail(LF_EINVAL, "precision must be LF_F32 or LF_F64");
   if (d->mode != LF_MODE_HYBRID && d->mode != LF_MODE_SPLIT && d->mode != LF_MODE_PURE_FV &&
-      d->mode != LF_MODE_PURE_LBM && d->mode != LF_MODE_HYBRID_GS2)
+      d->mode != LF_MODE_PURE_LBM && d->mode != LF_MODE_HYBRID_GS2 && d->mode != LF_MODE_SPLIT_H)
     return fail(LF_EINVAL, "mode %d unknown", d->mode);
   if (d->mode == LF_MODE_HYBRID_GS2 && (d->nx % 2 || d->ny % 2))
     return fail(LF_EINVAL, "grid setting 2 needs even nx, ny (got %d, %d)", d->nx, d->ny);
-  if (d->mode == LF_MODE_SPLIT) {
-    if (d->nx % 2 || d->nx < 12)
-      return fail(LF_EINVAL, "split mode needs an even nx >= 12 (got %d)", d->nx);
-    if (d->split_col != 0 && d->split_col != d->nx / 2)
-      return fail(LF_ENOTIMPL, "split_col must be nx/2 (0 selects it)");
+  if (d->mode == LF_MODE_SPLIT || d->mode == LF_MODE_SPLIT_H) {
+    // the divided extent: nx (vertical division) or ny (horizontal)
+    const int ext = d->mode == LF_MODE_SPLIT ? d->nx : d->ny;
+    if (ext % 2 || ext < 12)
+      return fail(LF_EINVAL, "the divided extent must be even and >= 12 (got %d)", ext);
+    if (d->split_col != 0 && d->split_col != ext / 2)
+      return fail(LF_ENOTIMPL, "split_col must be half the divided extent (0 selects it)");
     if (d->overlap != 0 && d->overlap != 3) return fail(LF_ENOTIMPL, "overlap must be 3");
     if (d->iface != LF_IFACE_NEQ_EXTRAP && d->iface != LF_IFACE_FD_GRADIENT)
       return fail(LF_EINVAL, "bad iface %d", d->iface);
@@ -271,8 +273,10 @@ lf_status lf_case_create(lf_ctx* ctx, const lf_case_desc* d, lf_case** out) {
   if (d->mode != LF_MODE_HYBRID) {
     c->split = true;
     lf::SplitGeom& G = c->sg;
-    G.nx = d->nx;
-    G.ny = d->ny;
+    // the horizontally divided cavity is stored transposed, gravity along -x
+    G.transposed = G.gdir = d->mode == LF_MODE_SPLIT_H;
+    G.nx = G.transposed ? d->ny : d->nx;
+    G.ny = G.transposed ? d->nx : d->ny;
     G.fv_only = d->mode == LF_MODE_PURE_FV;
     G.lbm_only = d->mode == LF_MODE_PURE_LBM;
     G.gs2 = d->mode == LF_MODE_HYBRID_GS2;
@@ -296,7 +300,7 @@ lf_status lf_case_create(lf_ctx* ctx, const lf_case_desc* d, lf_case** out) {
       G.pL = (G.nx + 63) / 64 * 64;
       G.pF = 0;
     } else {
-      G.s = d->nx / 2;
+      G.s = G.nx / 2;
       G.c0 = G.s - 1;
       G.ib = G.s + 1;
       G.pL = (G.ib + 1 + 63) / 64 * 64;
@@ -304,8 +308,10 @@ lf_status lf_case_create(lf_ctx* ctx, const lf_case_desc* d, lf_case** out) {
     }
     c->sp.kind = d->iface;
     c->sp.tau = c->sp.tauT = 1.0;
-    c->sp.tfix[LF_SIDE_W] = 1; c->sp.Tw[LF_SIDE_W] = 0.5;
-    c->sp.tfix[LF_SIDE_E] = 1; c->sp.Tw[LF_SIDE_E] = -0.5;
+    // stored sides of the caller's hot west and cold east walls
+    const int sw = G.transposed ? LF_SIDE_S : LF_SIDE_W, se = G.transposed ? LF_SIDE_N : LF_SIDE_E;
+    c->sp.tfix[sw] = 1; c->sp.Tw[sw] = 0.5;
+    c->sp.tfix[se] = 1; c->sp.Tw[se] = -0.5;
     layout_split(c);
   } else {
     c->tcomp = d->precision == LF_F32 && d->tcomp;
@@ -456,8 +462,11 @@ lf_status lf_case_set_wall(lf_case* c, int side, const lf_wall* w) {
   if (c->split) {
     if (per) return fail(LF_ENOTIMPL, "periodic sides are not available in the split mode");
     if (w->u_wall != 0.0) return fail(LF_ENOTIMPL, "moving walls are not available in the split mode");
-    c->sp.tfix[side] = w->thermal == LF_T_DIRICHLET;
-    c->sp.Tw[side] = w->T_wall;
+    // stored side (transposed storage: W, E, S, N -> S, N, W, E)
+    static const int tmap[4] = {LF_SIDE_S, LF_SIDE_N, LF_SIDE_W, LF_SIDE_E};
+    const int ss = c->sg.transposed ? tmap[side] : side;
+    c->sp.tfix[ss] = w->thermal == LF_T_DIRICHLET;
+    c->sp.Tw[ss] = w->T_wall;
   }
   const int other = side ^ 1;  // W<->E, S<->N
   const bool axis_per = side < 2 ? c->w.xper : c->w.yper;

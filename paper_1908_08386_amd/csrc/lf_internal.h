@@ -135,6 +135,9 @@ struct SplitGeom {
   int nx, ny, s, c0, ib, pL, pF;
   int fv_only, lbm_only;
   int gs2, NXc, NYc, pC;
+  // horizontally divided cavity: stored transposed (the caller's x is the
+  // stored y) with gravity along the stored -x
+  int gdir, transposed;
 };
 
 template <typename real>

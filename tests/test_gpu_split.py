@@ -216,5 +216,66 @@ def test_pure_mode_errors(lf, ctx):
             g.set_wall(lf.N, lf.WALL_NOSLIP, 0.05, lf.T_ADIABATIC, 0.0)
         assert e.value.status == lf.LF_ENOTIMPL
     with pytest.raises(lf.LFError) as e:
-        lf.Case(ctx, 32, 32, mode=5)
+        lf.Case(ctx, 32, 32, mode=99)
+    assert e.value.status == lf.LF_EINVAL
+
+
+def h_pair(lf, ctx, nx, ny, prec, iface, Ra=1e5, Pr=0.71, T0=None):
+    """The horizontally divided cavity (LBM below, FV above) through the
+    library, and the oracle's vertically divided cavity stored transposed
+    with gravity along -x."""
+    g = lf.Case(ctx, nx, ny, prec, mode=lf.MODE_SPLIT_H, iface=iface)
+    g.set_physics(Ra, Pr).set_cavity_walls().init(T0)
+    p = g.params()
+    o = oracle.DDCase(ny, nx, oracle.SPLIT, iface)
+    o.set_lattice(p["nu"], p["alpha"], p["gbeta"], 0.0).set_gravity_axis("x")
+    o.set_thermal(oracle.S, True, 0.5).set_thermal(oracle.N, True, -0.5)
+    o.set_thermal(oracle.W, False).set_thermal(oracle.E, False)
+    o.init(None if T0 is None else np.ascontiguousarray(T0.T))
+    return g, o
+
+
+def h_check(g, o, tol):
+    pairs = (("u", "v"), ("v", "u"), ("T", "T"), ("rho", "rho"))
+    errs = {}
+    for fg, fo in pairs:
+        a, b = g.fetch(fg), o.fetch(fo).T
+        if fg == "rho":
+            a, b = a - 1, b - 1
+        errs[fg] = rel_linf(a, b)
+    for f, e in errs.items():
+        assert e <= tol, (f, e, errs)
+    T = o.fetch("T").T
+    ny = T.shape[0]
+    hot = (2.0 * ny * (0.5 - T[:, 0])).mean()
+    cold = (2.0 * ny * (T[:, -1] + 0.5)).mean()
+    nu = g.nusselt()
+    assert abs(nu["nu_hot"] - hot) <= tol * abs(hot) and abs(nu["nu_cold"] - cold) <= tol * abs(cold)
+
+
+@pytest.mark.parametrize("iface", [0, 1])
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_horizontal_division_parity(lf, ctx, iface, prec, tol):
+    """Fig. 17b's division: 48 wide, 64 high, LBM rows 0..31 (+ overlap),
+    FV above, against the oracle's transposed vertical division."""
+    oracle.set_threads(8)
+    nx, ny = 48, 64
+    T0 = perturbation(nx, ny, 61, amp=0.1)
+    g, o = h_pair(lf, ctx, nx, ny, prec, iface, T0=T0)
+    g.step(600)
+    o.step(600)
+    h_check(g, o, tol)
+
+
+def test_horizontal_division_ragged_fp64(lf, ctx):
+    """77 wide, 138 high at Ra 1e6: ragged tiles in both stored directions."""
+    oracle.set_threads(8)
+    nx, ny = 77, 138
+    T0 = perturbation(nx, ny, 62, amp=0.05)
+    g, o = h_pair(lf, ctx, nx, ny, "f64", 0, Ra=1e6, T0=T0)
+    g.step(500)
+    o.step(500)
+    h_check(g, o, 1e-10)
+    with pytest.raises(lf.LFError) as e:
+        lf.Case(ctx, 64, 65, mode=lf.MODE_SPLIT_H)  # odd divided extent
     assert e.value.status == lf.LF_EINVAL
