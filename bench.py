@@ -304,6 +304,22 @@ def main():
                             "frac_of_8TBs": round(ach / HBM_PEAK_GBS, 4)}
         del g2
 
+    if args.split_point:
+        # LBM-MCM (Sec. 6): 128^2, one Monte Carlo solve of 1024 walkers per
+        # node after every 100 lattice steps, timed over whole cycles
+        m, S, N = 128, 100, 1024
+        mc = lf.Case(ctx, m, m, "f32", mode=lf.MODE_LBM_MCM).set_physics(1e4, 0.71)
+        mc.set_cavity_walls().set_mcm(S, N).init(perturbation(m, m, SEED_C2))
+        mc.step(S)
+        a_ms, _, _ = mc.profile_steps(S)
+        out["mcm_point"] = {"workload": f"{m}x{m} cavity, LBM-MCM, Ra 1e4, Pr 0.71, FP32 lattice, "
+                                        f"{N} walkers per node, one solve per {S} lattice steps",
+                            "ms_per_cycle": round(a_ms * S, 3),
+                            "ms_per_step": round(a_ms, 5),
+                            "mlups": round(m * m / (a_ms * 1e-3) / 1e6, 1),
+                            "capped_walkers": mc.mcm_capped()}
+        del mc
+
     if args.batch_point:
         from synth_inputs import cavity_sweep
         cases = cavity_sweep(args.batch_point)

@@ -26,6 +26,10 @@
  *     lattice on all nx x ny nodes, the temperature on nx/2 x ny/2 control
  *     volumes of 2 x 2 nodes, one implicit energy step per S lattice steps
  *     (S = nx, i.e. 2NX, by default; lf_case_set_subcycle).
+ *   - LBM-MCM (LF_MODE_LBM_MCM, Sec. 6, Eq 97-102, Fig. 39): the lattice on
+ *     all nodes, the node temperatures from Monte Carlo walkers (Eq 99's
+ *     probabilities from the lattice velocity), one solve per S lattice
+ *     steps (lf_case_set_mcm).
  *
  * Conventions (all entry points):
  *   - Every call returns lf_status; LF_OK is 0.  On failure
@@ -80,7 +84,8 @@ enum {
   LF_MODE_PURE_FV = 2,
   LF_MODE_PURE_LBM = 3,
   LF_MODE_HYBRID_GS2 = 4,
-  LF_MODE_SPLIT_H = 5
+  LF_MODE_SPLIT_H = 5,
+  LF_MODE_LBM_MCM = 6
 };
 enum { LF_IFACE_NEQ_EXTRAP = 0, LF_IFACE_FD_GRADIENT = 1 };
 enum { LF_CONV_QUICK = 0, LF_CONV_CENTRAL = 1, LF_CONV_UPWIND = 2 };
@@ -100,7 +105,8 @@ typedef struct {
   int nx, ny;
   int precision; /* LF_F32 or LF_F64                                        */
   int mode;      /* LF_MODE_HYBRID, LF_MODE_SPLIT, LF_MODE_SPLIT_H,
-                    LF_MODE_PURE_FV, LF_MODE_PURE_LBM or LF_MODE_HYBRID_GS2
+                    LF_MODE_PURE_FV, LF_MODE_PURE_LBM, LF_MODE_HYBRID_GS2
+                    or LF_MODE_LBM_MCM
                     (all but the first: walls at rest, no periodic sides,
                     start from rest; LF_MODE_HYBRID_GS2 needs even nx and
                     ny, the split modes an even divided extent >= 12)      */
@@ -191,6 +197,25 @@ lf_status lf_case_get_params(const lf_case* c, double out[8]);
  * control-volume values, ghosts 2 T_w - T at fixed walls, T at adiabatic
  * ones).  LF_EINVAL in the other modes or for negative counts.             */
 lf_status lf_case_set_subcycle(lf_case* c, int lattice_steps, int sweeps);
+/* LF_MODE_LBM_MCM only (defaults 100, 256, 1908083868, 2^24): a Monte Carlo
+ * solve of the node temperatures follows every lattice step whose count
+ * since init is a multiple of lattice_steps, with `walkers` walks per node
+ * started from the node and stopped after max_steps steps.  A walker steps
+ * x+, y+, x-, y- with the link weights alpha - u, alpha - v, alpha, alpha
+ * over their sum (Eq 99-100, velocity of that lattice step; |u|, |v| <
+ * alpha keeps them positive), chosen by one uniform draw in Eq 101's order;
+ * a link through a fixed-temperature wall (half a spacing) weighs double
+ * and absorbs the walker with T_w, a step into an adiabatic wall is
+ * refused.  Draws: splitmix64, the stream of walker w at node p seeded by
+ * mix(seed + s + (1 + p walkers + w) 0x9E3779B97F4A7C15) for the s-th solve
+ * (s = 0, 1, ...).  The node temperature is the mean wall temperature of
+ * its absorbed walkers (Eq 102).  LF_EINVAL in other modes or for counts
+ * below 1; stepping fails with LF_EINVAL without a fixed-temperature wall. */
+lf_status lf_case_set_mcm(lf_case* c, int lattice_steps, int walkers, uint64_t seed,
+                          int64_t max_steps);
+/* Walkers of the last Monte Carlo solve stopped by max_steps (or by a
+ * velocity at or above alpha) instead of a wall; synchronises.             */
+lf_status lf_case_mcm_capped(lf_case* c, uint64_t* walkers);
 /* Initial state from host arrays of ny*nx doubles (NULL = 0): rho = 1,
  * f = f_eq(1, (u0, v0)), T = T0; the residual snapshot starts here.        */
 lf_status lf_case_init(lf_case* c, const double* T0, const double* u0,

@@ -38,7 +38,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 LF_OK, LF_EINVAL, LF_ENOMEM, LF_EWORKSPACE, LF_EDEVICE, LF_EUNSTABLE, LF_EDIVERGED, \
     LF_ENOTCONV, LF_ESTATE, LF_ENOTIMPL = range(10)
 F32, F64 = 0, 1
-MODE_HYBRID, MODE_SPLIT, MODE_PURE_FV, MODE_PURE_LBM, MODE_HYBRID_GS2, MODE_SPLIT_H = range(6)
+MODE_HYBRID, MODE_SPLIT, MODE_PURE_FV, MODE_PURE_LBM, MODE_HYBRID_GS2, MODE_SPLIT_H, \
+    MODE_LBM_MCM = range(7)
 IFACE_NEQ_EXTRAP, IFACE_FD_GRADIENT = 0, 1
 CONV_QUICK, CONV_CENTRAL, CONV_UPWIND = 0, 1, 2
 WALL_NOSLIP, WALL_PERIODIC = 0, 1
@@ -100,6 +101,9 @@ _SIGS = {
     "lf_case_set_wall": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(lf_wall)]),
     "lf_case_get_params": (ctypes.c_int, [_vp, _dp]),
     "lf_case_set_subcycle": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    "lf_case_set_mcm": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                       ctypes.c_int64]),
+    "lf_case_mcm_capped": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_uint64)]),
     "lf_case_init": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
     "lf_case_step": (ctypes.c_int, [_vp, _i64]),
     "lf_case_residual": (ctypes.c_int, [_vp, _dp]),
@@ -248,7 +252,8 @@ class Context:
 class Case:
     """One cavity: Mode H (grid setting 1, or 2 with MODE_HYBRID_GS2), the split
     LBM|FV mode divided vertically (MODE_SPLIT) or horizontally (MODE_SPLIT_H),
-    or one of the single methods (MODE_PURE_FV, MODE_PURE_LBM).
+    one of the single methods (MODE_PURE_FV, MODE_PURE_LBM), or LBM-MCM
+    (MODE_LBM_MCM).
     Fields are numpy arrays of shape (ny, nx)."""
 
     def __init__(self, ctx: Context, nx: int, ny: int, precision: str = "f32",
@@ -303,6 +308,19 @@ class Case:
         _check(_lib.lf_case_set_subcycle(self._h, int(lattice_steps), int(sweeps)),
                "lf_case_set_subcycle")
         return self
+
+    def set_mcm(self, lattice_steps=100, walkers=256, seed=1908083868, max_steps=1 << 24):
+        """LBM-MCM: lattice steps per Monte Carlo solve, walkers per node,
+        stream seed and the step cap of a walk."""
+        _check(_lib.lf_case_set_mcm(self._h, int(lattice_steps), int(walkers), int(seed),
+                                    int(max_steps)), "lf_case_set_mcm")
+        return self
+
+    def mcm_capped(self) -> int:
+        """Walkers of the last Monte Carlo solve stopped by the step cap."""
+        n = ctypes.c_uint64()
+        _check(_lib.lf_case_mcm_capped(self._h, ctypes.byref(n)), "lf_case_mcm_capped")
+        return n.value
 
     def set_cavity_walls(self, T_hot=0.5, T_cold=-0.5):
         self.set_wall(W, WALL_NOSLIP, 0.0, T_DIRICHLET, T_hot)

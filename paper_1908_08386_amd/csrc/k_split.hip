@@ -110,6 +110,8 @@ struct SplitArgs {
   // grid setting 2: coarse planes (see SplitPtrs::gc), sizes and pitch
   real* __restrict__ gc[10];
   int NXc, NYc, pC;
+  int* __restrict__ mcm_count;
+  unsigned long long* __restrict__ mcm_stats;
   int gdir;        // gravity along -y (0) or along -x (1, the transposed horizontal division)
   int transposed;  // fields are handed in and out transposed (user x = stored y)
   int west_wall;  // FV zone closed by a wall at x = 0 (FV-only cavity)
@@ -960,6 +962,93 @@ __global__ __launch_bounds__(256) void k_gs2_init(SplitArgs<real> a, const doubl
   a.gc[G2_TA][J * a.pC + I] = real(t);
 }
 
+// ---- LBM-MCM (Sec. 6, Eq 97-102) ------------------------------------------
+// A walker at node (i, j) steps to x+, y+, x- or y- with Eq 99's
+// probabilities from the node velocity (link weights alpha - u, alpha - v,
+// alpha, alpha over their sum, Eq 100); the link through a fixed-temperature
+// wall (half a spacing away) has its weight doubled and absorbs the walker;
+// a step into an adiabatic wall is refused.  Eq 101 picks the direction by
+// the cumulative thresholds in FP64 from one uniform draw per step.  Draws:
+// splitmix64 (Steele, Lea and Flood; Vigna's constants), draw k of walker w
+// at node p is mix(s0 + (k + 1) gamma) with s0 = mix(seed + (1 + p N + w)
+// gamma), RN = (draw >> 11) 2^-53.  Each node counts its walkers per
+// absorbing wall (integer atomics, so the estimate of Eq 102 does not depend
+// on the order in which walks finish).
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+constexpr unsigned long long kGamma = 0x9E3779B97F4A7C15ull;
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_mcm_clear(SplitArgs<real> a) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < 5 * a.nx * a.ny) a.mcm_count[k] = 0;
+  if (k == 0) a.mcm_stats[0] = 0ull;
+}
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_mcm_walk(SplitArgs<real> a, int walkers,
+                                                  unsigned long long seed, long long max_steps) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long nodes = (long long)a.nx * a.ny;
+  if (t >= nodes * walkers) return;
+  const int node = (int)(t / walkers), w = (int)(t - (long long)node * walkers);
+  int i = node % a.nx, j = node / a.nx;
+  const real* ux = a.mom + a.planeL;
+  const real* uy = a.mom + 2 * a.planeL;
+  const double al = (double)a.alpha;
+  const unsigned long long s0 =
+      mix64(seed + (1ull + (unsigned long long)node * (unsigned long long)walkers +
+                    (unsigned long long)w) * kGamma);
+  int side = -1;
+  for (long long k = 0; k < max_steps; ++k) {
+    const double rn = (double)(mix64(s0 + (unsigned long long)(k + 1) * kGamma) >> 11) *
+                      (1.0 / 9007199254740992.0);
+    const double u = (double)ux[j * a.pL + i], v = (double)uy[j * a.pL + i];
+    const double fe = (a.tfix[1] && i == a.nx - 1) ? 2.0 : 1.0;
+    const double fn = (a.tfix[3] && j == a.ny - 1) ? 2.0 : 1.0;
+    const double fw = (a.tfix[0] && i == 0) ? 2.0 : 1.0;
+    const double fs = (a.tfix[2] && j == 0) ? 2.0 : 1.0;
+    const double we = fe * (al - u), wn = fn * (al - v), ww = fw * al, ws = fs * al;
+    const double D = ((we + wn) + ww) + ws;
+    // Eq 99 needs |u|, |v| < alpha; past that the walker stops and is
+    // counted with the capped ones instead of drawing from a broken partition
+    if (!(we >= 0.0 && wn >= 0.0 && D > 0.0)) break;
+    const double c1 = we / D;
+    const double c2 = c1 + wn / D;
+    const double c3 = c2 + ww / D;
+    int ti = i, tj = j, s;
+    if (rn < c1) { ti = i + 1; s = 1; }
+    else if (rn < c2) { tj = j + 1; s = 3; }
+    else if (rn < c3) { ti = i - 1; s = 0; }
+    else { tj = j - 1; s = 2; }
+    if (ti >= 0 && ti < a.nx && tj >= 0 && tj < a.ny) {
+      i = ti;
+      j = tj;
+    } else if (a.tfix[s]) {
+      side = s;
+      break;
+    }
+  }
+  atomicAdd(&a.mcm_count[5 * node + (side < 0 ? 4 : side)], 1);
+}
+
+// node temperatures: the mean wall temperature recorded by the absorbed
+// walkers (sides summed in a fixed order); the cap count is totalled
+template <typename real>
+__global__ __launch_bounds__(256) void k_mcm_finish(SplitArgs<real> a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+  if (i >= a.nx) return;
+  const int* c = a.mcm_count + 5 * (j * a.nx + i);
+  const int absorbed = ((c[0] + c[1]) + c[2]) + c[3];
+  double t = 0.0;
+  for (int s = 0; s < 4; ++s) t += (double)c[s] * (double)a.Tw[s];
+  a.mom[3 * a.planeL + j * a.pL + i] = absorbed > 0 ? real(t / absorbed) : real(0);
+  if (c[4]) atomicAdd(a.mcm_stats, (unsigned long long)c[4]);
+}
+
 }  // namespace
 
 template <typename real>
@@ -975,7 +1064,7 @@ static SplitArgs<real> make_args(const SplitGeom& G, const SplitPtrs<real>& P, c
   a.xf = P.xf;
   a.pL = G.pL;
   a.planeL = G.pL * G.ny;
-  a.nl = G.fv_only ? 0 : (G.lbm_only || G.gs2) ? G.nx : G.ib + 1;
+  a.nl = G.fv_only ? 0 : (G.lbm_only || G.gs2 || G.mcm) ? G.nx : G.ib + 1;
   a.u = P.u[cur];
   a.v = P.v[cur];
   a.T = P.T[cur];
@@ -991,6 +1080,8 @@ static SplitArgs<real> make_args(const SplitGeom& G, const SplitPtrs<real>& P, c
   a.c0 = G.c0;
   a.ib = G.ib;
   for (int k = 0; k < 10; ++k) a.gc[k] = P.gc[k];
+  a.mcm_count = P.mcm_count;
+  a.mcm_stats = P.mcm_stats;
   a.NXc = G.NXc;
   a.NYc = G.NYc;
   a.pC = G.pC;
@@ -1109,6 +1200,20 @@ hipError_t launch_gs2_init(const SplitGeom& G, const SplitPtrs<real>& P, const S
   return hipGetLastError();
 }
 
+template <typename real>
+hipError_t launch_mcm_energy(const SplitGeom& G, const SplitPtrs<real>& P, const SplitParams& S,
+                             int walkers, unsigned long long seed, long long max_steps,
+                             hipStream_t s) {
+  const SplitArgs<real> a = make_args<real>(G, P, S, 0, 0);
+  const long long nodes = (long long)G.nx * G.ny, threads = nodes * walkers;
+  hipLaunchKernelGGL(k_mcm_clear<real>, dim3((unsigned)((5 * nodes + 255) / 256)), dim3(256), 0, s,
+                     a);
+  hipLaunchKernelGGL(k_mcm_walk<real>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, a,
+                     walkers, seed, max_steps);
+  hipLaunchKernelGGL(k_mcm_finish<real>, dim3((G.nx + 255) / 256, G.ny), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 #define LF_SPLIT_INST(real)                                                                   \
   template hipError_t launch_split_step<real>(const SplitGeom&, const SplitPtrs<real>&,        \
                                               const SplitParams&, int, int, hipStream_t);      \
@@ -1121,7 +1226,10 @@ hipError_t launch_gs2_init(const SplitGeom& G, const SplitPtrs<real>& P, const S
   template hipError_t launch_gs2_energy<real>(const SplitGeom&, const SplitPtrs<real>&,        \
                                               const SplitParams&, int, int, hipStream_t);      \
   template hipError_t launch_gs2_init<real>(const SplitGeom&, const SplitPtrs<real>&,          \
-                                            const SplitParams&, const double*, hipStream_t);
+                                            const SplitParams&, const double*, hipStream_t);   \
+  template hipError_t launch_mcm_energy<real>(const SplitGeom&, const SplitPtrs<real>&,        \
+                                              const SplitParams&, int, unsigned long long,     \
+                                              long long, hipStream_t);
 LF_SPLIT_INST(float)
 LF_SPLIT_INST(double)
 #undef LF_SPLIT_INST

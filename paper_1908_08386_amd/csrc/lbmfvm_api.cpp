@@ -58,6 +58,12 @@ struct lf_case {
   // line sweeps per energy step
   size_t off_gs2[10];
   int gs2_S, gs2_K;
+  // LBM-MCM: walker counts per node and wall, the cap total; lattice steps
+  // per Monte Carlo solve, walkers per node, stream seed, step cap
+  size_t off_mcm_count, off_mcm_stats;
+  int mcm_S, mcm_N;
+  unsigned long long mcm_seed;
+  long long mcm_max;
 };
 
 template <typename real>
@@ -87,6 +93,10 @@ static void layout_split(lf_case* c) {
     c->off_gs2[k] = o;
     if (G.gs2) o += align_up((size_t)G.pC * G.NYc * c->es, 256);
   }
+  c->off_mcm_count = o;
+  if (G.mcm) o += align_up((size_t)5 * G.nx * G.ny * sizeof(int), 256);
+  c->off_mcm_stats = o;
+  if (G.mcm) o += 256;
   c->off_dense = o; o += 4 * pbD;
   c->off_dsnap = o; o += 3 * pbD;
   c->off_part = o; o += align_up((size_t)c->nblk * 8 * sizeof(double), 256);
@@ -113,6 +123,8 @@ static lf::SplitPtrs<real> split_ptrs(lf_case* c) {
   P.p = (real*)(c->ws + c->off_sp);
   P.iface = (double*)(c->ws + c->off_siface);
   for (int k = 0; k < 10; ++k) P.gc[k] = (real*)(c->ws + c->off_gs2[k]);
+  P.mcm_count = (int*)(c->ws + c->off_mcm_count);
+  P.mcm_stats = (unsigned long long*)(c->ws + c->off_mcm_stats);
   return P;
 }
 
@@ -134,6 +146,7 @@ static lf_status split_init(lf_case* c, const double* dT) {
     HIP_TRY(lf::launch_gs2_init<real>(c->sg, P, c->sp, dT, s));
   else
     HIP_TRY(lf::launch_split_init<real>(c->sg, P, c->sp, dT, s));
+  if (c->sg.mcm) HIP_TRY(hipMemsetAsync(c->ws + c->off_mcm_stats, 0, 8, s));
   real* dense = (real*)(c->ws + c->off_dense);
   HIP_TRY(lf::launch_split_output<real>(c->sg, P, c->sp, 0, dense, s));
   const size_t n = (size_t)c->sg.nx * c->sg.ny;
@@ -147,14 +160,26 @@ template <typename real>
 static lf_status split_steps(lf_case* c, int64_t n) {
   hipStream_t s = c->ctx->stream;
   const lf::SplitPtrs<real> P = split_ptrs<real>(c);
-  if (c->sg.gs2) {
-    // lattice steps; after every S-th (counted since init) one energy step,
-    // which reads the moments of that lattice step
+  if (c->sg.gs2 || c->sg.mcm) {
+    // lattice steps; after every S-th (counted since init) one energy step
+    // (implicit FV on the coarse grid, or a Monte Carlo solve whose stream
+    // seed advances with the solve's index), which reads the moments of
+    // that lattice step
+    const int S = c->sg.gs2 ? c->gs2_S : c->mcm_S;
+    if (c->sg.mcm && !(c->sp.tfix[0] || c->sp.tfix[1] || c->sp.tfix[2] || c->sp.tfix[3]))
+      return fail(LF_EINVAL, "the Monte Carlo solve needs a wall with a fixed temperature");
     for (int64_t k = 0; k < n; ++k) {
-      const bool energy = (c->steps + k + 1) % c->gs2_S == 0;
+      const int64_t done = c->steps + k + 1;
+      const bool energy = done % S == 0;
       HIP_TRY(lf::launch_gs2_lbm<real>(c->sg, P, c->sp, c->cur, (energy || k == n - 1) ? 1 : 0, s));
       c->cur ^= 1;
-      if (energy) HIP_TRY(lf::launch_gs2_energy<real>(c->sg, P, c->sp, c->gs2_S, c->gs2_K, s));
+      if (!energy) continue;
+      if (c->sg.gs2)
+        HIP_TRY(lf::launch_gs2_energy<real>(c->sg, P, c->sp, c->gs2_S, c->gs2_K, s));
+      else
+        HIP_TRY(lf::launch_mcm_energy<real>(c->sg, P, c->sp, c->mcm_N,
+                                            c->mcm_seed + (unsigned long long)(done / S - 1),
+                                            c->mcm_max, s));
     }
     c->steps += n;
     return LF_OK;
@@ -236,7 +261,8 @@ lf_status lf_case_create(lf_ctx* ctx, const lf_case_desc* d, lf_case** out) {
   if (d->precision != LF_F32 && d->precision != LF_F64)
     return fail(LF_EINVAL, "precision must be LF_F32 or LF_F64");
   if (d->mode != LF_MODE_HYBRID && d->mode != LF_MODE_SPLIT && d->mode != LF_MODE_PURE_FV &&
-      d->mode != LF_MODE_PURE_LBM && d->mode != LF_MODE_HYBRID_GS2 && d->mode != LF_MODE_SPLIT_H)
+      d->mode != LF_MODE_PURE_LBM && d->mode != LF_MODE_HYBRID_GS2 && d->mode != LF_MODE_SPLIT_H &&
+      d->mode != LF_MODE_LBM_MCM)
     return fail(LF_EINVAL, "mode %d unknown", d->mode);
   if (d->mode == LF_MODE_HYBRID_GS2 && (d->nx % 2 || d->ny % 2))
     return fail(LF_EINVAL, "grid setting 2 needs even nx, ny (got %d, %d)", d->nx, d->ny);
@@ -280,7 +306,17 @@ lf_status lf_case_create(lf_ctx* ctx, const lf_case_desc* d, lf_case** out) {
     G.fv_only = d->mode == LF_MODE_PURE_FV;
     G.lbm_only = d->mode == LF_MODE_PURE_LBM;
     G.gs2 = d->mode == LF_MODE_HYBRID_GS2;
-    if (G.gs2) {  // lattice on all nodes, temperature on 2 x 2 blocks
+    G.mcm = d->mode == LF_MODE_LBM_MCM;
+    if (G.mcm) {  // lattice and Monte Carlo temperatures on all nodes
+      G.s = G.ib = G.nx;
+      G.c0 = G.nx + 2;
+      G.pL = (G.nx + 63) / 64 * 64;
+      G.pF = 0;
+      c->mcm_S = 100;
+      c->mcm_N = 256;
+      c->mcm_seed = 1908083868ull;
+      c->mcm_max = 1ll << 24;
+    } else if (G.gs2) {  // lattice on all nodes, temperature on 2 x 2 blocks
       G.s = G.ib = G.nx;
       G.c0 = G.nx + 2;
       G.pL = (G.nx + 63) / 64 * 64;
@@ -356,7 +392,7 @@ static lf_status apply_lattice(lf_case* c, double nu, double alpha, double gbeta
   const double tau = 3.0 * nu + 0.5;  // Eq 15 with c_s^2 = 1/3, Eq 42
   lf_status st = check_stable(tau, alpha);
   if (st != LF_OK) return st;
-  if (c->split && !c->sg.lbm_only && !c->sg.gs2 && nu > 1.0 / 12.0)
+  if (c->split && !c->sg.lbm_only && !c->sg.gs2 && !c->sg.mcm && nu > 1.0 / 12.0)
     return fail(LF_EUNSTABLE, "nu = %.6g: the explicit artificial-compressibility FV zone is "
                 "linearly stable only for nu <= 1/12", nu);
   if (c->split && (gx != 0.0 || gy != 0.0))
@@ -441,7 +477,7 @@ extern "C" {
 lf_status lf_case_set_physics(lf_case* c, const lf_physics* ph) {
   if (!c || !ph) return fail(LF_EINVAL, "NULL argument");
   double prm[8];
-  lf_status st = lf_derive_params(ph, c->g.ny, c->split && !c->sg.gs2, prm);
+  lf_status st = lf_derive_params(ph, c->g.ny, c->split && !c->sg.gs2 && !c->sg.mcm, prm);
   if (st != LF_OK) return st;
   st = apply_lattice(c, prm[1], prm[3], prm[5], prm[6], ph->body_gx, ph->body_gy, ph->conv);
   if (st != LF_OK) return st;
@@ -493,6 +529,33 @@ lf_status lf_case_set_subcycle(lf_case* c, int lattice_steps, int sweeps) {
     return fail(LF_EINVAL, "lattice_steps >= 0 and 0 <= sweeps <= 4096 (0: default)");
   c->gs2_S = lattice_steps > 0 ? lattice_steps : c->sg.nx;
   c->gs2_K = sweeps > 0 ? sweeps : 4;
+  return LF_OK;
+}
+
+lf_status lf_case_set_mcm(lf_case* c, int lattice_steps, int walkers, uint64_t seed,
+                          int64_t max_steps) {
+  if (!c) return fail(LF_EINVAL, "NULL case");
+  if (!c->split || !c->sg.mcm) return fail(LF_EINVAL, "set_mcm applies to LF_MODE_LBM_MCM");
+  if (lattice_steps < 1 || walkers < 1 || max_steps < 1)
+    return fail(LF_EINVAL, "lattice_steps, walkers and max_steps must be >= 1");
+  if ((long long)walkers * c->sg.nx * c->sg.ny > (1ll << 40))
+    return fail(LF_EINVAL, "walkers x nodes above 2^40");
+  c->mcm_S = lattice_steps;
+  c->mcm_N = walkers;
+  c->mcm_seed = (unsigned long long)seed;
+  c->mcm_max = (long long)max_steps;
+  return LF_OK;
+}
+
+lf_status lf_case_mcm_capped(lf_case* c, uint64_t* walkers) {
+  if (!c || !walkers) return fail(LF_EINVAL, "NULL argument");
+  if (!c->split || !c->sg.mcm) return fail(LF_EINVAL, "mcm_capped applies to LF_MODE_LBM_MCM");
+  if (!c->inited) return fail(LF_ESTATE, "init first");
+  unsigned long long h = 0;
+  HIP_TRY(hipMemcpyAsync(&h, c->ws + c->off_mcm_stats, sizeof(h), hipMemcpyDeviceToHost,
+                         c->ctx->stream));
+  HIP_TRY(hipStreamSynchronize(c->ctx->stream));
+  *walkers = (uint64_t)h;
   return LF_OK;
 }
 
@@ -873,7 +936,7 @@ lf_status lf_case_mass(lf_case* c, double* sum_f, double* sum_T) {
     // populations of the LBM zone (nodes 0 .. ib, all nx nodes without an FV
     // zone); T summed over the whole cavity from the output field
     lf::Grid gl;
-    gl.nx = (c->sg.lbm_only || c->sg.gs2) ? c->sg.nx : c->sg.ib + 1;
+    gl.nx = (c->sg.lbm_only || c->sg.gs2 || c->sg.mcm) ? c->sg.nx : c->sg.ib + 1;
     gl.ny = c->sg.ny;
     gl.pitch = c->sg.pL;
     gl.plane = (long long)c->sg.pL * c->sg.ny;

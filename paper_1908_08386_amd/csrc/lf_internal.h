@@ -138,6 +138,9 @@ struct SplitGeom {
   // horizontally divided cavity: stored transposed (the caller's x is the
   // stored y) with gravity along the stored -x
   int gdir, transposed;
+  // LBM-MCM (Sec. 6): lattice on all nodes like gs2, node temperatures from
+  // Monte Carlo walkers (mom plane 3)
+  int mcm;
 };
 
 template <typename real>
@@ -154,6 +157,10 @@ struct SplitPtrs {
   // grid setting 2, NYc rows * pC each: T (iterate A), T (iterate B),
   // a_P, a_W, a_E, a_S, a_N, b, and the Thomas sweep's c', r'
   real* gc[10];
+  // LBM-MCM: per node the walkers absorbed by each wall (W, E, S, N) and
+  // those still walking at the step cap; [0] of stats: the cap count total
+  int* mcm_count;
+  unsigned long long* mcm_stats;
 };
 
 struct SplitParams {
@@ -188,6 +195,13 @@ hipError_t launch_gs2_energy(const SplitGeom& G, const SplitPtrs<real>& P, const
 template <typename real>
 hipError_t launch_gs2_init(const SplitGeom& G, const SplitPtrs<real>& P, const SplitParams& S,
                            const double* T0, hipStream_t s);
+// LBM-MCM: one Monte Carlo solve of the node temperatures with the velocity
+// of the last lattice step: `walkers` walks per node, stream seed `seed`, at
+// most `max_steps` steps each.
+template <typename real>
+hipError_t launch_mcm_energy(const SplitGeom& G, const SplitPtrs<real>& P, const SplitParams& S,
+                             int walkers, unsigned long long seed, long long max_steps,
+                             hipStream_t s);
 // Dense rho, u, v, T planes ([4][ny][nx]) of the current state.
 template <typename real>
 hipError_t launch_split_output(const SplitGeom& G, const SplitPtrs<real>& P, const SplitParams& S,
