@@ -988,17 +988,42 @@ __global__ __launch_bounds__(256) void k_mcm_clear(SplitArgs<real> a) {
   if (k == 0) a.mcm_stats[0] = 0ull;
 }
 
+// Eq 101's cumulative thresholds of every node, once per solve (they depend
+// only on the node's velocity and walls): 4 doubles per node (the fourth is
+// padding), so a step reads one 32-byte record; c3 = -1 marks a node where
+// Eq 99 loses positivity (|u| or |v| >= alpha)
 template <typename real>
-__global__ __launch_bounds__(256) void k_mcm_walk(SplitArgs<real> a, int walkers,
-                                                  unsigned long long seed, long long max_steps) {
+__global__ __launch_bounds__(256) void k_mcm_prep(SplitArgs<real> a, double* __restrict__ cth) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+  if (i >= a.nx) return;
+  const double al = (double)a.alpha;
+  const double u = (double)a.mom[a.planeL + j * a.pL + i];
+  const double v = (double)a.mom[2 * a.planeL + j * a.pL + i];
+  const double fe = (a.tfix[1] && i == a.nx - 1) ? 2.0 : 1.0;
+  const double fn = (a.tfix[3] && j == a.ny - 1) ? 2.0 : 1.0;
+  const double fw = (a.tfix[0] && i == 0) ? 2.0 : 1.0;
+  const double fs = (a.tfix[2] && j == 0) ? 2.0 : 1.0;
+  const double we = fe * (al - u), wn = fn * (al - v), ww = fw * al, ws = fs * al;
+  const double D = ((we + wn) + ww) + ws;
+  double4* rec = (double4*)cth + (j * a.nx + i);
+  if (!(we >= 0.0 && wn >= 0.0 && D > 0.0)) {
+    *rec = double4{-1.0, -1.0, -1.0, 0.0};
+    return;
+  }
+  const double c1 = we / D;
+  const double c2 = c1 + wn / D;
+  *rec = double4{c1, c2, c2 + ww / D, 0.0};
+}
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_mcm_walk(SplitArgs<real> a, const double* __restrict__ cth,
+                                                  int walkers, unsigned long long seed,
+                                                  long long max_steps) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long nodes = (long long)a.nx * a.ny;
   if (t >= nodes * walkers) return;
   const int node = (int)(t / walkers), w = (int)(t - (long long)node * walkers);
   int i = node % a.nx, j = node / a.nx;
-  const real* ux = a.mom + a.planeL;
-  const real* uy = a.mom + 2 * a.planeL;
-  const double al = (double)a.alpha;
   const unsigned long long s0 =
       mix64(seed + (1ull + (unsigned long long)node * (unsigned long long)walkers +
                     (unsigned long long)w) * kGamma);
@@ -1006,19 +1031,10 @@ __global__ __launch_bounds__(256) void k_mcm_walk(SplitArgs<real> a, int walkers
   for (long long k = 0; k < max_steps; ++k) {
     const double rn = (double)(mix64(s0 + (unsigned long long)(k + 1) * kGamma) >> 11) *
                       (1.0 / 9007199254740992.0);
-    const double u = (double)ux[j * a.pL + i], v = (double)uy[j * a.pL + i];
-    const double fe = (a.tfix[1] && i == a.nx - 1) ? 2.0 : 1.0;
-    const double fn = (a.tfix[3] && j == a.ny - 1) ? 2.0 : 1.0;
-    const double fw = (a.tfix[0] && i == 0) ? 2.0 : 1.0;
-    const double fs = (a.tfix[2] && j == 0) ? 2.0 : 1.0;
-    const double we = fe * (al - u), wn = fn * (al - v), ww = fw * al, ws = fs * al;
-    const double D = ((we + wn) + ww) + ws;
-    // Eq 99 needs |u|, |v| < alpha; past that the walker stops and is
-    // counted with the capped ones instead of drawing from a broken partition
-    if (!(we >= 0.0 && wn >= 0.0 && D > 0.0)) break;
-    const double c1 = we / D;
-    const double c2 = c1 + wn / D;
-    const double c3 = c2 + ww / D;
+    const double4 rec = ((const double4*)cth)[j * a.nx + i];
+    const double c1 = rec.x, c2 = rec.y, c3 = rec.z;
+    // a node past Eq 99's positivity stops the walker (counted as capped)
+    if (c3 < 0.0) break;
     int ti = i, tj = j, s;
     if (rn < c1) { ti = i + 1; s = 1; }
     else if (rn < c2) { tj = j + 1; s = 3; }
@@ -1206,10 +1222,12 @@ hipError_t launch_mcm_energy(const SplitGeom& G, const SplitPtrs<real>& P, const
                              hipStream_t s) {
   const SplitArgs<real> a = make_args<real>(G, P, S, 0, 0);
   const long long nodes = (long long)G.nx * G.ny, threads = nodes * walkers;
+  double* cth = P.mcm_cth;
   hipLaunchKernelGGL(k_mcm_clear<real>, dim3((unsigned)((5 * nodes + 255) / 256)), dim3(256), 0, s,
                      a);
+  hipLaunchKernelGGL(k_mcm_prep<real>, dim3((G.nx + 255) / 256, G.ny), dim3(256), 0, s, a, cth);
   hipLaunchKernelGGL(k_mcm_walk<real>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, a,
-                     walkers, seed, max_steps);
+                     (const double*)cth, walkers, seed, max_steps);
   hipLaunchKernelGGL(k_mcm_finish<real>, dim3((G.nx + 255) / 256, G.ny), dim3(256), 0, s, a);
   return hipGetLastError();
 }

@@ -60,7 +60,7 @@ struct lf_case {
   int gs2_S, gs2_K;
   // LBM-MCM: walker counts per node and wall, the cap total; lattice steps
   // per Monte Carlo solve, walkers per node, stream seed, step cap
-  size_t off_mcm_count, off_mcm_stats;
+  size_t off_mcm_count, off_mcm_stats, off_mcm_cth;
   int mcm_S, mcm_N;
   unsigned long long mcm_seed;
   long long mcm_max;
@@ -97,6 +97,8 @@ static void layout_split(lf_case* c) {
   if (G.mcm) o += align_up((size_t)5 * G.nx * G.ny * sizeof(int), 256);
   c->off_mcm_stats = o;
   if (G.mcm) o += 256;
+  c->off_mcm_cth = o;
+  if (G.mcm) o += align_up((size_t)4 * G.nx * G.ny * sizeof(double), 256);
   c->off_dense = o; o += 4 * pbD;
   c->off_dsnap = o; o += 3 * pbD;
   c->off_part = o; o += align_up((size_t)c->nblk * 8 * sizeof(double), 256);
@@ -125,6 +127,7 @@ static lf::SplitPtrs<real> split_ptrs(lf_case* c) {
   for (int k = 0; k < 10; ++k) P.gc[k] = (real*)(c->ws + c->off_gs2[k]);
   P.mcm_count = (int*)(c->ws + c->off_mcm_count);
   P.mcm_stats = (unsigned long long*)(c->ws + c->off_mcm_stats);
+  P.mcm_cth = (double*)(c->ws + c->off_mcm_cth);
   return P;
 }
 

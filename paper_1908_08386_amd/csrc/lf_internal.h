@@ -161,6 +161,7 @@ struct SplitPtrs {
   // those still walking at the step cap; [0] of stats: the cap count total
   int* mcm_count;
   unsigned long long* mcm_stats;
+  double* mcm_cth;  // Eq 101's thresholds per node, 4 doubles (one padding)
 };
 
 struct SplitParams {
