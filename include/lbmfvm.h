@@ -245,7 +245,8 @@ lf_status lf_case_mass(lf_case* c, double* sum_f, double* sum_T);
 /* Steps taken since init.                                                 */
 lf_status lf_case_steps(const lf_case* c, int64_t* steps);
 /* Checkpoint: the complete state of an initialised case (fields, moments,
- * residual snapshot, step count, lattice parameters and walls) as a host
+ * residual snapshot, step count, lattice parameters, walls and the cycle
+ * settings of lf_case_set_subcycle / lf_case_set_mcm) as a host
  * blob.  With blob == NULL, *bytes receives the size needed; otherwise
  * *bytes must hold at least that size and receives the size written
  * (synchronises the stream).  lf_case_load restores such a blob into a

@@ -844,7 +844,7 @@ lf_status lf_case_fetch(lf_case* c, int field, void* dst, size_t dst_bytes, int 
 // checkpoint blob: header, then the bound workspace's first `need` bytes
 namespace {
 struct CaseBlobHeader {
-  char magic[8];  // "LFCASE1"
+  char magic[8];  // "LFCASE2"
   int abi;
   lf_case_desc desc;
   size_t es, need;
@@ -854,6 +854,10 @@ struct CaseBlobHeader {
   lf::WallSet w;
   lf::HybridParams p;
   lf::SplitParams sp;
+  // cycle settings of grid setting 2 and of LBM-MCM
+  int gs2_S, gs2_K, mcm_S, mcm_N;
+  unsigned long long mcm_seed;
+  long long mcm_max;
 };
 }  // namespace
 
@@ -868,7 +872,7 @@ lf_status lf_case_save(lf_case* c, void* blob, size_t* bytes) {
   if (*bytes < total) return fail(LF_EINVAL, "blob holds %zu bytes, %zu needed", *bytes, total);
   CaseBlobHeader h;
   memset(&h, 0, sizeof(h));
-  memcpy(h.magic, "LFCASE1", 8);
+  memcpy(h.magic, "LFCASE2", 8);
   h.abi = LF_ABI_VERSION;
   h.desc = c->desc;
   h.es = c->es;
@@ -880,6 +884,12 @@ lf_status lf_case_save(lf_case* c, void* blob, size_t* bytes) {
   h.w = c->w;
   h.p = c->p;
   h.sp = c->sp;
+  h.gs2_S = c->gs2_S;
+  h.gs2_K = c->gs2_K;
+  h.mcm_S = c->mcm_S;
+  h.mcm_N = c->mcm_N;
+  h.mcm_seed = c->mcm_seed;
+  h.mcm_max = c->mcm_max;
   memcpy(blob, &h, sizeof(h));
   hipStream_t s = c->ctx->stream;
   HIP_TRY(hipMemcpyAsync((char*)blob + sizeof(h), c->ws, c->need, hipMemcpyDeviceToHost, s));
@@ -894,7 +904,7 @@ lf_status lf_case_load(lf_case* c, const void* blob, size_t bytes) {
   CaseBlobHeader h;
   if (bytes < sizeof(h)) return fail(LF_EINVAL, "blob too short");
   memcpy(&h, blob, sizeof(h));
-  if (memcmp(h.magic, "LFCASE1", 8) != 0 || h.abi != LF_ABI_VERSION)
+  if (memcmp(h.magic, "LFCASE2", 8) != 0 || h.abi != LF_ABI_VERSION)
     return fail(LF_EINVAL, "not a checkpoint of this library");
   if (memcmp(&h.desc, &c->desc, sizeof(lf_case_desc)) != 0 || h.es != c->es || h.need != c->need)
     return fail(LF_EINVAL, "checkpoint of a different case geometry or precision");
@@ -909,6 +919,12 @@ lf_status lf_case_load(lf_case* c, const void* blob, size_t bytes) {
   c->w = h.w;
   c->p = h.p;
   c->sp = h.sp;
+  c->gs2_S = h.gs2_S;
+  c->gs2_K = h.gs2_K;
+  c->mcm_S = h.mcm_S;
+  c->mcm_N = h.mcm_N;
+  c->mcm_seed = h.mcm_seed;
+  c->mcm_max = h.mcm_max;
   c->inited = true;
   return LF_OK;
 }

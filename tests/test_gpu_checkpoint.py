@@ -48,3 +48,30 @@ def test_load_rejects_other_geometry(lf, ctx):
     with pytest.raises(lf.LFError) as e:
         lf.Case(ctx, 64, 32, "f32").save()
     assert e.value.status == lf.LF_ESTATE
+
+
+@pytest.mark.parametrize("mode", ["gs2", "mcm"])
+def test_resume_keeps_cycle_settings(lf, ctx, mode):
+    """Grid setting 2 and LBM-MCM carry their cycle settings (and, for the
+    walkers, the stream seed) in the checkpoint: a restored case continues
+    bit for bit although the target case was created with the defaults."""
+    nx, ny = 32, 24
+    T0 = perturbation(nx, ny, 81, amp=0.2)
+    m = lf.MODE_HYBRID_GS2 if mode == "gs2" else lf.MODE_LBM_MCM
+
+    def make():
+        return lf.Case(ctx, nx, ny, "f64", mode=m).set_physics(1e4, 0.71).set_cavity_walls()
+
+    a = make()
+    if mode == "gs2":
+        a.set_subcycle(7, 3)
+    else:
+        a.set_mcm(9, 64, 12345, 1 << 20)
+    a.init(T0).step(20)
+    blob = a.save()
+    b = make()
+    b.init(T0).load(blob)
+    a.step(25)
+    b.step(25)
+    for f in ("u", "v", "T"):
+        assert np.array_equal(a.fetch(f), b.fetch(f)), f
