@@ -101,6 +101,9 @@ def lib() -> ctypes.CDLL:
             L.dd_init_uniform_flow.argtypes = [vp, dp, ctypes.c_double, ctypes.c_double]
             L.dd_set_fv.argtypes = [vp, dp, dp, dp]
             L.dd_set_gdir.argtypes = [vp, ctypes.c_int]
+            L.dd_set_lid.argtypes = [vp, ctypes.c_double]
+            L.dd_zone_mass.restype = ctypes.c_double
+            L.dd_zone_mass.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -302,6 +305,16 @@ class DDCase:
     def set_thermal(self, side, fixed: bool, T_wall=0.0):
         lib().dd_set_wall(self._h, int(side), 0.0, 1 if fixed else 0, float(T_wall))
         return self
+
+    def set_lid(self, u_wall: float):
+        """The north wall slides along +x at u_wall (lattice units)."""
+        if lib().dd_set_lid(self._h, float(u_wall)) != 0:
+            raise ValueError("no sliding wall on a periodic axis")
+        return self
+
+    def zone_mass(self) -> float:
+        """Split mode: mass of the LBM nodes west of x_b (post-collision)."""
+        return lib().dd_zone_mass(self._h)
 
     def set_periodic(self, axis: str):
         side = W if axis == "x" else S

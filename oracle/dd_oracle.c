@@ -32,10 +32,15 @@
  *   3. rho0 = mean LBM density (previous step) and p_bar = mean FV pressure
  *      (new) over the three shared columns (Sec. 4.1.2);
  *   4. LBM streaming on nodes 0 .. ib-1; the boundary node x_b gets
- *      rho_b from Eq 93, u_b, v_b, T_b from the FV zone and its populations
- *      from non-equilibrium extrapolation (Eq 60 / Eq 94-95) or from the
- *      finite-difference velocity-gradient closure (Eq 70-72);
+ *      rho_b from Eq 93 (its level shifted so that the LBM zone keeps its
+ *      mass, see iface_boundary_node), u_b, v_b, T_b from the FV zone and
+ *      its populations from non-equilibrium extrapolation (Eq 60 /
+ *      Eq 94-95) or from the finite-difference velocity-gradient closure
+ *      (Eq 70-72);
  *   5. collision of all LBM nodes.
+ * The north wall may slide along +x (the lid-driven cavity of Sec. 3.3,
+ * Fig. 5): half-way bounce-back with the moving-wall term in the LBM zone,
+ * the ghost u = 2 u_lid - u_edge in the FV zone.
  * Output: LBM values on columns < s, FV values (face velocities averaged
  * to centres) on columns >= s.
  */
@@ -79,6 +84,8 @@ typedef struct dd_case {
   int gdir; /* buoyancy along +y (0, gravity -y) or along +x (1, gravity -x):
                the horizontally divided cavity of Fig. 17b, stored transposed */
   int conv;
+  double ulid;  /* tangential velocity of the north wall (0: at rest)     */
+  double mass0; /* split mode: mass of the LBM nodes 0 .. ib-1 at init   */
   /* LBM zone, [q][j][i] / [j][i] with nl columns */
   double *f, *fpre, *g, *gpre;
   double *rho, *ux, *uy, *TL; /* moments of the last LBM step (pre-collision) */
@@ -265,7 +272,7 @@ static double U_at(const dd_case* c, const double* u, int x, int j) {
   int nx = c->nx, ny = c->ny;
   if (c->yper) j = (j + ny) % ny;
   else if (j < 0) return -U_at(c, u, x, -1 - j);       /* no-slip mirror */
-  else if (j >= ny) return -U_at(c, u, x, 2 * ny - 1 - j);
+  else if (j >= ny) return 2.0 * c->ulid - U_at(c, u, x, 2 * ny - 1 - j);
   if (c->xper) x = ((x % nx) + nx) % nx;
   else if (x > nx) return -U_at(c, u, 2 * nx - x, j); /* through the wall face */
   else if (x < 0 && fv_has_west_wall(c)) return -U_at(c, u, -x, j);
@@ -463,6 +470,10 @@ static void lbm_stream(dd_case* c, int nstream) {
         if (c->yper) sj = (sj + ny) % ny;
         int out = sj < 0 || sj >= ny || si < 0 || (east_wall && si >= nl);
         double fq = out ? FL(c, c->f, OPP9[q], j, i) : FL(c, c->f, q, sj, si);
+        /* half-way bounce-back from the sliding north wall: the returning
+         * population gains 6 w_q (e_q . u_w); a source beyond the north
+         * wall counts as that wall also at the two top corners           */
+        if (out && !c->yper && sj >= ny) fq += 6.0 * W9D[q] * DX9[q] * c->ulid;
         FL(c, c->fpre, q, j, i) = fq;
         r += fq;
         mx += DX9[q] * fq;
@@ -562,18 +573,33 @@ static double iface_pbar(const dd_case* c) {
 
 static void iface_boundary_node(dd_case* c) {
   const int ny = c->ny, ib = c->ib, xf = ib - 1;
+  /* The level of Eq 93.  rho0, the mean LBM density over the shared
+   * columns, follows the LBM zone's own level, so nothing holds the zone's
+   * mass: the walls conserve it and it changes only through the links to
+   * x_b, by whatever small net flux the coupling leaves.  The boundary
+   * density is therefore shifted, uniformly over the rows, by the amount
+   * that -- carried by the rest weights of the populations x_b sends into
+   * the zone (W, NW, SW; one diagonal fewer on the two wall rows) --
+   * returns the zone's mass (nodes 0 .. ib-1, just streamed) to its value
+   * at init.                                                               */
+  double m = 0.0;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < ib; ++i) m += LN(c, c->rho, j, i);
+  const double wsum = ny * (W9D[3] + W9D[6] + W9D[7]) - W9D[6] - W9D[7];
+  const double delta = (c->mass0 - m) / wsum;
   for (int j = 0; j < ny; ++j) {
     double ub = 0.5 * (FC(c, c->u, j, ib) + FC(c, c->u, j, ib + 1));
     double vb = 0.5 * (FVF(c, c->v, j, ib) + FVF(c, c->v, j + 1, ib));
     double Tb = FC(c, c->T, j, ib);
-    double rb = dd_boundary_density(c->rho0, FC(c, c->p, j, ib), c->pbar);
+    double rb = dd_boundary_density(c->rho0, FC(c, c->p, j, ib), c->pbar) + delta;
     double ff[Q9], fo[Q9];
     for (int q = 0; q < Q9; ++q) ff[q] = FL(c, c->fpre, q, j, xf);
     double dudx = FC(c, c->u, j, ib + 1) - FC(c, c->u, j, ib);
     /* cell-centred u of column ib at rows j-1 and j+1 (no-slip mirror at
      * the walls) and cell-centred v of columns ib-1 and ib+1              */
     double um = j > 0 ? 0.5 * (FC(c, c->u, j - 1, ib) + FC(c, c->u, j - 1, ib + 1)) : -ub;
-    double up = j < ny - 1 ? 0.5 * (FC(c, c->u, j + 1, ib) + FC(c, c->u, j + 1, ib + 1)) : -ub;
+    double up = j < ny - 1 ? 0.5 * (FC(c, c->u, j + 1, ib) + FC(c, c->u, j + 1, ib + 1))
+                           : 2.0 * c->ulid - ub;
     double vw = 0.5 * (FVF(c, c->v, j, ib - 1) + FVF(c, c->v, j + 1, ib - 1));
     double ve = 0.5 * (FVF(c, c->v, j, ib + 1) + FVF(c, c->v, j + 1, ib + 1));
     dd_reconstruct_node(c->iface, ff, rb, ub, vb, c->tau, dudx, 0.5 * (up - um),
@@ -625,6 +651,17 @@ static void dd_output(const dd_case* c, int field, double* out) {
     }
 }
 
+/* mass of the LBM nodes 0 .. ib-1 (split mode), summed over the
+ * post-collision populations                                             */
+double dd_zone_mass(const dd_case* c) {
+  if (c->mode != DD_SPLIT) return 0.0;
+  double m = 0.0;
+  for (int j = 0; j < c->ny; ++j)
+    for (int i = 0; i < c->ib; ++i)
+      for (int q = 0; q < Q9; ++q) m += FL(c, c->f, q, j, i);
+  return m;
+}
+
 int dd_init(dd_case* c, const double* T0) {
   int ny = c->ny;
   for (int j = 0; j < ny; ++j)
@@ -648,6 +685,7 @@ int dd_init(dd_case* c, const double* T0) {
         if (x >= 0) FC(c, c->T, j, x) = T0 ? T0[(size_t)j * c->nx + x] : 0.0;
   }
   for (int k = 0; k < 3; ++k) dd_output(c, k, c->snap[k]);
+  c->mass0 = dd_zone_mass(c);
   c->steps = 0;
   return 0;
 }
@@ -762,6 +800,7 @@ int dd_init_uniform_flow(dd_case* c, const double* T0, double U, double V) {
       LN(c, c->ux, j, x) = U;
       LN(c, c->uy, j, x) = V;
     }
+  c->mass0 = dd_zone_mass(c);
   return 0;
 }
 
@@ -789,6 +828,13 @@ int dd_set_iface(dd_case* c, int kind) {
 int dd_set_gdir(dd_case* c, int gdir) {
   if (gdir < 0 || gdir > 1) return -1;
   c->gdir = gdir;
+  return 0;
+}
+
+/* tangential velocity of the north wall (lid-driven cavity, Sec. 3.3) */
+int dd_set_lid(dd_case* c, double u) {
+  if (c->yper) return -1;
+  c->ulid = u;
   return 0;
 }
 

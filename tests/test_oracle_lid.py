@@ -1,0 +1,109 @@
+"""Pins of the lid-driven cavity (Sec. 3.3, Fig. 5) in the domain-decomposed
+oracle: the sliding north wall in both single methods against the exact
+Couette profile, the primary-vortex centre of the single methods and of the
+two hybrid methods (non-equilibrium extrapolation, finite-difference
+velocity gradient) against the centres the paper prints, and the LBM zone's
+mass held by the level of Eq 93 under the strong cross-interface flow."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+
+HERE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+U = 0.1
+
+
+def centres():
+    with open(os.path.join(HERE, "paper_tables.json")) as f:
+        return json.load(f)["sec33_vortex_centre"]
+
+
+def lid_case(n, Re, mode, iface=oracle.IFACE_NEQ):
+    """n x n cavity, lid speed 0.1 (the paper's nondimensional lid
+    velocity, Sec. 3.1), nu from Re = U n / nu; temperature inert."""
+    c = oracle.DDCase(n, n, mode, iface).set_lattice(U * n / Re, 0.1, 0.0)
+    for sd in (oracle.W, oracle.E, oracle.S, oracle.N):
+        c.set_thermal(sd, False)
+    return c.set_lid(U).init()
+
+
+def vortex_centre(u):
+    """Centre of the primary vortex: the minimum of the stream function
+    psi = integral of u dy, taken at the top face of each cell row."""
+    n = u.shape[0]
+    psi = np.cumsum(u, axis=0) / n
+    j, i = np.unravel_index(np.argmin(psi), psi.shape)
+    return (i + 0.5) / n, (j + 1.0) / n
+
+
+@pytest.mark.parametrize("mode", [oracle.PURE_LBM, oracle.PURE_FV])
+def test_sliding_wall_gives_exact_couette(mode):
+    """Periodic in x, bottom at rest, top sliding at U: the steady profile
+    u = U (j + 1/2) / ny is exact for half-way bounce-back with the
+    moving-wall term and for the FV ghost u = 2 U - u_edge."""
+    ny, Uw = 16, 0.05
+    c = oracle.DDCase(24, ny, mode).set_lattice(0.1, 0.1, 0.0)
+    c.set_thermal(oracle.S, False).set_thermal(oracle.N, False)
+    c.set_periodic("x").set_lid(Uw).init()
+    c.step(40000)
+    exact = Uw * (np.arange(ny) + 0.5) / ny
+    assert np.abs(c.fetch("u") - exact[:, None]).max() < 1e-11
+    assert np.abs(c.fetch("v")).max() < 1e-12
+
+
+@pytest.mark.parametrize("mode,iface", [(oracle.PURE_LBM, 0), (oracle.PURE_FV, 0),
+                                        (oracle.SPLIT, oracle.IFACE_NEQ),
+                                        (oracle.SPLIT, oracle.IFACE_FDGRAD)])
+def test_vortex_centre_re100(mode, iface):
+    """64 x 64, Re 100: the single methods and both hybrid methods put the
+    primary-vortex centre within one cell of Ref [35]'s centre and of the
+    SIMPLE and LBM centres the paper prints (160 x 160)."""
+    c = lid_case(64, 100.0, mode, iface)
+    steps, r = c.run_to_steady(tol=1e-9, check_every=1000, max_steps=60000, fields=(0, 1))
+    assert r[:2].max() <= 1e-9, (steps, r)
+    x, y = vortex_centre(c.fetch("u"))
+    for ref in centres()["100"].values():
+        assert abs(x - ref[0]) <= 1 / 64 and abs(y - ref[1]) <= 1 / 64, (x, y, ref)
+
+
+def test_vortex_centre_re400_hybrid():
+    """64 x 64, Re 400, hybrid method 1: within one cell of Ref [35]."""
+    c = lid_case(64, 400.0, oracle.SPLIT)
+    steps, r = c.run_to_steady(tol=1e-9, check_every=1000, max_steps=90000, fields=(0, 1))
+    assert r[:2].max() <= 1e-9, (steps, r)
+    x, y = vortex_centre(c.fetch("u"))
+    ref = centres()["400"]["reference_35"]
+    assert abs(x - ref[0]) <= 1 / 64 and abs(y - ref[1]) <= 1 / 64, (x, y, ref)
+
+
+def test_lbm_zone_mass_is_held():
+    """The lid drives a strong flow across the interface; the LBM zone's
+    mass stays within one step's flux of its initial value (rather than
+    drifting without bound)."""
+    c = lid_case(64, 100.0, oracle.SPLIT)
+    m0 = c.zone_mass()
+    assert abs(m0 - 64 * 33) < 1e-9
+    dm = []
+    for _ in range(20):
+        c.step(500)
+        dm.append(c.zone_mass() - m0)
+    assert np.abs(dm).max() < 0.02, dm
+
+
+def test_natural_convection_split_reaches_steady_state():
+    """64 x 64 cavity, Ra 1e4, Pr 0.71, hybrid method 1: the coupled run
+    reaches a 1e-9 residual and its wall-averaged Nusselt number lies
+    within 1 % of both single methods."""
+    nu = {}
+    for mode in (oracle.SPLIT, oracle.PURE_FV, oracle.PURE_LBM):
+        c = oracle.DDCase(64, 64, mode).set_physics(1e4, 0.71).set_cavity_walls().init()
+        steps, r = c.run_to_steady(tol=1e-9, check_every=1000, max_steps=80000)
+        assert r.max() <= 1e-9, (mode, steps, r)
+        nu[mode] = c.nusselt()
+    s = nu[oracle.SPLIT]
+    assert abs(s["nu_hot"] - s["nu_cold"]) < 1e-3 * s["nu_hot"]
+    for m in (oracle.PURE_FV, oracle.PURE_LBM):
+        assert abs(s["nu_hot"] - nu[m]["nu_hot"]) < 0.01 * nu[m]["nu_hot"], (s, nu[m])
