@@ -13,7 +13,12 @@
  *     on the west part, FVM on the east part, three shared columns, coupled
  *     through non-equilibrium extrapolation (Eq 60, Eq 94-95) or the
  *     finite-difference velocity-gradient reconstruction (Eq 70-72) with the
- *     density transfer of Eq 91-93.  LF_MODE_SPLIT_H divides the cavity
+ *     density transfer of Eq 91-93; the level rho0 of Eq 93 is shifted each
+ *     step so that the LBM zone keeps its mass at init (the walls conserve
+ *     it; it changes only through the boundary node's links).  With a
+ *     sliding north wall it is the lid-driven cavity of Sec. 3.3 (Fig. 5;
+ *     hybrid method 1 = non-equilibrium extrapolation, 2 = finite-difference
+ *     gradient).  LF_MODE_SPLIT_H divides the cavity
  *     horizontally instead (Fig. 17b: LBM in the lower half, FVM in the
  *     upper half; stored transposed with gravity along the stored -x, so
  *     the same kernels run it; fields, walls and Nusselt numbers keep the
@@ -132,7 +137,12 @@ typedef struct {
 } lf_physics;
 
 /* One side of the box.  vel: LF_WALL_NOSLIP (half-way bounce-back; u_wall
- * is the tangential wall speed) or LF_WALL_PERIODIC (both opposite sides).
+ * is the tangential wall speed, along +x or +y, with the moving-wall term
+ * 6 w_q rho_w (e_q . u_w), rho_w = 1) or LF_WALL_PERIODIC (both opposite
+ * sides).  In LF_MODE_SPLIT, LF_MODE_PURE_FV and LF_MODE_PURE_LBM only the
+ * north wall may move (the lid of Sec. 3.3; the FV zone takes the ghost
+ * u = 2 u_wall - u_edge); other split-family modes and sides give
+ * LF_ENOTIMPL.
  * thermal: LF_T_DIRICHLET (T = T_wall), LF_T_ADIABATIC, or LF_T_PERIODIC
  * (together with vel periodic).                                            */
 typedef struct {

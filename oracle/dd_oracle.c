@@ -85,7 +85,8 @@ typedef struct dd_case {
                the horizontally divided cavity of Fig. 17b, stored transposed */
   int conv;
   double ulid;  /* tangential velocity of the north wall (0: at rest)     */
-  double mass0; /* split mode: mass of the LBM nodes 0 .. ib-1 at init   */
+  double excess0; /* split mode: mass of the LBM nodes 0 .. ib-1 over one
+                     per node, at init                                    */
   /* LBM zone, [q][j][i] / [j][i] with nl columns */
   double *f, *fpre, *g, *gpre;
   double *rho, *ux, *uy, *TL; /* moments of the last LBM step (pre-collision) */
@@ -577,16 +578,20 @@ static void iface_boundary_node(dd_case* c) {
    * columns, follows the LBM zone's own level, so nothing holds the zone's
    * mass: the walls conserve it and it changes only through the links to
    * x_b, by whatever small net flux the coupling leaves.  The boundary
-   * density is therefore shifted, uniformly over the rows, by the amount
-   * that -- carried by the rest weights of the populations x_b sends into
-   * the zone (W, NW, SW; one diagonal fewer on the two wall rows) --
-   * returns the zone's mass (nodes 0 .. ib-1, just streamed) to its value
-   * at init.                                                               */
+   * density is therefore shifted, uniformly over the rows, by a quarter of
+   * the amount that -- carried by the rest weights of the populations x_b
+   * sends into the zone (W, NW, SW; one diagonal fewer on the two wall
+   * rows) -- would return the zone's mass (nodes 0 .. ib-1, just streamed)
+   * to its value at init.  (The whole amount each step overshoots with the
+   * finite-difference closure: its boundary populations answer the FV
+   * pressure, which answers the shift one step later.)  The mass is summed
+   * as its excess over one per node: each rho - 1 is exact, so the small
+   * deficit does not drown in the rounding of a sum of ones.              */
   double m = 0.0;
   for (int j = 0; j < ny; ++j)
-    for (int i = 0; i < ib; ++i) m += LN(c, c->rho, j, i);
+    for (int i = 0; i < ib; ++i) m += LN(c, c->rho, j, i) - 1.0;
   const double wsum = ny * (W9D[3] + W9D[6] + W9D[7]) - W9D[6] - W9D[7];
-  const double delta = (c->mass0 - m) / wsum;
+  const double delta = (c->excess0 - m) / (4.0 * wsum);
   for (int j = 0; j < ny; ++j) {
     double ub = 0.5 * (FC(c, c->u, j, ib) + FC(c, c->u, j, ib + 1));
     double vb = 0.5 * (FVF(c, c->v, j, ib) + FVF(c, c->v, j + 1, ib));
@@ -651,15 +656,24 @@ static void dd_output(const dd_case* c, int field, double* out) {
     }
 }
 
-/* mass of the LBM nodes 0 .. ib-1 (split mode), summed over the
- * post-collision populations                                             */
-double dd_zone_mass(const dd_case* c) {
+/* mass of the LBM nodes 0 .. ib-1 (split mode) over one per node, from
+ * the post-collision populations (summed per node in the streaming's
+ * order)                                                                 */
+static double zone_excess(const dd_case* c) {
   if (c->mode != DD_SPLIT) return 0.0;
   double m = 0.0;
   for (int j = 0; j < c->ny; ++j)
-    for (int i = 0; i < c->ib; ++i)
-      for (int q = 0; q < Q9; ++q) m += FL(c, c->f, q, j, i);
+    for (int i = 0; i < c->ib; ++i) {
+      double r = 0.0;
+      for (int q = 0; q < Q9; ++q) r += FL(c, c->f, q, j, i);
+      m += r - 1.0;
+    }
   return m;
+}
+
+/* mass of the LBM nodes 0 .. ib-1 (split mode)                          */
+double dd_zone_mass(const dd_case* c) {
+  return c->mode == DD_SPLIT ? (double)c->ib * c->ny + zone_excess(c) : 0.0;
 }
 
 int dd_init(dd_case* c, const double* T0) {
@@ -685,7 +699,7 @@ int dd_init(dd_case* c, const double* T0) {
         if (x >= 0) FC(c, c->T, j, x) = T0 ? T0[(size_t)j * c->nx + x] : 0.0;
   }
   for (int k = 0; k < 3; ++k) dd_output(c, k, c->snap[k]);
-  c->mass0 = dd_zone_mass(c);
+  c->excess0 = zone_excess(c);
   c->steps = 0;
   return 0;
 }
@@ -800,7 +814,7 @@ int dd_init_uniform_flow(dd_case* c, const double* T0, double U, double V) {
       LN(c, c->ux, j, x) = U;
       LN(c, c->uy, j, x) = V;
     }
-  c->mass0 = dd_zone_mass(c);
+  c->excess0 = zone_excess(c);
   return 0;
 }
 

@@ -19,16 +19,23 @@
 //                 gradient, buoyancy on v faces; Eq 74-75 explicit);
 //   k_dd_press_energy  p <- p - c_s^2 div u*, and the conservative QUICK
 //                 energy balance on u* (Eq 76);
-//   k_dd_pbar_rows, k_dd_pbar_fold  mean FV pressure over the shared columns;
+//   k_dd_pbar_rows, k_dd_pbar_fold  mean FV pressure over the shared columns,
+//                 and the mass the LBM zone is about to gain through the
+//                 links to x_b (its running total is the zone's mass change
+//                 since init: the walls conserve mass);
 //   k_dd_lbm      pull-stream + bounce-back / anti-bounce-back walls,
 //                 moments, BGK collision with buoyancy from T = sum g
 //                 (Eq 5, 18, 19-23) for nodes 0 .. ib-1; the streamed state
 //                 of x_f = ib-1 is kept for the boundary node;
-//   k_dd_xb       x_b from the FV zone: rho_b by Eq 93, u_b, v_b, T_b by
+//   k_dd_xb       x_b from the FV zone: rho_b by Eq 93 with its level
+//                 shifted to hold the LBM zone's mass, u_b, v_b, T_b by
 //                 face averages, populations by non-equilibrium
 //                 extrapolation (Eq 60 / Eq 94-95) or by the
 //                 finite-difference velocity-gradient closure (Eq 70-72);
 //                 then its collision.
+// The north wall may slide along +x (the lid-driven cavity of Sec. 3.3):
+// moving-wall bounce-back in the LBM zone, ghost u = 2 u_lid - u_edge in the
+// FV zone.
 // The LBM zone is 112 B per node (FP32) and the FV zone streams u, v, p, T
 // twice; the interface work is O(ny).
 // The single-method cavities of the Sec. 4.2 comparison run the same zone
@@ -103,8 +110,9 @@ struct SplitArgs {
   real* __restrict__ Tn;
   real* __restrict__ p;
   int pF;
-  // interface scalars (double): [0] rho0, [1] p_bar, from [kIfacePart] the
-  // per-block sums of the ghost kernel
+  // interface scalars (double): [0] rho0, [1] p_bar, [2] the LBM zone's mass
+  // change since init, from [kIfacePart] the per-block sums of the ghost and
+  // p_bar kernels
   double* __restrict__ iface;
   int nx, ny, s, c0, ib;
   // grid setting 2: coarse planes (see SplitPtrs::gc), sizes and pitch
@@ -118,6 +126,7 @@ struct SplitArgs {
   int east_wall;  // LBM zone closed by a wall at x = nx (LBM-only cavity)
   int kind, mom_all;
   real omega, omegaT, tau, nu, alpha, gbeta, Tref;
+  real ulid;  // north wall velocity along +x
   int tfix[4];
   real Tw[4];
 };
@@ -129,12 +138,12 @@ __device__ __forceinline__ int fidx(const SplitArgs<real>& a, int x) {
 }
 template <typename real>
 __device__ __forceinline__ real U_at(const SplitArgs<real>& a, const real* u, int x, int j) {
-  real sg = real(1);
+  real sg = real(1), lid = real(0);
   if (j < 0) { j = -1 - j; sg = -sg; }
-  else if (j >= a.ny) { j = 2 * a.ny - 1 - j; sg = -sg; }
+  else if (j >= a.ny) { j = 2 * a.ny - 1 - j; sg = -sg; lid = real(2) * a.ulid; }
   if (x > a.nx) { x = 2 * a.nx - x; sg = -sg; }
   else if (x < 0 && a.west_wall) { x = -x; sg = -sg; }
-  return sg * u[j * a.pF + fidx(a, x)];
+  return lid + sg * u[j * a.pF + fidx(a, x)];
 }
 template <typename real>
 __device__ __forceinline__ real V_at(const SplitArgs<real>& a, const real* v, int x, int jf) {
@@ -467,29 +476,58 @@ __global__ __launch_bounds__(256) void k_dd_press_energy(SplitArgs<real> a) {
   else press_energy_at<real, CONV, false>(a, GenAcc<real>{a, x, j}, x, j);
 }
 
-// 4. p_bar: mean new FV pressure over the shared columns; per-block sums
-//    (one thread per row) then an in-order fold by one thread
+// 4. p_bar: mean new FV pressure over the shared columns; and the net mass
+//    the coming stream moves into the LBM zone through the links to x_b:
+//    the post-collision populations x_b sends west (W, NW, SW) less those
+//    x_f sends east (E, NE, SE), each only where its target row exists (a
+//    diagonal leaving through a wall returns to its own node).  Both sets
+//    carry the same weights, so the shifted values give the same sum.
+//    Per-block sums (one thread per row), then an in-order fold by one
+//    thread; the fold adds the flux to the running mass change.
 template <typename real>
 __global__ __launch_bounds__(kGhostBlock) void k_dd_pbar_rows(SplitArgs<real> a) {
-  __shared__ double sh[kGhostBlock];
+  __shared__ double sh[2][kGhostBlock];
   const int j = blockIdx.x * kGhostBlock + threadIdx.x;
-  double s = 0.0;
-  if (j < a.ny)
+  double s = 0.0, fl = 0.0;
+  if (j < a.ny) {
     for (int x = a.c0; x <= a.ib; ++x) s += (double)a.p[j * a.pF + fidx(a, x)];
-  sh[threadIdx.x] = s;
+    const int PL = a.planeL, ob = j * a.pL + a.ib, of = ob - 1;
+    double in = (double)a.fin[3 * PL + ob], out = (double)a.fin[1 * PL + of];
+    if (j + 1 < a.ny) {
+      in += (double)a.fin[6 * PL + ob];
+      out += (double)a.fin[5 * PL + of];
+    }
+    if (j > 0) {
+      in += (double)a.fin[7 * PL + ob];
+      out += (double)a.fin[8 * PL + of];
+    }
+    fl = in - out;
+  }
+  sh[0][threadIdx.x] = s;
+  sh[1][threadIdx.x] = fl;
   __syncthreads();
   for (int k = kGhostBlock / 2; k > 0; k >>= 1) {
-    if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+    if ((int)threadIdx.x < k) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + k];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + k];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) a.iface[kIfacePart + blockIdx.x] = sh[0];
+  if (threadIdx.x == 0) {
+    a.iface[kIfacePart + 2 * blockIdx.x] = sh[0][0];
+    a.iface[kIfacePart + 2 * blockIdx.x + 1] = sh[1][0];
+  }
 }
 
 template <typename real>
 __global__ __launch_bounds__(256) void k_dd_pbar_fold(SplitArgs<real> a, int nblocks) {
   __shared__ double stage[1024];
-  const double t = ordered_sum(a.iface + kIfacePart, nblocks, 1, stage);
-  if (threadIdx.x == 0) a.iface[1] = t / (3.0 * a.ny);
+  const double t = ordered_sum(a.iface + kIfacePart, nblocks, 2, stage);
+  const double tf = ordered_sum(a.iface + kIfacePart + 1, nblocks, 2, stage);
+  if (threadIdx.x == 0) {
+    a.iface[1] = t / (3.0 * a.ny);
+    a.iface[2] += tf;
+  }
 }
 
 // 5. LBM zone, nodes 0 .. ib-1: stream, moments, collide
@@ -546,6 +584,8 @@ __global__ __launch_bounds__(256) void k_dd_lbm(SplitArgs<real> a) {
     const int sx = i - ex9(q), sy = j - ey9(q);
     if (sx >= 0 && !(a.east_wall && sx >= a.nx) && sy >= 0 && sy < a.ny)
       f[q] = a.fin[q * PL + sy * pL + sx];
+    else if (sy >= a.ny)  // the north wall, sliding at ulid: + 6 w_q (e_q . u_w)
+      f[q] = a.fin[opp9(q) * PL + j * pL + i] + real(6) * w9<real>(q) * real(ex9(q)) * a.ulid;
     else f[q] = a.fin[opp9(q) * PL + j * pL + i];  // walls at rest: bounce-back
   }
 #pragma unroll
@@ -597,8 +637,16 @@ __global__ __launch_bounds__(256) void k_dd_xb(SplitArgs<real> a) {
   const real vb = real(0.5) * (a.vs[j * a.pF + fidx(a, ib)] + a.vs[(j + 1) * a.pF + fidx(a, ib)]);
   const real Tb = a.Tn[j * a.pF + fidx(a, ib)];
   const double rho0 = a.iface[0], pbar = a.iface[1];
-  // Eq 93: rho_b = rho0 ((p_S - p_bar) / (rho0 c_s^2) + 1)
-  const double rb = rho0 * (((double)a.p[j * a.pF + fidx(a, ib)] - pbar) / (rho0 / 3.0) + 1.0);
+  // Eq 93: rho_b = rho0 ((p_S - p_bar) / (rho0 c_s^2) + 1), its level shifted
+  // uniformly over the rows by a quarter of the amount that, carried by the
+  // rest weights of the populations x_b sends into the zone (W, NW, SW; one
+  // diagonal fewer on the wall rows), would return the zone to its mass at
+  // init (the whole amount per step overshoots with the finite-difference
+  // closure, whose populations answer the FV pressure one step later)
+  const double wsum = a.ny * ((1.0 / 9.0 + 1.0 / 36.0) + 1.0 / 36.0) - 1.0 / 36.0 - 1.0 / 36.0;
+  const double delta = -a.iface[2] / (4.0 * wsum);
+  const double rb =
+      rho0 * (((double)a.p[j * a.pF + fidx(a, ib)] - pbar) / (rho0 / 3.0) + 1.0) + delta;
   const real drb = (real)(rb - 1.0);
   const real* xf = a.xf + j * 18;
   real f[9], g[5];
@@ -614,7 +662,7 @@ __global__ __launch_bounds__(256) void k_dd_xb(SplitArgs<real> a) {
       return real(0.5) * (a.us[jj * a.pF + fidx(a, ib)] + a.us[jj * a.pF + fidx(a, ib + 1)]);
     };
     const real um = j > 0 ? ucell(j - 1) : -ub;
-    const real up = j < ny - 1 ? ucell(j + 1) : -ub;
+    const real up = j < ny - 1 ? ucell(j + 1) : real(2) * a.ulid - ub;
     const real vw = real(0.5) * (a.vs[j * a.pF + fidx(a, ib - 1)] + a.vs[(j + 1) * a.pF + fidx(a, ib - 1)]);
     const real ve = real(0.5) * (a.vs[j * a.pF + fidx(a, ib + 1)] + a.vs[(j + 1) * a.pF + fidx(a, ib + 1)]);
     const real Sxx = dudx, Syy = -dudx;
@@ -688,6 +736,7 @@ __global__ __launch_bounds__(256) void k_dd_init(SplitArgs<real> a, const double
   if (j >= a.ny) return;
   const auto t0_at = [&](int xx) { return a.transposed ? T0[xx * a.ny + j] : T0[j * a.nx + xx]; };
   const double t0 = (x < a.nx && T0) ? t0_at(x) : 0.0;
+  if (x == 0 && j == 0) a.iface[2] = 0.0;  // the LBM zone's mass change
   if (x < a.nl) {
     const int o = j * a.pL + x;
     real* f = const_cast<real*>(a.fin);
@@ -1114,6 +1163,7 @@ static SplitArgs<real> make_args(const SplitGeom& G, const SplitPtrs<real>& P, c
   a.alpha = real(S.alpha);
   a.gbeta = real(S.gbeta);
   a.Tref = real(S.T_ref);
+  a.ulid = real(S.ulid);
   for (int k = 0; k < 4; ++k) {
     a.tfix[k] = S.tfix[k];
     a.Tw[k] = real(S.Tw[k]);

@@ -500,7 +500,14 @@ lf_status lf_case_set_wall(lf_case* c, int side, const lf_wall* w) {
     return fail(LF_EINVAL, "bad thermal %d", w->thermal);
   if (c->split) {
     if (per) return fail(LF_ENOTIMPL, "periodic sides are not available in the split mode");
-    if (w->u_wall != 0.0) return fail(LF_ENOTIMPL, "moving walls are not available in the split mode");
+    // a sliding lid (Sec. 3.3): the north wall of the split, FV-only and
+    // LBM-only cavities as stored untransposed
+    if (w->u_wall != 0.0 &&
+        (side != LF_SIDE_N || c->sg.transposed || c->sg.gs2 || c->sg.mcm))
+      return fail(LF_ENOTIMPL,
+                  "in the split-family modes only the north wall of LF_MODE_SPLIT, "
+                  "LF_MODE_PURE_FV and LF_MODE_PURE_LBM may move");
+    if (side == LF_SIDE_N && !c->sg.transposed) c->sp.ulid = w->u_wall;
     // stored side (transposed storage: W, E, S, N -> S, N, W, E)
     static const int tmap[4] = {LF_SIDE_S, LF_SIDE_N, LF_SIDE_W, LF_SIDE_E};
     const int ss = c->sg.transposed ? tmap[side] : side;

@@ -153,7 +153,8 @@ struct SplitPtrs {
   real* v[2];   // y-faces, (ny + 1) rows * pF
   real* T[2];   // centres
   real* p;      // centres
-  double* iface;  // [0] rho0, [1] p_bar, from [8] two sums per 256 rows
+  double* iface;  // [0] rho0, [1] p_bar, [2] LBM zone mass minus its value at
+                  // init (carried across steps), from [8] two sums per 256 rows
   // grid setting 2, NYc rows * pC each: T (iterate A), T (iterate B),
   // a_P, a_W, a_E, a_S, a_N, b, and the Thomas sweep's c', r'
   real* gc[10];
@@ -170,6 +171,7 @@ struct SplitParams {
   int kind;   // 0 non-equilibrium extrapolation, 1 finite-difference gradient
   int tfix[4];
   double Tw[4];
+  double ulid;  // tangential velocity of the north wall (split, FV-only, LBM-only)
 };
 
 // One step; the state is read from buffers [cur] and written to [cur ^ 1].
