@@ -298,6 +298,10 @@ class Case:
         return self
 
     def set_wall(self, side, vel=WALL_NOSLIP, u_wall=0.0, thermal=T_ADIABATIC, T_wall=0.0):
+        """One side (W, E, S, N): no-slip wall sliding tangentially at u_wall
+        (in the split, FV-only and LBM-only modes only the north wall, the
+        lid of the lid-driven cavity), or periodic; fixed T_wall or
+        adiabatic."""
         w = lf_wall(int(vel), float(u_wall), int(thermal), float(T_wall))
         _check(_lib.lf_case_set_wall(self._h, int(side), ctypes.byref(w)), "lf_case_set_wall")
         return self
