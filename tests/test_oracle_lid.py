@@ -16,6 +16,11 @@ HERE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 U = 0.1
 
 
+@pytest.fixture(autouse=True)
+def _threads():
+    oracle.set_threads(8)
+
+
 def centres():
     with open(os.path.join(HERE, "paper_tables.json")) as f:
         return json.load(f)["sec33_vortex_centre"]
@@ -94,17 +99,18 @@ def test_lbm_zone_mass_is_held():
     assert np.abs(dm).max() < 0.05, dm
 
 
-def test_natural_convection_split_reaches_steady_state():
-    """64 x 64 cavity, Ra 1e4, Pr 0.71, hybrid method 1: the coupled run
-    reaches a 1e-9 residual and its wall-averaged Nusselt number lies
-    within 1 % of both single methods."""
-    nu = {}
-    for mode in (oracle.SPLIT, oracle.PURE_FV, oracle.PURE_LBM):
-        c = oracle.DDCase(64, 64, mode).set_physics(1e4, 0.71).set_cavity_walls().init()
-        steps, r = c.run_to_steady(tol=1e-9, check_every=1000, max_steps=80000)
-        assert r.max() <= 1e-9, (mode, steps, r)
-        nu[mode] = c.nusselt()
-    s = nu[oracle.SPLIT]
-    assert abs(s["nu_hot"] - s["nu_cold"]) < 1e-3 * s["nu_hot"]
-    for m in (oracle.PURE_FV, oracle.PURE_LBM):
-        assert abs(s["nu_hot"] - nu[m]["nu_hot"]) < 0.01 * nu[m]["nu_hot"], (s, nu[m])
+@pytest.mark.parametrize("iface", [oracle.IFACE_NEQ, oracle.IFACE_FDGRAD])
+def test_natural_convection_split_reaches_steady_state(iface):
+    """64 x 64 cavity, Ra 1e4, Pr 0.71, both hybrid methods: the coupled
+    run reaches a 1e-9 residual (with the shared-column mean as the level
+    it stalled near 5e-6), its hot- and cold-wall Nusselt numbers balance,
+    and their average lies within 1 % of Table 3's reference value (the
+    single methods give 2.2505 and 2.2421 here)."""
+    with open(os.path.join(HERE, "paper_tables.json")) as f:
+        ref = json.load(f)["table3_nu_avg"]["reference_46"]["1e4"]
+    c = oracle.DDCase(64, 64, oracle.SPLIT, iface).set_physics(1e4, 0.71).set_cavity_walls().init()
+    steps, r = c.run_to_steady(tol=1e-9, check_every=1000, max_steps=60000)
+    assert r.max() <= 1e-9, (steps, r)
+    nu = c.nusselt()
+    assert abs(nu["nu_hot"] - nu["nu_cold"]) < 1e-3 * nu["nu_hot"]
+    assert abs(nu["nu_hot"] - ref) < 0.01 * ref, (nu, ref)
