@@ -423,12 +423,34 @@ __device__ __forceinline__ void bstore<double>(double v, __amdgpu_buffer_rsrc_t 
 // and the second pull hits in L2.  A node's arithmetic does not depend on
 // the direction: the face between rows r and r + 1 is always evaluated
 // from (v_r, v_r+1, T_r-1 .. T_r+2) in that order.
-template <typename real, int CONV, int DIR>
+//
+// SIDE 1 / 2: the strip holds the west / east wall (rows still clear of the
+// south and north walls), with the wall-adjacent column an output lane and
+// the column beyond it a lane of the wave.  The march is the interior one
+// plus the general march's wall rules, with the same arithmetic: the three
+// links of the wall lane that cross the wall take the node's own reversed
+// population plus 6 w_q (e_q . u_w) (these three loads carry their whole
+// shift in the per-lane offset: the link's upstream shift, or on the wall
+// lane its own reversed plane; both are non-negative, as the buffer's range
+// check needs),
+// the lane beyond the wall carries the ghost T (2 T_w - T_edge fixed,
+// T_edge adiabatic) for its neighbours' stencils, and the wall face takes
+// the wall rule.  Lanes beyond the wall compute values nobody keeps.
+template <typename real, int CONV, int DIR, int SIDE = 0>
 __device__ void march_interior(const StepArgs<real>& a, int lane, int i, int j0, int j1) {
   static_assert(DIR == 1 || DIR == -1, "march direction");
+  static_assert(SIDE >= 0 && SIDE <= 2, "side wall");
   constexpr int es = sizeof(real);
   const int P = a.pitch;
-  const bool act = lane >= 1 && lane <= kOut;
+  const bool act = lane >= 1 && lane <= kOut && (SIDE != 2 || i < a.nx);
+  // the wall-adjacent lane and the lane beyond the wall
+  const bool wlane = SIDE == 1 ? i == 0 : SIDE == 2 ? i == a.nx - 1 : false;
+  const bool glane = SIDE == 1 ? i == -1 : SIDE == 2 ? i == a.nx : false;
+  // links crossing the wall (pulled from beyond it) and their reverses
+  constexpr int xq0 = SIDE == 2 ? 3 : 1, xq1 = SIDE == 2 ? 6 : 5, xq2 = SIDE == 2 ? 7 : 8;
+  const real uwall = SIDE == 2 ? a.uw[1] : a.uw[0];
+  const bool wfix = SIDE == 2 ? a.tfix[1] : a.tfix[0];
+  const real wallT = SIDE == 2 ? a.Tw[1] : a.Tw[0];
   const unsigned fbytes = 9u * (unsigned)a.plane * es, pbytes = (unsigned)a.plane * es;
   const __amdgpu_buffer_rsrc_t rf = make_rsrc(a.fin, fbytes);
   const __amdgpu_buffer_rsrc_t rT = make_rsrc(a.Tin, pbytes);
@@ -443,10 +465,33 @@ __device__ void march_interior(const StepArgs<real>& a, int lane, int i, int j0,
   const int xoff = (lane < 32 ? -1 : 2) * es;
   const real al = a.alpha;
 
+  // byte shifts of the crossing links: the upstream shift sq[q], or on the
+  // wall lane the node's own reversed population (plane opp(q))
+  int xs[3] = {0, 0, 0};
+  if constexpr (SIDE != 0) {
+    xs[0] = wlane ? opp(xq0) * a.plane * es : sq[xq0];
+    xs[1] = wlane ? opp(xq1) * a.plane * es : sq[xq1];
+    xs[2] = wlane ? opp(xq2) * a.plane * es : sq[xq2];
+  }
   auto load_row = [&](int r, real f[9]) {
     const int vo = (r * P + i) * es;
 #pragma unroll
-    for (int q = 0; q < 9; ++q) f[q] = bload<real>(rf, vo, sq[q]);
+    for (int q = 0; q < 9; ++q) {
+      if (SIDE != 0 && (q == xq0 || q == xq1 || q == xq2))
+        f[q] = bload<real>(rf, vo + (q == xq0 ? xs[0] : q == xq1 ? xs[1] : xs[2]), 0);
+      else
+        f[q] = bload<real>(rf, vo, sq[q]);
+    }
+  };
+  // the wall lane's crossing links: reversed population + moving-wall term
+  auto wall_fix = [&](real f[9]) {
+    if constexpr (SIDE != 0) {
+      const real e0 = real(ey(xq0)) * uwall, e1 = real(ey(xq1)) * uwall,
+                 e2 = real(ey(xq2)) * uwall;
+      f[xq0] = wlane ? f[xq0] + real(6) * wq<real>(xq0) * e0 : f[xq0];
+      f[xq1] = wlane ? f[xq1] + real(6) * wq<real>(xq1) * e1 : f[xq1];
+      f[xq2] = wlane ? f[xq2] + real(6) * wq<real>(xq2) * e2 : f[xq2];
+    }
   };
   auto T_row = [&](int r) { return bload<real>(rT, (r * P + i) * es, 0); };
   // first output row; rows "behind" it are r - DIR, rows "ahead" r + DIR
@@ -471,20 +516,27 @@ __device__ void march_interior(const StepArgs<real>& a, int lane, int i, int j0,
   auto tx_row = [&](int r) { return bload<real>(rT, (r * P + i) * es + xoff, 0); };
   auto lo_row = [&](int r) { return bload<real>(rL, (r * P + i) * es, 0); };
   real txa = tx_row(js), loa = lo_row(js);
+  wall_fix(D);
+  wall_fix(A);
   moments(D, d_unused, u_unused, uy_p);
   moments(A, dr_c, ux_c, uy_c);
   // the face behind the first row
   real Fb = DIR > 0 ? face_flux<real, CONV>(al, uy_p, uy_c, tm2, t1, t2, t3)
                     : face_flux<real, CONV>(al, uy_c, uy_p, t3, t2, t1, tm2);
 
-  auto row = [&](int j, const real (&fc)[9], const real (&fn)[9], real (&fl)[9]) {
+  auto row = [&](int j, const real (&fc)[9], real (&fn)[9], real (&fl)[9]) {
     if (pulled(j + 3 * DIR)) load_row(j + 3 * DIR, fl);  // two rows ahead
     real dr_n, ux_n, uy_n;
+    wall_fix(fn);
     moments(fn, dr_n, ux_n, uy_n);
     const real tx = txa, lo = loa;
     if (inside(j + DIR)) {
       txa = tx_row(j + DIR);
       loa = lo_row(j + DIR);
+    }
+    if constexpr (SIDE != 0) {  // the ghost T beyond the wall
+      const real te = SIDE == 1 ? __shfl_down(t2, 1, 64) : __shfl_up(t2, 1, 64);
+      t2 = glane ? (wfix ? real(2) * wallT - te : te) : t2;
     }
     real tW1 = __shfl_up(t2, 1, 64);
     const real tE1 = __shfl_down(t2, 1, 64);
@@ -492,8 +544,15 @@ __device__ void march_interior(const StepArgs<real>& a, int lane, int i, int j0,
     const real uE = __shfl_down(ux_c, 1, 64);
     if (lane == 0) tW1 = tx;
     if (lane == kOut) tE2 = tx;
-    const real Fe = face_flux<real, CONV>(al, ux_c, uE, tW1, t2, tE1, tE2);
-    const real Fw = __shfl_up(Fe, 1, 64);
+    real Fe = face_flux<real, CONV>(al, ux_c, uE, tW1, t2, tE1, tE2);
+    real Fw = __shfl_up(Fe, 1, 64);
+    if constexpr (SIDE == 1) {
+      const real wW = wfix ? real(-2) * al * (t2 - wallT) : real(0);
+      Fw = wlane ? wW : Fw;
+    } else if constexpr (SIDE == 2) {
+      const real wE = wfix ? real(-2) * al * (wallT - t2) : real(0);
+      Fe = wlane ? wE : Fe;
+    }
     // the face ahead; north minus south either way
     const real Fa = DIR > 0 ? face_flux<real, CONV>(al, uy_c, uy_n, t1, t2, t3, t4)
                             : face_flux<real, CONV>(al, uy_n, uy_c, t4, t3, t2, t1);
@@ -561,10 +620,18 @@ void k_hybrid_step(StepArgs<real> a) {
   const int i = c0 + lane - 1;   // this lane's column
   const int j0 = bnd * a.band;
   const int j1 = min(j0 + a.band, a.ny);
-  const bool interior = c0 - 1 >= 1 && c0 + kOut <= a.nx - 2 && j0 - 1 >= 2 && j1 <= a.ny - 2;
-  if (interior) {
+  const bool rows_in = j0 - 1 >= 2 && j1 <= a.ny - 2;
+  // strips holding the west / east wall: the wall column an output lane with
+  // room for the column beyond it, and no periodic seam
+  const bool west = !a.xper && c0 == 0 && kOut <= a.nx - 2;
+  const bool east = !a.xper && c0 - 1 >= 1 && a.nx - c0 <= kOut - 2;
+  if (rows_in && c0 - 1 >= 1 && c0 + kOut <= a.nx - 2) {
     if (bnd & 1) march_interior<real, CONV, -1>(a, lane, i, j0, j1);
     else march_interior<real, CONV, 1>(a, lane, i, j0, j1);
+  } else if (rows_in && west) {  // upward only: a downward instance spills registers
+    march_interior<real, CONV, 1, 1>(a, lane, i, j0, j1);
+  } else if (rows_in && east) {
+    march_interior<real, CONV, 1, 2>(a, lane, i, j0, j1);
   } else {
     march_general_any<real, CONV>(a, lane, i, j0, j1);
   }

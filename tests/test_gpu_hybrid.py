@@ -170,6 +170,40 @@ def test_residual_mass_and_energy(lf, ctx):
     assert abs(s1 - s0) <= 1e-4 * np.abs(T0).sum()
 
 
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_adiabatic_sliding_side_walls(lf, ctx, prec, tol):
+    """140 x 50: the west wall adiabatic and sliding along +y, the east wall
+    fixed, heated from below: the strips that hold a side wall (rows clear
+    of the south and north walls) take the side-wall march."""
+    nx, ny = 140, 50
+    T0 = perturbation(nx, ny, 11, amp=0.2)
+    walls = {lf.W: (0, 0.02, 1, 0.0), lf.E: (0, 0.0, 0, -0.5),
+             lf.S: (0, 0.0, 0, 0.5), lf.N: (0, 0.0, 1, 0.0)}
+    g, o = make_pair(lf, ctx, nx, ny, prec, lattice=(0.05, 0.04, 3e-4, 0.0), walls=walls, T0=T0)
+    g.step(300)
+    o.step(300)
+    compare(g, o, tol, ("u", "v", "T", "rho"))
+
+
+def test_band_invariance_bitwise_side_walls(lf, ctx):
+    """An adiabatic east wall sliding along -y: bands of 1, 3 and 16 rows
+    cut the side-wall strips differently (side-wall or general march for
+    the same node) and give identical bits."""
+    nx, ny = 150, 60
+    T0 = perturbation(nx, ny, 12, amp=0.2)
+    outs = []
+    for band in (1, 3, 16):
+        ctx.set_band(band)
+        g = lf.Case(ctx, nx, ny, "f32").set_physics(1e5, 0.71).set_cavity_walls()
+        g.set_wall(lf.E, lf.WALL_NOSLIP, -0.02, lf.T_ADIABATIC, 0.0).init(T0)
+        g.step(150)
+        outs.append([g.fetch(f) for f in ("u", "v", "T")])
+    ctx.set_band(0)
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            assert np.array_equal(a, b)
+
+
 def test_band_invariance_bitwise(lf, ctx):
     """The step has no cross-node reduction: any band height gives identical bits."""
     nx, ny = 150, 90
