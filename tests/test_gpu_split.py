@@ -138,6 +138,26 @@ def test_split_full_size_first_steps(lf, ctx):
         assert np.abs(a - b).max() <= 1e-4 * max(np.abs(b).max(), 1e-12) + 1e-12, f
 
 
+@pytest.mark.parametrize("iface", [0, 1])
+def test_split_full_size_20000_steps(lf, ctx, iface):
+    """The 4096 x 4096 split cavity of the benchmark (Ra 1e6, FP32) over
+    20 000 steps with each closure: the fields stay finite, the LBM zone
+    (nodes 0 .. ib) keeps its mass to 1e-6 of its 2050 x 4096 at init (the
+    level of Eq 93), and the wall Nusselt numbers are finite and positive."""
+    n = 4096
+    g = lf.Case(ctx, n, n, "f32", mode=lf.MODE_SPLIT, iface=iface).set_physics(1e6, 0.71)
+    g.set_cavity_walls().init(perturbation(n, n, 1908083860))
+    m0 = g.mass()[0]
+    assert abs(m0 - 2050 * 4096) < 1e-3
+    g.step(20000)
+    for f in ("u", "v", "T"):
+        assert np.isfinite(g.fetch(f)).all(), f
+    assert abs(g.mass()[0] - m0) < 1e-6 * m0
+    nu = g.nusselt()
+    for k in ("nu_hot", "nu_cold"):
+        assert np.isfinite(nu[k]) and 0.0 < nu[k] < 100.0, (k, nu)
+
+
 def pure_pair(lf, ctx, nx, ny, prec, mode, omode, Ra=1e5, Pr=0.71, T0=None, conv=0):
     g = lf.Case(ctx, nx, ny, prec, mode=mode)
     g.set_physics(Ra, Pr, conv=conv).set_cavity_walls().init(T0)
