@@ -185,6 +185,19 @@ def test_adiabatic_sliding_side_walls(lf, ctx, prec, tol):
     compare(g, o, tol, ("u", "v", "T", "rho"))
 
 
+@pytest.mark.parametrize("nx", [184, 185])
+def test_side_wall_strip_limits(lf, ctx, nx):
+    """The east strip takes the side-wall march while the wall column is at
+    most lane 60 (nx = 184: lane 60) and the general march past it
+    (nx = 185: lane 61); FP64 against the oracle."""
+    ny = 40
+    T0 = perturbation(nx, ny, 13, amp=0.2)
+    g, o = make_pair(lf, ctx, nx, ny, "f64", physics=(1e5, 0.71), T0=T0)
+    g.step(200)
+    o.step(200)
+    compare(g, o, 1e-10, ("u", "v", "T", "rho"))
+
+
 def test_band_invariance_bitwise_side_walls(lf, ctx):
     """An adiabatic east wall sliding along -y: bands of 1, 3 and 16 rows
     cut the side-wall strips differently (side-wall or general march for
