@@ -118,6 +118,24 @@ def test_periodic_x_dirichlet_y(lf, ctx, prec, tol):
     compare(g, o, tol, ("u", "v", "T"))
 
 
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_periodic_y_side_walls(lf, ctx, prec, tol):
+    """A vertical slot: periodic along y, hot west and cold east walls, so
+    the side-wall march serves the rows away from the seam and the general
+    march the rows that wrap."""
+    nx, ny = 130, 40
+    walls = {lf.W: (0, 0.0, 0, 0.5), lf.E: (0, 0.0, 0, -0.5),
+             lf.S: (1, 0, 2, 0), lf.N: (1, 0, 2, 0)}
+    T0 = perturbation(nx, ny, 14, amp=0.05)
+    g, o = make_pair(lf, ctx, nx, ny, prec, lattice=(0.05, 0.05, 5e-4, 0.0), walls=walls, T0=T0)
+    g.step(400)
+    o.step(400)
+    compare(g, o, tol, ("v", "T"))
+    # the flow is vertical: u is measured against the slot's velocity scale
+    vs = np.abs(o.fetch("v")).max()
+    assert np.abs(g.fetch("u") - o.fetch("u")).max() <= tol * vs
+
+
 @pytest.mark.parametrize("conv", [1, 2])
 def test_central_and_upwind_convection(lf, ctx, conv):
     nx, ny = 70, 66
