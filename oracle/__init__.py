@@ -1,6 +1,6 @@
 """Plain FP64 CPU oracle for the hybrid LBM-FVM method (arXiv:1908.08386).
 
-TEST INFRASTRUCTURE ONLY: the reference the GPU library is judged against.
+TEST INFRASTRUCTURE ONLY: the reference the GPU library is checked against.
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  It shares no code with the HIP
 library (``paper_1908_08386_amd``) and never imports it.

@@ -5,7 +5,7 @@
  * (arXiv:1908.08386).
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the reference the GPU library is
- * judged against.  Only the test-suite, the smoke check and the CPU-baseline
+ * checked against.  Only the test-suite, the smoke check and the CPU-baseline
  * leg of the benchmark may load it; the product path never does.  It shares
  * no code, header, table or constant generator with the HIP library: every
  * table below is written out here from the paper.
