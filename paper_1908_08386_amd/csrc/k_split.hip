@@ -180,8 +180,9 @@ __device__ __forceinline__ real P_at(const SplitArgs<real>& a, int x, int j) {
 //    (a) one thread per row (and per y-face): ghost values, plus per-block
 //        sums of the inflow face and of rho over the shared columns,
 //        reduced in a fixed order;
-//    (b) one block folds the block sums in order, removes the inflow
-//        face's mean and stores rho0.
+//    (b) one block per 256 rows folds the block sums in order (every block
+//        the same sums in the same order, so the same bits), removes the
+//        inflow face's mean from its rows; the first block stores rho0.
 constexpr int kGhostBlock = 256;
 
 template <typename real>
@@ -251,19 +252,19 @@ __device__ __forceinline__ double ordered_sum(const double* __restrict__ base, i
 }
 
 template <typename real>
-__global__ __launch_bounds__(1024) void k_dd_ghost_fold(SplitArgs<real> a, int nblocks) {
+__global__ __launch_bounds__(kGhostBlock) void k_dd_ghost_fold(SplitArgs<real> a, int nblocks) {
   __shared__ double stage[1024];
   __shared__ real mean_sh;
   const double tu = ordered_sum(a.iface + kIfacePart, nblocks, 2, stage);
-  const double tr = ordered_sum(a.iface + kIfacePart + 1, nblocks, 2, stage);
-  if (threadIdx.x == 0) {
-    mean_sh = (real)(tu / a.ny);
-    a.iface[0] = tr / (3.0 * a.ny);
+  if (threadIdx.x == 0) mean_sh = (real)(tu / a.ny);
+  if (blockIdx.x == 0) {
+    const double tr = ordered_sum(a.iface + kIfacePart + 1, nblocks, 2, stage);
+    if (threadIdx.x == 0) a.iface[0] = tr / (3.0 * a.ny);
   }
   __syncthreads();
   real* u = const_cast<real*>(a.u);
-  const real mean_u = mean_sh;
-  for (int j = threadIdx.x; j < a.ny; j += blockDim.x) u[j * a.pF + fidx(a, a.c0)] -= mean_u;
+  const int j = blockIdx.x * kGhostBlock + threadIdx.x;
+  if (j < a.ny) u[j * a.pF + fidx(a, a.c0)] -= mean_sh;
 }
 
 // ---- field access relative to a thread's face / cell (x, j) ------------
@@ -1188,7 +1189,8 @@ hipError_t launch_split_step(const SplitGeom& G, const SplitPtrs<real>& P, const
   const int ngb = (G.ny + 1 + kGhostBlock - 1) / kGhostBlock;  // rows and y-faces 0 .. ny
   if (split) {
     hipLaunchKernelGGL(k_dd_ghost_rows<real>, dim3(ngb), dim3(kGhostBlock), 0, s, a);
-    hipLaunchKernelGGL(k_dd_ghost_fold<real>, dim3(1), dim3(1024), 0, s, a, ngb);
+    hipLaunchKernelGGL(k_dd_ghost_fold<real>, dim3((G.ny + kGhostBlock - 1) / kGhostBlock),
+                       dim3(kGhostBlock), 0, s, a, ngb);
   }
   if (S.conv == 1) {
     hipLaunchKernelGGL((k_dd_momentum<real, 1>), gm, dim3(256), 0, s, a);
