@@ -139,6 +139,25 @@ def test_split_full_size_first_steps(lf, ctx):
 
 
 @pytest.mark.parametrize("iface", [0, 1])
+def test_split_steady_state_parity(lf, ctx, iface):
+    """64 x 64, Ra 1e4, FP64, both closures run to a 1e-9 residual (the
+    level of Eq 93 gives the split mode a fixed point): the steady fields
+    and Nusselt numbers against the oracle's own steady state."""
+    oracle.set_threads(8)
+    n = 64
+    g = lf.Case(ctx, n, n, "f64", mode=lf.MODE_SPLIT, iface=iface).set_physics(1e4, 0.71)
+    g.set_cavity_walls().init()
+    sg, rg, _ = g.run_to_steady(tol=1e-9, check_every=1000, max_steps=80000)
+    o = oracle.DDCase(n, n, oracle.SPLIT, iface).set_physics(1e4, 0.71).set_cavity_walls().init()
+    so, ro = o.run_to_steady(tol=1e-9, check_every=1000, max_steps=80000)
+    assert sg == so and max(rg) <= 1e-9 and ro.max() <= 1e-9, (sg, so, rg, ro)
+    check(g, o, 1e-8)
+    ng, no = g.nusselt(), o.nusselt()
+    for k in ("nu_hot", "nu_cold", "nu_hot_max"):
+        assert abs(ng[k] - no[k]) <= 1e-8 * abs(no[k]), (k, ng[k], no[k])
+
+
+@pytest.mark.parametrize("iface", [0, 1])
 def test_split_full_size_20000_steps(lf, ctx, iface):
     """The 4096 x 4096 split cavity of the benchmark (Ra 1e6, FP32) over
     20 000 steps with each closure: the fields stay finite, the LBM zone
