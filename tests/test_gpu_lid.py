@@ -99,6 +99,20 @@ def test_lid_single_method_parity(lf, ctx, mode, omode, prec, tol, nx, ny):
 
 
 @pytest.mark.parametrize("iface", [0, 1])
+def test_lid_steady_state_parity(lf, ctx, iface):
+    """64 x 64, Re 100, FP64, both hybrid methods from rest to a 1e-9
+    residual: the same stopping step and the same steady fields as the
+    oracle (1e-8)."""
+    oracle.set_threads(8)
+    g = gpu_lid(lf, ctx, 64, 64, "f64", lf.MODE_SPLIT, iface)
+    sg, rg, _ = g.run_to_steady(tol=1e-9, check_every=1000, max_steps=60000)
+    o = oracle_lid(64, 64, oracle.SPLIT, iface)
+    so, ro = o.run_to_steady(tol=1e-9, check_every=1000, max_steps=60000, fields=(0, 1))
+    assert sg == so and max(rg[:2]) <= 1e-9 and ro[:2].max() <= 1e-9, (sg, so, rg, ro)
+    check(g, o, 1e-8)
+
+
+@pytest.mark.parametrize("iface", [0, 1])
 def test_lid_vortex_centre_re100(lf, ctx, iface):
     """64 x 64, Re 100, FP64 to a 1e-9 residual: the primary-vortex centre
     within one cell of the centres the paper prints (Ref [35], its SIMPLE
