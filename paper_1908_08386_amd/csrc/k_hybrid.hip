@@ -150,13 +150,34 @@ __device__ __forceinline__ real face_value(const int conv, real uf, real tll, re
                        : fma_(real(0.75), tr, fma_(real(0.375), tl, real(-0.125) * trr));
 }
 
+// x / 3 from an unevaluated pair hi + lo = 1/3 (hi the nearest value):
+// within an ulp of the exact quotient and without the common relative error
+// a rounded constant 1/3 would give every node.
+template <typename real>
+__device__ __forceinline__ real third(real x);
+template <>
+__device__ __forceinline__ float third<float>(float x) {
+  return __builtin_fmaf(x, 0x1.555556p-2f, x * -0x1.555556p-27f);
+}
+template <>
+__device__ __forceinline__ double third<double>(double x) {
+  return __builtin_fma(x, 0x1.5555555555555p-2, x * 0x1.5555555555555p-56);
+}
+
 // BGK collision with the buoyancy force, on shifted populations.
 //   f_eq = rho w (1 + P),  P = 3 e.u + 9/2 (e.u)^2 - 3/2 u.u       (Eq 8)
 //   F    = 3 w (G.(e - u)) (1 + P)  = G.(e - u) f_eq / (rho c_s^2) (Eq 18)
 //   f*   = f + (f_eq - f) / tau + F                           (Eq 5 / 19)
 // with G = (gx, g beta (T - T_ref) + gy) (Eq 81).  In shifted form
-// f~_eq = w (drho + rho P).  Opposite directions share e.u up to sign, so
-// they are evaluated in pairs.
+//   f~_eq = w (drho + rho A) + 3 w e.j,  A = 9/2 (e.u)^2 - 3/2 u.u,
+// with j = sum e f~ the streamed momentum (3 w = 1/3 on the axes, 1/12 on
+// the diagonals).  The linear term is built from j itself, not as rho * u:
+// rho = 1 + drho and the weights rounded to FP32 carry relative errors of up
+// to 6e-8 that are the same over regions of nodes, and through the
+// relaxation such an error acts as a body force proportional to the local
+// momentum, which the slowly decaying large-scale modes of a steady cavity
+// amplify by ~ L^2 / nu.  Opposite directions share e.u and e.j up to sign,
+// so they are evaluated in pairs.
 template <typename real>
 __device__ __forceinline__ void collide(const StepArgs<real>& a, const real f[9],
                                         real drho, real ux, real uy, real T,
@@ -167,6 +188,9 @@ __device__ __forceinline__ void collide(const StepArgs<real>& a, const real f[9]
   const real usq = real(1.5) * fma_(ux, ux, uy * uy);
   const real Gu = fma_(Gx, ux, Gy * uy);
   const real om = a.omega;
+  // streamed momentum, summed as in moments()
+  const real jx = (f[1] - f[3]) + ((f[5] - f[6]) + (f[8] - f[7]));
+  const real jy = (f[2] - f[4]) + ((f[5] - f[7]) + (f[6] - f[8]));
   {
     const real w = wq<real>(0);
     const real P = -usq;
@@ -174,19 +198,21 @@ __device__ __forceinline__ void collide(const StepArgs<real>& a, const real f[9]
     const real F = (real(3) * w) * (-Gu) * (real(1) + P);
     out[0] = fma_(om, feq - f[0], f[0]) + F;
   }
-  auto pair = [&](int q, int qb, real eu, real Ge, real w) {
+  auto pair = [&](int q, int qb, real eu, real ej, real Ge, real w, bool diag) {
     const real A = fma_(real(4.5) * eu, eu, -usq);
     const real B = real(3) * eu;
     const real Pq = A + B, Pb = A - B;
-    const real fq = w * fma_(rho, Pq, drho), fb = w * fma_(rho, Pb, drho);
+    const real base = w * fma_(rho, A, drho);
+    const real lin = diag ? real(0.25) * third(ej) : third(ej);
+    const real fq = base + lin, fb = base - lin;
     const real cq = (real(3) * w) * (Ge - Gu), cb = (real(3) * w) * (-Ge - Gu);
     out[q] = fma_(om, fq - f[q], f[q]) + fma_(cq, Pq, cq);
     out[qb] = fma_(om, fb - f[qb], f[qb]) + fma_(cb, Pb, cb);
   };
-  pair(1, 3, ux, Gx, wq<real>(1));
-  pair(2, 4, uy, Gy, wq<real>(2));
-  pair(5, 7, ux + uy, Gx + Gy, wq<real>(5));
-  pair(6, 8, uy - ux, Gy - Gx, wq<real>(6));
+  pair(1, 3, ux, jx, Gx, wq<real>(1), false);
+  pair(2, 4, uy, jy, Gy, wq<real>(2), false);
+  pair(5, 7, ux + uy, jx + jy, Gx + Gy, wq<real>(5), true);
+  pair(6, 8, uy - ux, jy - jx, Gy - Gx, wq<real>(6), true);
 }
 
 // Flux through the face between cells L and R (positive from L to R):

@@ -532,6 +532,26 @@ __global__ __launch_bounds__(256) void k_dd_pbar_fold(SplitArgs<real> a, int nbl
 }
 
 // 5. LBM zone, nodes 0 .. ib-1: stream, moments, collide
+// x / 3 from an unevaluated pair hi + lo = 1/3: within an ulp of the exact
+// quotient, with no relative error common to all nodes.
+template <typename real>
+__device__ __forceinline__ real third(real x);
+template <>
+__device__ __forceinline__ float third<float>(float x) {
+  return __builtin_fmaf(x, 0x1.555556p-2f, x * -0x1.555556p-27f);
+}
+template <>
+__device__ __forceinline__ double third<double>(double x) {
+  return __builtin_fma(x, 0x1.5555555555555p-2, x * 0x1.5555555555555p-56);
+}
+
+// BGK collision with buoyancy on shifted populations (Eq 5, 8, 18):
+//   f~_eq = w (drho + rho A) + 3 w e.j,  A = 9/2 (e.u)^2 - 3/2 u.u,
+// with j = sum e f~ the streamed momentum (3 w = 1/3 on the axes, 1/12 on the
+// diagonals).  Building the linear term from j itself, not as rho * u with
+// rho = 1 + drho and FP32-rounded weights, keeps the equilibrium's momentum
+// free of relative errors shared by whole regions of nodes, which would act
+// as a body force proportional to the momentum.
 template <typename real>
 __device__ __forceinline__ void collide_f(const SplitArgs<real>& a, real f[9], real drho, real ux,
                                           real uy, real T) {
@@ -540,26 +560,38 @@ __device__ __forceinline__ void collide_f(const SplitArgs<real>& a, real f[9], r
   const real G = a.gbeta * (T - a.Tref);
   const real Gu = G * (a.gdir ? ux : uy);
   const real usq = real(1.5) * fmad(ux, ux, uy * uy);
+  const real jx = (f[1] - f[3]) + ((f[5] - f[6]) + (f[8] - f[7]));
+  const real jy = (f[2] - f[4]) + ((f[5] - f[7]) + (f[6] - f[8]));
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
     const real eu = real(ex9(q)) * ux + real(ey9(q)) * uy;
-    const real P = fmad(real(4.5) * eu, eu, real(3) * eu) - usq;
-    const real fe = w9<real>(q) * fmad(rho, P, drho);
+    const real A = fmad(real(4.5) * eu, eu, -usq);
+    const real P = A + real(3) * eu;
+    const real ej = ex9(q) == 0 ? real(ey9(q)) * jy
+                    : ey9(q) == 0 ? real(ex9(q)) * jx
+                                  : real(ex9(q)) * jx + real(ey9(q)) * jy;
+    const real lin = q == 0 ? real(0) : q < 5 ? third(ej) : real(0.25) * third(ej);
+    const real fe = w9<real>(q) * fmad(rho, A, drho) + lin;
     const real eG = real(a.gdir ? ex9(q) : ey9(q)) * G;
     const real c = (real(3) * w9<real>(q)) * (eG - Gu);
     f[q] = fmad(a.omega, fe - f[q], f[q]) + fmad(c, P, c);
   }
 }
 
+// D2Q5 heat collision (Eq 19-22): g_eq = T w (1 + 3 e.u); the rest
+// population takes T minus the four moving ones, so that sum g_eq = T holds
+// without the common relative error of FP32-rounded weights (T / 6 is formed
+// from the unbiased T / 3).
 template <typename real>
 __device__ __forceinline__ void collide_fg(const SplitArgs<real>& a, real f[9], real g[5],
                                            real drho, real ux, real uy, real T) {
   collide_f(a, f, drho, ux, uy, T);
+  const real t6 = real(0.5) * third(T);
+  const real gE = t6 * (real(1) + real(3) * ux), gW = t6 * (real(1) - real(3) * ux);
+  const real gN = t6 * (real(1) + real(3) * uy), gS = t6 * (real(1) - real(3) * uy);
+  const real ge[5] = {T - ((gE + gW) + (gN + gS)), gE, gN, gW, gS};
 #pragma unroll
-  for (int q = 0; q < 5; ++q) {
-    const real ge = T * w5<real>(q) * (real(1) + real(3) * (real(ex5(q)) * ux + real(ey5(q)) * uy));
-    g[q] = fmad(a.omegaT, ge - g[q], g[q]);
-  }
+  for (int q = 0; q < 5; ++q) g[q] = fmad(a.omegaT, ge[q] - g[q], g[q]);
 }
 
 template <typename real>
