@@ -136,6 +136,43 @@ def test_periodic_y_side_walls(lf, ctx, prec, tol):
     assert np.abs(g.fetch("u") - o.fetch("u")).max() <= tol * vs
 
 
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-14), ("f32", 2e-6)])
+@pytest.mark.parametrize("axis,U", [("x", 0.05), ("x", -0.05), ("y", 0.04), ("y", -0.04)])
+def test_quick_wall_ghost_closed_form(lf, ctx, prec, tol, axis, U):
+    """QUICK's upstream ghost 2 T_w - T_edge beyond a fixed-temperature wall,
+    against the closed form it must reproduce: for a temperature linear
+    across the walls every face carries the exact value of the profile, so
+    one step changes each cell by minus the divergence of u_f T(x_f) of the
+    step's own velocities (the diffusive fluxes cancel).  130 cells across
+    the walls: the wall strips' interior march and the general march (rows
+    at the periodic seam) both take the ghost; tolerances absolute (T is
+    0.1 .. 2.7)."""
+    a, b, nw, npd = 0.1, 0.02, 130, 40
+    nx, ny = (nw, npd) if axis == "x" else (npd, nw)
+    g = lf.Case(ctx, nx, ny, prec).set_lattice(0.1, 0.07, 0.0)
+    lo, hi = (lf.W, lf.E) if axis == "x" else (lf.S, lf.N)
+    for sd in ((lf.S, lf.N) if axis == "x" else (lf.W, lf.E)):
+        g.set_wall(sd, 1, 0.0, 2, 0.0)
+    g.set_wall(lo, 0, 0.0, 0, a)
+    g.set_wall(hi, 0, 0.0, 0, a + b * nw)
+    prof = a + b * (np.arange(nw) + 0.5)
+    T0 = np.tile(prof, (ny, 1)) if axis == "x" else np.tile(prof[:, None], (1, nx))
+    vel0 = np.full((ny, nx), U)
+    zero = np.zeros((ny, nx))
+    g.init(T0, vel0 if axis == "x" else zero, zero if axis == "x" else vel0)
+    g.step(1)
+    vel = g.fetch("u" if axis == "x" else "v")
+    T1 = g.fetch("T")
+    Tface = a + b * np.arange(nw + 1)
+    T0a, vela, T1a = (T0, vel, T1) if axis == "x" else (T0.T, vel.T, T1.T)
+    uf = np.zeros((T0a.shape[0], nw + 1))
+    uf[:, 1:-1] = 0.5 * (vela[:, :-1] + vela[:, 1:])
+    F = uf * Tface[None, :]
+    exp = T0a - (F[:, 1:] - F[:, :-1])
+    assert (uf[:, 1].min() > 1e-3) if U > 0 else (uf[:, -2].max() < -1e-3)
+    assert np.abs(T1a - exp).max() <= tol
+
+
 @pytest.mark.parametrize("conv", [1, 2])
 def test_central_and_upwind_convection(lf, ctx, conv):
     nx, ny = 70, 66

@@ -172,6 +172,63 @@ def test_conduction_linear_profile_is_fixed_point_and_nu_is_1_over_A():
     assert np.abs(c2.fetch("T") - lin).max() < 1e-12
 
 
+def linear_ghost_case(case_cls, axis, n_wall, n_per, U, a=0.1, b=0.02, alpha=0.07):
+    """A box with fixed-temperature walls across `axis` (periodic along the
+    other), T linear across the walls and consistent with them
+    (T_w = a at the low wall, a + b n_wall at the high one), uniform
+    velocity U along `axis`.  Returns the case, T0 and the wall-face
+    coordinate of every cell face along `axis`."""
+    nx, ny = (n_wall, n_per) if axis == "x" else (n_per, n_wall)
+    c = case_cls(nx, ny).set_lattice(0.1, alpha, 0.0)
+    lo, hi = (oracle.W, oracle.E) if axis == "x" else (oracle.S, oracle.N)
+    plo, phi = (oracle.S, oracle.N) if axis == "x" else (oracle.W, oracle.E)
+    c.set_wall(lo, oracle.VEL_NOSLIP, 0.0, oracle.T_FIXED, a)
+    c.set_wall(hi, oracle.VEL_NOSLIP, 0.0, oracle.T_FIXED, a + b * n_wall)
+    for sd in (plo, phi):
+        c.set_wall(sd, oracle.VEL_PERIODIC, 0.0, oracle.T_PERIODIC, 0.0)
+    prof = a + b * (np.arange(n_wall) + 0.5)
+    T0 = np.tile(prof, (ny, 1)) if axis == "x" else np.tile(prof[:, None], (1, nx))
+    u0 = np.full((ny, nx), U) if axis == "x" else np.zeros((ny, nx))
+    v0 = np.zeros((ny, nx)) if axis == "x" else np.full((ny, nx), U)
+    c.init(T0, u0, v0)
+    return c, T0, a + b * np.arange(n_wall + 1)
+
+
+def linear_ghost_expected(axis, T0, vel, Tface):
+    """One FV step of a linear profile when every face carries its exact
+    value T(x_f): T1 = T0 - div(u_f T(x_f)); the wall faces carry no flow,
+    and the diffusive fluxes (interior -alpha b, wall half-cell
+    -2 alpha (b / 2)) are all equal and cancel."""
+    if axis == "y":
+        T0, vel = T0.T, vel.T
+    uf = np.zeros((T0.shape[0], T0.shape[1] + 1))
+    uf[:, 1:-1] = 0.5 * (vel[:, :-1] + vel[:, 1:])
+    F = uf * Tface[None, :]
+    T1 = T0 - (F[:, 1:] - F[:, :-1])
+    return (T1.T if axis == "y" else T1), uf
+
+
+@pytest.mark.parametrize("axis,U", [("x", 0.05), ("x", -0.05), ("y", 0.04), ("y", -0.04)])
+def test_quick_wall_ghost_is_exact_on_linear_temperature(axis, U):
+    """QUICK's far-upstream point beyond a fixed-temperature wall is the ghost
+    2 T_w - T_edge, which is exact for a profile linear across the wall; with
+    QUICK exact on quadratics every face then carries the exact value of the
+    profile, so one step must change each cell by minus the divergence of
+    u_f T(x_f) alone.  The flow reaching the wall-adjacent faces from the
+    wall side (u_f of the first face > 0 for U > 0, of the last face < 0 for
+    U < 0) makes those faces use the ghost; the adiabatic ghost T_edge would
+    put their face value off by b / 8."""
+    c, T0, Tface = linear_ghost_case(oracle.Case, axis, 20, 6, U)
+    c.step(1)
+    vel = c.fetch("u" if axis == "x" else "v")
+    exp, uf = linear_ghost_expected(axis, T0, vel, Tface)
+    if U > 0:
+        assert uf[:, 1].min() > 1e-3  # towards +: the low wall's ghost is upstream
+    else:
+        assert uf[:, -2].max() < -1e-3  # towards -: the high wall's ghost is upstream
+    assert np.abs(c.fetch("T") - exp).max() < 1e-15
+
+
 def _laplace_series(X, Y, terms=4001):
     # Eq 112: theta on the unit square with theta = 1 on the top wall only
     th = np.zeros_like(X)
