@@ -102,6 +102,7 @@ def lib() -> ctypes.CDLL:
             L.dd_set_fv.argtypes = [vp, dp, dp, dp]
             L.dd_set_gdir.argtypes = [vp, ctypes.c_int]
             L.dd_set_lid.argtypes = [vp, ctypes.c_double]
+            L.dd_set_level.argtypes = [vp, ctypes.c_double, ctypes.c_double]
             L.dd_zone_mass.restype = ctypes.c_double
             L.dd_zone_mass.argtypes = [vp]
         _lib = L
@@ -310,6 +311,13 @@ class DDCase:
         """The north wall slides along +x at u_wall (lattice units)."""
         if lib().dd_set_lid(self._h, float(u_wall)) != 0:
             raise ValueError("no sliding wall on a periodic axis")
+        return self
+
+    def set_level_gains(self, kp: float, ki: float):
+        """Gains of the level of Eq 93 on the LBM zone's mass deficit and on
+        its running sum (split mode)."""
+        if lib().dd_set_level(self._h, float(kp), float(ki)) != 0:
+            raise ValueError("dd_set_level: gains must be >= 0")
         return self
 
     def zone_mass(self) -> float:

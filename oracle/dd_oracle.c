@@ -87,6 +87,9 @@ typedef struct dd_case {
   double ulid;  /* tangential velocity of the north wall (0: at rest)     */
   double excess0; /* split mode: mass of the LBM nodes 0 .. ib-1 over one
                      per node, at init                                    */
+  double kp, ki;  /* gains of the level of Eq 93 on the zone's mass deficit
+                     and on its running sum                              */
+  double integ;   /* running sum of the deficit over the steps           */
   /* LBM zone, [q][j][i] / [j][i] with nl columns */
   double *f, *fpre, *g, *gpre;
   double *rho, *ux, *uy, *TL; /* moments of the last LBM step (pre-collision) */
@@ -185,6 +188,8 @@ dd_case* dd_create(int nx, int ny, int mode) {
   c->c0 = mode == DD_SPLIT ? c->i0 : 0;
   c->nf = mode == DD_PURE_LBM ? 0 : nx - c->c0 + 3;
   c->tau = c->tauT = 1.0;
+  c->kp = 0.25;
+  c->ki = 1.0 / 64.0;
   c->tfix[SW] = c->tfix[SE] = 1;
   c->Tw[SW] = 0.5;
   c->Tw[SE] = -0.5;
@@ -578,20 +583,27 @@ static void iface_boundary_node(dd_case* c) {
    * columns, follows the LBM zone's own level, so nothing holds the zone's
    * mass: the walls conserve it and it changes only through the links to
    * x_b, by whatever small net flux the coupling leaves.  The boundary
-   * density is therefore shifted, uniformly over the rows, by a quarter of
-   * the amount that -- carried by the rest weights of the populations x_b
+   * density is therefore shifted, uniformly over the rows, by kp times the
+   * amount e that -- carried by the rest weights of the populations x_b
    * sends into the zone (W, NW, SW; one diagonal fewer on the two wall
    * rows) -- would return the zone's mass (nodes 0 .. ib-1, just streamed)
-   * to its value at init.  (The whole amount each step overshoots with the
-   * finite-difference closure: its boundary populations answer the FV
-   * pressure, which answers the shift one step later.)  The mass is summed
-   * as its excess over one per node: each rho - 1 is exact, so the small
-   * deficit does not drown in the rounding of a sum of ones.              */
+   * to its value at init, plus ki times the running sum of e over the
+   * steps.  The sum can only settle where e = 0, so every steady state
+   * holds the zone's mass at its value at init whatever the gains (with
+   * kp alone the steady mass would sit off by an amount inversely
+   * proportional to kp, and the fields with it).  A whole correction each
+   * step overshoots with the finite-difference closure: its boundary
+   * populations answer the FV pressure, which answers the shift one step
+   * later.  The mass is summed as its excess over one per node: each
+   * rho - 1 is exact, so the small deficit does not drown in the rounding
+   * of a sum of ones.                                                     */
   double m = 0.0;
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < ib; ++i) m += LN(c, c->rho, j, i) - 1.0;
   const double wsum = ny * (W9D[3] + W9D[6] + W9D[7]) - W9D[6] - W9D[7];
-  const double delta = (c->excess0 - m) / (4.0 * wsum);
+  const double e = c->excess0 - m;
+  c->integ += e;
+  const double delta = (c->kp * e + c->ki * c->integ) / wsum;
   for (int j = 0; j < ny; ++j) {
     double ub = 0.5 * (FC(c, c->u, j, ib) + FC(c, c->u, j, ib + 1));
     double vb = 0.5 * (FVF(c, c->v, j, ib) + FVF(c, c->v, j + 1, ib));
@@ -700,6 +712,7 @@ int dd_init(dd_case* c, const double* T0) {
   }
   for (int k = 0; k < 3; ++k) dd_output(c, k, c->snap[k]);
   c->excess0 = zone_excess(c);
+  c->integ = 0.0;
   c->steps = 0;
   return 0;
 }
@@ -815,6 +828,7 @@ int dd_init_uniform_flow(dd_case* c, const double* T0, double U, double V) {
       LN(c, c->uy, j, x) = V;
     }
   c->excess0 = zone_excess(c);
+  c->integ = 0.0;
   return 0;
 }
 
@@ -853,3 +867,10 @@ int dd_set_lid(dd_case* c, double u) {
 }
 
 long dd_steps(const dd_case* c) { return c->steps; }
+
+int dd_set_level(dd_case* c, double kp, double ki) {
+  if (!(kp >= 0.0) || !(ki >= 0.0)) return 1;
+  c->kp = kp;
+  c->ki = ki;
+  return 0;
+}

@@ -90,6 +90,9 @@ __device__ __forceinline__ real feq_s(int q, real drho, real ux, real uy) {
 }
 
 constexpr int kIfacePart = 8;
+// gains of the level of Eq 93 on the LBM zone's mass deficit and on its
+// running sum over the steps
+constexpr double kLevelP = 0.25, kLevelI = 1.0 / 64.0;
 
 template <typename real>
 struct SplitArgs {
@@ -528,6 +531,7 @@ __global__ __launch_bounds__(256) void k_dd_pbar_fold(SplitArgs<real> a, int nbl
   if (threadIdx.x == 0) {
     a.iface[1] = t / (3.0 * a.ny);
     a.iface[2] += tf;
+    a.iface[3] -= a.iface[2];  // running sum of the zone's mass deficit
   }
 }
 
@@ -671,13 +675,17 @@ __global__ __launch_bounds__(256) void k_dd_xb(SplitArgs<real> a) {
   const real Tb = a.Tn[j * a.pF + fidx(a, ib)];
   const double rho0 = a.iface[0], pbar = a.iface[1];
   // Eq 93: rho_b = rho0 ((p_S - p_bar) / (rho0 c_s^2) + 1), its level shifted
-  // uniformly over the rows by a quarter of the amount that, carried by the
+  // uniformly over the rows by kLevelP times the amount that, carried by the
   // rest weights of the populations x_b sends into the zone (W, NW, SW; one
   // diagonal fewer on the wall rows), would return the zone to its mass at
-  // init (the whole amount per step overshoots with the finite-difference
-  // closure, whose populations answer the FV pressure one step later)
+  // init, plus kLevelI times the running sum of that deficit over the steps
+  // (iface[3]).  The sum holds the zone's mass at its value at init in any
+  // steady state, whatever the two gains; the partial correction keeps the
+  // finite-difference closure stable (its populations answer the FV
+  // pressure one step later, and a whole correction per step overshoots).
   const double wsum = a.ny * ((1.0 / 9.0 + 1.0 / 36.0) + 1.0 / 36.0) - 1.0 / 36.0 - 1.0 / 36.0;
-  const double delta = -a.iface[2] / (4.0 * wsum);
+  const double e = -a.iface[2];
+  const double delta = (kLevelP * e + kLevelI * a.iface[3]) / wsum;
   const double rb =
       rho0 * (((double)a.p[j * a.pF + fidx(a, ib)] - pbar) / (rho0 / 3.0) + 1.0) + delta;
   const real drb = (real)(rb - 1.0);
@@ -769,7 +777,10 @@ __global__ __launch_bounds__(256) void k_dd_init(SplitArgs<real> a, const double
   if (j >= a.ny) return;
   const auto t0_at = [&](int xx) { return a.transposed ? T0[xx * a.ny + j] : T0[j * a.nx + xx]; };
   const double t0 = (x < a.nx && T0) ? t0_at(x) : 0.0;
-  if (x == 0 && j == 0) a.iface[2] = 0.0;  // the LBM zone's mass change
+  if (x == 0 && j == 0) {
+    a.iface[2] = 0.0;  // the LBM zone's mass change
+    a.iface[3] = 0.0;  // and its running sum
+  }
   if (x < a.nl) {
     const int o = j * a.pL + x;
     real* f = const_cast<real*>(a.fin);
