@@ -23,7 +23,10 @@ What it computes (the readings are listed with the design notes):
   system is solved approximately by K alternating-direction line sweeps
   (x-lines, then y-lines, each line by the Thomas algorithm with the other
   direction's neighbours from the previous iterate), starting from the old
-  T.
+  T, or (solver="direct") exactly by a sparse direct solve.  A fixed point
+  of the sweeps satisfies the whole system (a line relaxation that returns
+  its start solves it), so the steady state does not depend on K and the
+  direct solve is its K-free reference.
 """
 from __future__ import annotations
 
@@ -62,9 +65,12 @@ def quick_face(w, ll, l, r, rr):
 
 
 class GS2Case:
-    def __init__(self, nx: int, ny: int, S: int = 0, K: int = 4):
+    def __init__(self, nx: int, ny: int, S: int = 0, K: int = 4, solver: str = "adi"):
         if nx % 2 or ny % 2 or nx < 8 or ny < 8:
             raise ValueError("nx and ny must be even and >= 8")
+        if solver not in ("adi", "direct"):
+            raise ValueError("solver is 'adi' or 'direct'")
+        self.solver = solver
         self.nx, self.ny = nx, ny
         self.NX, self.NY = nx // 2, ny // 2
         self.S = S if S > 0 else nx  # lattice steps per energy step (2NX)
@@ -249,10 +255,35 @@ class GS2Case:
             X = thomas((-aS).T, aP.T, (-aN).T, ((b + aW * Xw) + aE * Xe).T).T  # y-lines
         return X
 
+    def matrix(self, coef):
+        """The five-point system a_P T_P - sum a_nb T_nb = b as a sparse
+        matrix (rows and columns in row-major cell order)."""
+        import scipy.sparse as sp
+        aP, aW, aE, aS, aN, _ = coef
+        n = aP.size
+        idx = np.arange(n).reshape(aP.shape)
+        rows, cols, vals = [idx.ravel()], [idx.ravel()], [aP.ravel()]
+        for a, dj, di in ((aW, 0, -1), (aE, 0, 1), (aS, -1, 0), (aN, 1, 0)):
+            J, I = np.nonzero(a)
+            rows.append(idx[J, I])
+            cols.append(idx[J + dj, I + di])
+            vals.append(-a[J, I])
+        return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                             (n, n))
+
+    def direct(self, coef):
+        """The implicit energy step solved exactly (sparse LU)."""
+        import scipy.sparse.linalg as spla
+        b = coef[5]
+        return spla.spsolve(self.matrix(coef).tocsc(), b.ravel()).reshape(b.shape)
+
     def fv_step(self):
         U, V = self.face_velocities()
         coef = self.assemble(U, V, self.T)
-        self.T = self.adi(coef, self.T.copy(), self.K)
+        if self.solver == "direct":
+            self.T = self.direct(coef)
+        else:
+            self.T = self.adi(coef, self.T.copy(), self.K)
         self.Tf = self.interp(self.T)
 
     def step(self, n: int):
@@ -262,6 +293,23 @@ class GS2Case:
             if self.steps % self.S == 0:
                 self.fv_step()
         return self
+
+    def run_to_steady(self, tol, cycles=16, max_steps=10**7):
+        """Step in blocks of `cycles` energy cycles until the relative
+        change of u, v and T over a block, ||phi - phi_prev||_2 / ||phi||_2,
+        is at most tol.  Returns the steps taken and the last changes."""
+        K = cycles * self.S
+        prev = [self.ux.copy(), self.uy.copy(), self.Tf.copy()]
+        r = np.full(3, np.inf)
+        while self.steps < max_steps:
+            self.step(K)
+            cur = [self.ux, self.uy, self.Tf]
+            r = np.array([np.linalg.norm(a - b) / max(np.linalg.norm(a), 1e-300)
+                          for a, b in zip(cur, prev)])
+            prev = [a.copy() for a in cur]
+            if r.max() <= tol:
+                break
+        return self.steps, r
 
     # ---- observables ---------------------------------------------------
     def fetch(self, field):

@@ -1,6 +1,8 @@
 """GPU parity of Mode H on grid setting 2 (coarse temperature control volumes
 under the lattice, one implicit energy step per S lattice steps, Sec. 5.1)
 against the FP64 numpy oracle, through the C-ABI library."""
+import os
+
 import numpy as np
 import pytest
 
@@ -117,3 +119,29 @@ def test_gs2_errors(lf, ctx):
     with pytest.raises(lf.LFError) as e:
         g.set_subcycle(-1, 2)
     assert e.value.status == lf.LF_EINVAL
+
+
+GOLDEN_GS2 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "gs2_steady_64.npz")
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-8), ("f32", 1e-4)])
+def test_gs2_steady_state_against_the_exact_implicit_step(lf, ctx, prec, tol):
+    """The library relaxes each implicit energy step by 4 line sweeps; a
+    fixed point of the sweeps solves the whole step, so its steady state is
+    the exact step's.  64 x 64 lattice (32 x 32 control volumes), Ra 1e4,
+    from rest, run to steady (checks every 16 energy cycles; FP64 to a
+    1e-12 change, FP32 to its own stop rule) against the oracle's steady
+    state with every energy step solved exactly (sparse direct solve,
+    tests/golden/gs2_steady_64.npz)."""
+    if not os.path.exists(GOLDEN_GS2):
+        pytest.skip("golden steady state not generated")
+    gd = np.load(GOLDEN_GS2)
+    c = lf.Case(ctx, 64, 64, prec, mode=lf.MODE_HYBRID_GS2).set_physics(1e4, 0.71)
+    c.set_cavity_walls().init()
+    steps, r, rule = c.run_to_steady(tol=1e-12 if prec == "f64" else 1e-8, check_every=1024,
+                                     max_steps=2_000_000)
+    for f in ("u", "v", "T"):
+        assert rel_linf(c.fetch(f), gd[f]) <= tol, (prec, f, steps, r, rule)
+    nu = c.nusselt()
+    for k in ("nu_hot", "nu_cold", "nu_hot_max"):
+        assert abs(nu[k] - float(gd[k])) <= tol * abs(float(gd[k])), (prec, k, nu[k])

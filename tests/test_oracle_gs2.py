@@ -4,8 +4,7 @@ import json
 import os
 
 import numpy as np
-import scipy.sparse as sp
-import scipy.sparse.linalg as spla
+import pytest
 
 from oracle.gs2 import SE, SN, SS, SW, GS2Case, quick_face, thomas
 
@@ -74,15 +73,7 @@ def synthetic_step(seed):
 def test_energy_step_conserves_and_adi_reaches_the_direct_solve():
     c, U, V, T = synthetic_step(3)
     coef = c.assemble(U, V, T)
-    aP, aW, aE, aS, aN, b = coef
-    n = T.size
-    idx = np.arange(n).reshape(T.shape)
-    rows, cols, vals = [idx.ravel()], [idx.ravel()], [aP.ravel()]
-    for a, dj, di in ((aW, 0, -1), (aE, 0, 1), (aS, -1, 0), (aN, 1, 0)):
-        J, I = np.nonzero(a)
-        rows.append(idx[J, I]); cols.append(idx[J + dj, I + di]); vals.append(-a[J, I])
-    A = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), (n, n))
-    direct = spla.spsolve(A.tocsc(), b.ravel()).reshape(T.shape)
+    direct = c.direct(coef)
     X = c.adi(coef, T.copy(), 400)
     assert np.abs(X - direct).max() < 1e-12
     # closed adiabatic box, divergence-free faces: sum T is kept
@@ -108,3 +99,42 @@ def test_table1_table2_at_ra1e4():
     y_ref = tab["table2_y_of_nu_max"]["hybrid"]["1e4"]
     assert abs(nu["y_hot_max"] - y_ref) * 64 <= 1.5, (nu, y_ref)
     assert abs(nu["nu_hot"] - nu["nu_cold"]) <= 1e-6 * nu["nu_hot"]
+
+
+def test_steady_state_does_not_depend_on_the_sweep_count():
+    """The line sweeps only relax each implicit energy step, but a fixed
+    point of theirs solves the step's whole system (a relaxation that
+    returns its start satisfies the equations it relaxes), so the coupled
+    steady state is that of the exact implicit step: 24 x 24 lattice
+    (12 x 12 control volumes), Ra 1e4, with 4 sweeps and with 1 sweep per
+    energy step against the sparse direct solve, each run until u, v and T
+    change by at most 1e-12 over 16 energy cycles."""
+    out = {}
+    for solver, K in (("direct", 4), ("adi", 4), ("adi", 1)):
+        c = GS2Case(24, 24, K=K, solver=solver).set_physics(1e4, 0.71).init()
+        steps, r = c.run_to_steady(1e-12, cycles=16, max_steps=200_000)
+        assert r.max() <= 1e-12, (solver, K, steps, r)
+        out[(solver, K)] = ([c.fetch(k) for k in ("u", "v", "T")], c.nusselt()["nu_hot"])
+    ref = out[("direct", 4)]
+    for key in (("adi", 4), ("adi", 1)):
+        for a, b in zip(out[key][0], ref[0]):
+            assert np.abs(a - b).max() <= 1e-9 * np.abs(b).max(), key
+        assert abs(out[key][1] - ref[1]) <= 1e-10 * ref[1], key
+
+
+def test_stored_direct_solve_steady_state():
+    """The stored 64 x 64 steady state of the exact implicit step (written by
+    tests/golden/make_gs2_steady.py from the oracle): steady, hot and cold
+    walls balanced, Nu_max within 3 % of Table 1 (this method and Ref [41])
+    and its height within 1.5 lattice cells of Table 2."""
+    p = os.path.join(HERE, "gs2_steady_64.npz")
+    if not os.path.exists(p):
+        pytest.skip("golden steady state not generated")
+    g = np.load(p)
+    assert float(np.max(g["change"])) <= float(g["tol"]) == 1e-12
+    assert abs(float(g["nu_hot"]) - float(g["nu_cold"])) <= 1e-8 * float(g["nu_hot"])
+    with open(os.path.join(HERE, "paper_tables.json")) as f:
+        tab = json.load(f)
+    for ref in (tab["table1_nu_max"]["hybrid"]["1e4"], tab["table1_nu_max"]["reference_41"]["1e4"]):
+        assert abs(float(g["nu_hot_max"]) - ref) / ref < 0.03
+    assert abs(float(g["y_hot_max"]) - tab["table2_y_of_nu_max"]["hybrid"]["1e4"]) * 64 <= 1.5
