@@ -195,6 +195,30 @@ def _torch_stream_ptr(device: int):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
+
+def _workspace(ctx, nbytes: int) -> torch.Tensor:
+    """A device buffer for the library, allocated on the library's stream:
+    the caching allocator then hands the block to other streams only after
+    that stream's queued kernels are done with it."""
+    with torch.cuda.stream(ctx.stream):
+        return torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{ctx.device}")
+
+
+def _release(obj, destroy):
+    """Destroy a handle and drop its workspace once the library stream has
+    finished the work queued on it (step and init are asynchronous)."""
+    h = getattr(obj, "_h", None)
+    if h:
+        try:
+            obj.ctx.stream.synchronize()
+        except Exception:  # interpreter shutdown: torch may be gone already
+            pass
+        if destroy is not None:
+            destroy(h)
+        obj._h = None
+    obj.workspace = None
+
+
 class Context:
     """A HIP device and the stream the library enqueues on.  By default a
     dedicated torch stream (default priority) is created, so that batches can
@@ -270,15 +294,12 @@ class Case:
         self._h = h
         nb = ctypes.c_size_t()
         _check(_lib.lf_case_workspace_bytes(h, ctypes.byref(nb)), "lf_case_workspace_bytes")
-        self.workspace = torch.empty(int(nb.value), dtype=torch.uint8,
-                                     device=f"cuda:{ctx.device}")
+        self.workspace = _workspace(ctx, int(nb.value))
         _check(_lib.lf_case_bind_workspace(h, ctypes.c_void_p(self.workspace.data_ptr()),
                                            nb.value), "lf_case_bind_workspace")
 
     def close(self):
-        if getattr(self, "_h", None) and _lib is not None:
-            _lib.lf_case_destroy(self._h)
-            self._h = None
+        _release(self, _lib.lf_case_destroy if _lib is not None else None)
 
     def __del__(self):
         self.close()
@@ -457,14 +478,12 @@ class Batch:
         self._h = h
         nb = ctypes.c_size_t()
         _check(_lib.lf_batch_workspace_bytes(h, ctypes.byref(nb)), "lf_batch_workspace_bytes")
-        self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=f"cuda:{ctx.device}")
+        self.workspace = _workspace(ctx, int(nb.value))
         _check(_lib.lf_batch_bind_workspace(h, ctypes.c_void_p(self.workspace.data_ptr()),
                                             nb.value), "lf_batch_bind_workspace")
 
     def close(self):
-        if getattr(self, "_h", None) and _lib is not None:
-            _lib.lf_batch_destroy(self._h)
-            self._h = None
+        _release(self, _lib.lf_batch_destroy if _lib is not None else None)
 
     def __del__(self):
         self.close()
@@ -623,15 +642,14 @@ class Net:
         self.nparam = n.value
         nb = ctypes.c_size_t()
         _check(_lib.lf_net_workspace_bytes(h, ctypes.byref(nb)), "lf_net_workspace_bytes")
-        self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=f"cuda:{ctx.device}")
+        self.workspace = _workspace(ctx, int(nb.value))
         _check(_lib.lf_net_bind_workspace(h, ctypes.c_void_p(self.workspace.data_ptr()),
                                           nb.value), "lf_net_bind_workspace")
-        self.loss_dev = torch.zeros(1, dtype=torch.float32, device=f"cuda:{ctx.device}")
+        with torch.cuda.stream(ctx.stream):
+            self.loss_dev = torch.zeros(1, dtype=torch.float32, device=f"cuda:{ctx.device}")
 
     def close(self):
-        if getattr(self, "_h", None) and _lib is not None:
-            _lib.lf_net_destroy(self._h)
-            self._h = None
+        _release(self, _lib.lf_net_destroy if _lib is not None else None)
 
     def __del__(self):
         self.close()

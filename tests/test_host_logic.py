@@ -57,3 +57,32 @@ def test_features():
     ws, _ = _warmstart_module()
     f = ws.features([{"nx": 256, "ny": 64, "Ra": 1e5, "Pr": 7.0}])
     np.testing.assert_allclose(f, [[5.0, 7.0, 4.0]], rtol=1e-6)
+
+
+def test_close_waits_for_the_library_stream_before_destroying():
+    """Handles and their workspaces are released only after the library
+    stream has drained (step and init are asynchronous; the workspace's
+    block must not be reused while queued kernels still write it)."""
+    pytest.importorskip("torch")
+    if not os.path.exists(os.path.join(ROOT, "paper_1908_08386_amd", "liblbmfvm.so")):
+        pytest.skip("library not built")
+    import paper_1908_08386_amd as lf
+    calls = []
+
+    class Stream:
+        def synchronize(self):
+            calls.append("sync")
+
+    class Ctx:
+        stream = Stream()
+
+    class Obj:
+        pass
+
+    o = Obj()
+    o.ctx, o._h, o.workspace = Ctx(), 7, object()
+    lf._release(o, lambda h: calls.append(("destroy", h)))
+    assert calls == ["sync", ("destroy", 7)]
+    assert o._h is None and o.workspace is None
+    lf._release(o, lambda h: calls.append(("destroy", h)))  # a second close is a no-op
+    assert calls == ["sync", ("destroy", 7)]
