@@ -236,6 +236,18 @@ lf_status lf_case_step(lf_case* c, int64_t nsteps);
  * snapshot (absolute when ||phi|| < 1e-300), then re-snapshot.
  * LF_EDIVERGED on NaN/Inf.                                                */
 lf_status lf_case_residual(lf_case* c, double r[3]);
+/* lf_case_residual for callers that cannot allocate device memory (code
+ * under graph capture, tight serving loops, harnesses that forbid it): the
+ * residual's per-block FP64 partials and its fold's output live in a device
+ * array the library holds for the life of the process, one copy per GPU
+ * (8200 doubles: partials of up to 1024 blocks, which covers every case the
+ * library creates; LF_EINVAL beyond), instead of in the bound workspace.
+ * Same result as lf_case_residual, bit for bit, with the same re-snapshot;
+ * nothing in the array has to start at zero (each call writes every entry
+ * it reads).  All calls on one GPU share that array: calls that overlap on
+ * one GPU (other streams or host threads) race and must be serialised by
+ * the caller.  Synchronises the stream.                                   */
+lf_status lf_case_residual_noalloc(lf_case* c, double r[3]);
 /* Step in blocks of check_every until max r <= tol (or all r = 0); in FP32
  * also stop "at the rounding floor" when max r <= 1e-6 and the last four
  * checks set no new minimum of max r (noise, not slow decay).  r_final receives the last r;

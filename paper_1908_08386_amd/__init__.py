@@ -107,6 +107,7 @@ _SIGS = {
     "lf_case_init": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
     "lf_case_step": (ctypes.c_int, [_vp, _i64]),
     "lf_case_residual": (ctypes.c_int, [_vp, _dp]),
+    "lf_case_residual_noalloc": (ctypes.c_int, [_vp, _dp]),
     "lf_case_run_to_steady": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_int, _i64,
                                              ctypes.POINTER(_i64), _dp,
                                              ctypes.POINTER(ctypes.c_int)]),
@@ -389,6 +390,14 @@ class Case:
     def residual(self) -> np.ndarray:
         r = np.zeros(3)
         _check(_lib.lf_case_residual(self._h, _dptr(r)), "lf_case_residual")
+        return r
+
+    def residual_noalloc(self) -> np.ndarray:
+        """lf_case_residual_noalloc: the same residual with its partials in
+        the library's per-GPU static scratch (for callers that cannot
+        allocate); calls overlapping on one GPU race."""
+        r = np.zeros(3)
+        _check(_lib.lf_case_residual_noalloc(self._h, _dptr(r)), "lf_case_residual_noalloc")
         return r
 
     def run_to_steady(self, tol=1e-8, check_every=1000, max_steps=10**7, raise_on_notconv=True):

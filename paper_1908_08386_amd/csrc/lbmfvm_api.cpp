@@ -7,6 +7,7 @@
 #include <stdarg.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -209,6 +210,39 @@ extern "C" {
 int lf_abi_version(void) { return LF_ABI_VERSION; }
 const char* lf_last_error(void) { return g_err; }
 
+}  // extern "C"
+
+// Scratch of lf_case_residual_noalloc: the residual's per-block FP64
+// partials (8 doubles per block, at most kNoallocBlocks blocks) followed by
+// the fold's 8 outputs, in a device array the process holds instead of the
+// case workspace's partials area.  Each GPU has its own copy at its own
+// address, looked up once per device when a context is created on it; host
+// code uses only that address (the array's name is a host-side stand-in).
+namespace {
+constexpr int kNoallocBlocks = 1024;
+constexpr int kNoallocDoubles = kNoallocBlocks * 8 + 8;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices];
+}  // namespace
+static __device__ __align__(256) double scratch[kNoallocDoubles];
+
+// with `dev` current
+static lf_status scratch_lookup(int dev) {
+  if (dev >= kMaxDevices) return fail(LF_EINVAL, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return LF_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    return fail(LF_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                hipGetErrorString(e));
+  g_scratch_ptr[dev] = (double*)p;
+  return LF_OK;
+}
+
+extern "C" {
+
 lf_status lf_ctx_create(int hip_device, void* hip_stream, lf_ctx** out) {
   if (!out) return fail(LF_EINVAL, "out is NULL");
   int n = 0;
@@ -216,6 +250,8 @@ lf_status lf_ctx_create(int hip_device, void* hip_stream, lf_ctx** out) {
   if (hip_device < 0 || hip_device >= n)
     return fail(LF_EINVAL, "device %d out of range (%d devices)", hip_device, n);
   HIP_TRY(hipSetDevice(hip_device));
+  const lf_status ss = scratch_lookup(hip_device);
+  if (ss != LF_OK) return ss;
   lf_ctx* c = new (std::nothrow) lf_ctx;
   if (!c) return fail(LF_ENOMEM, "ctx allocation");
   memset(c, 0, sizeof(*c));
@@ -711,12 +747,12 @@ lf_status lf_case_steps(const lf_case* c, int64_t* steps) {
   return LF_OK;
 }
 
-lf_status lf_case_residual(lf_case* c, double r[3]) {
-  if (!c || !r) return fail(LF_EINVAL, "NULL argument");
-  if (!c->inited) return fail(LF_ESTATE, "init first");
+}  // extern "C"
+
+// the residual with its partials in `part` (c->nblk blocks x 8 doubles) and
+// the fold's output in `out` (7 doubles)
+static lf_status case_residual(lf_case* c, double* part, double* out, double r[3]) {
   hipStream_t s = c->ctx->stream;
-  double* out = (double*)(c->ws + c->off_out);
-  double* part = (double*)(c->ws + c->off_part);
   if (c->split) {
     const lf::Grid dg = dense_grid(c);
     const size_t n = (size_t)dg.plane;
@@ -752,6 +788,25 @@ lf_status lf_case_residual(lf_case* c, double r[3]) {
   if (h[6] != 0.0) return fail(LF_EDIVERGED, "%.0f non-finite values after %lld steps", h[6],
                                (long long)c->steps);
   return LF_OK;
+}
+
+extern "C" {
+
+lf_status lf_case_residual(lf_case* c, double r[3]) {
+  if (!c || !r) return fail(LF_EINVAL, "NULL argument");
+  if (!c->inited) return fail(LF_ESTATE, "init first");
+  return case_residual(c, (double*)(c->ws + c->off_part), (double*)(c->ws + c->off_out), r);
+}
+
+lf_status lf_case_residual_noalloc(lf_case* c, double r[3]) {
+  if (!c || !r) return fail(LF_EINVAL, "NULL argument");
+  if (!c->inited) return fail(LF_ESTATE, "init first");
+  if (c->nblk > kNoallocBlocks)
+    return fail(LF_EINVAL, "residual needs %d partial blocks, the static scratch holds %d",
+                c->nblk, kNoallocBlocks);
+  double* part = g_scratch_ptr[c->ctx->device];
+  if (!part) return fail(LF_ESTATE, "no scratch address for device %d", c->ctx->device);
+  return case_residual(c, part, part + (size_t)kNoallocBlocks * 8, r);
 }
 
 lf_status lf_case_run_to_steady(lf_case* c, double tol, int check_every, int64_t max_steps,
