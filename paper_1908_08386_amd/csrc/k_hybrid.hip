@@ -178,10 +178,11 @@ __device__ __forceinline__ double third<double>(double x) {
 // momentum, which the slowly decaying large-scale modes of a steady cavity
 // amplify by ~ L^2 / nu.  Opposite directions share e.u and e.j up to sign,
 // so they are evaluated in pairs.
-template <typename real>
+// Each post-collision population goes to put(q, value) as soon as it is
+// formed, so that the nine need not be held together.
+template <typename real, typename Put>
 __device__ __forceinline__ void collide(const StepArgs<real>& a, const real f[9],
-                                        real drho, real ux, real uy, real T,
-                                        real out[9]) {
+                                        real drho, real ux, real uy, real T, Put&& put) {
   const real rho = real(1) + drho;
   const real Gx = a.gx;
   const real Gy = fma_(a.gbeta, T - a.Tref, a.gy);
@@ -196,7 +197,7 @@ __device__ __forceinline__ void collide(const StepArgs<real>& a, const real f[9]
     const real P = -usq;
     const real feq = w * fma_(rho, P, drho);
     const real F = (real(3) * w) * (-Gu) * (real(1) + P);
-    out[0] = fma_(om, feq - f[0], f[0]) + F;
+    put(0, fma_(om, feq - f[0], f[0]) + F);
   }
   auto pair = [&](int q, int qb, real eu, real ej, real Ge, real w, bool diag) {
     const real A = fma_(real(4.5) * eu, eu, -usq);
@@ -206,8 +207,8 @@ __device__ __forceinline__ void collide(const StepArgs<real>& a, const real f[9]
     const real lin = diag ? real(0.25) * third(ej) : third(ej);
     const real fq = base + lin, fb = base - lin;
     const real cq = (real(3) * w) * (Ge - Gu), cb = (real(3) * w) * (-Ge - Gu);
-    out[q] = fma_(om, fq - f[q], f[q]) + fma_(cq, Pq, cq);
-    out[qb] = fma_(om, fb - f[qb], f[qb]) + fma_(cb, Pb, cb);
+    put(q, fma_(om, fq - f[q], f[q]) + fma_(cq, Pq, cq));
+    put(qb, fma_(om, fb - f[qb], f[qb]) + fma_(cb, Pb, cb));
   };
   pair(1, 3, ux, jx, Gx, wq<real>(1), false);
   pair(2, 4, uy, jy, Gy, wq<real>(2), false);
@@ -226,10 +227,8 @@ __device__ __forceinline__ real face_flux(real al, real uL, real uR, real tll, r
 }
 
 template <typename real>
-__device__ __forceinline__ void store_node(const StepArgs<real>& a, int o, const real fo[9],
-                                           real Tnew, real drho, real ux, real uy) {
-#pragma unroll
-  for (int q = 0; q < 9; ++q) a.fout[q * a.plane + o] = fo[q];
+__device__ __forceinline__ void store_node(const StepArgs<real>& a, int o, real Tnew, real drho,
+                                           real ux, real uy) {
   a.Tout[o] = Tnew;
   if (a.mom) {
     a.mom[o] = real(1) + drho;
@@ -364,9 +363,9 @@ __device__ void march_general(const StepArgs<real>& a, int lane, int i, int j0, 
       Tnew = t2 - (Fe - Fw) - (Fn - Fs);
     }
     if (act) {
-      real fo[9];
-      collide(a, fc, dr_c, ux_c, uy_c, Tnew, fo);
-      store_node(a, j * P + i, fo, Tnew, dr_c, ux_c, uy_c);
+      const int o = j * P + i;
+      collide(a, fc, dr_c, ux_c, uy_c, Tnew, [&](int q, real v) { a.fout[q * plane + o] = v; });
+      store_node(a, o, Tnew, dr_c, ux_c, uy_c);
       if (a.Tlo_out) a.Tlo_out[j * P + i] = Tlo;
     }
     if (j + 1 == j1) break;
@@ -590,12 +589,10 @@ __device__ void march_interior(const StepArgs<real>& a, int lane, int i, int j0,
       Tnew = t2 - (Fe - Fw) - dFy;
     }
     if (act) {
-      real fo[9];
-      collide(a, fc, dr_c, ux_c, uy_c, Tnew, fo);
-      if (a.Tlo_out) a.Tlo_out[j * P + i] = Tlo;
       const int vo = (j * P + i) * es;
-#pragma unroll
-      for (int q = 0; q < 9; ++q) bstore<real>(fo[q], wf, vo, q * a.plane * es);
+      collide(a, fc, dr_c, ux_c, uy_c, Tnew,
+              [&](int q, real v) { bstore<real>(v, wf, vo, q * a.plane * es); });
+      if (a.Tlo_out) a.Tlo_out[j * P + i] = Tlo;
       bstore<real>(Tnew, wT, vo, 0);
       if (a.mom) {
         const int o = j * P + i;
