@@ -676,8 +676,14 @@ void k_hybrid_step(StepArgs<real> a) {
 // launches with alternating parity can be captured in a graph once and
 // replayed; the number of live tiles is read from device memory, so the
 // same graph serves a shrinking set of unconverged cavities.
+// The batched kernel is compiled for 4 waves per SIMD (up to 128 VGPRs): with
+// the side-wall marches it needs 108 and would spill at 5.  Measured on the
+// 256-cavity sweep, 1.076 ms per step at 4 waves with the side-wall marches
+// against 1.131 ms at 5 waves with the general march on those strips.
+#define LF_BATCH_WAVES(real) (sizeof(real) == 4 ? 4 : 2)
+
 template <typename real, int CONV>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LF_STEP_WAVES(real))))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LF_BATCH_WAVES(real))))
 void k_batch_step(const TileDesc* __restrict__ tiles, const int* __restrict__ ntiles,
                   const CavDesc<real>* __restrict__ cavs, int parity, int write_mom) {
   // The grid is sized for the largest tile table (band 1, all cavities
@@ -732,12 +738,20 @@ void k_batch_step(const TileDesc* __restrict__ tiles, const int* __restrict__ nt
   const int c0 = t.strip * kOut;
   const int i = c0 + lane - 1;
   const int j0 = t.j0, j1 = t.j1;
-  const bool interior = c0 - 1 >= 1 && c0 + kOut <= a.nx - 2 && j0 - 1 >= 2 && j1 <= a.ny - 2;
+  const bool rows_in = j0 - 1 >= 2 && j1 <= a.ny - 2;
+  const bool interior = c0 - 1 >= 1 && c0 + kOut <= a.nx - 2 && rows_in;
+  // strips holding the west / east wall, as in the single-cavity kernel
+  const bool west = c0 == 0 && kOut <= a.nx - 2;
+  const bool east = c0 - 1 >= 1 && a.nx - c0 <= kOut - 2;
   // march direction alternates with the band index (a cavity's last, shorter
   // band may share its neighbour's direction; only cache reuse depends on it)
   if (interior) {
     if ((j0 / (j1 - j0)) & 1) march_interior<real, CONV, -1>(a, lane, i, j0, j1);
     else march_interior<real, CONV, 1>(a, lane, i, j0, j1);
+  } else if (rows_in && west) {
+    march_interior<real, CONV, 1, 1>(a, lane, i, j0, j1);
+  } else if (rows_in && east) {
+    march_interior<real, CONV, 1, 2>(a, lane, i, j0, j1);
   } else {
     march_general<real, CONV, false, false>(a, lane, i, j0, j1);  // batches: no periodic sides
   }
