@@ -249,10 +249,12 @@ lf_status lf_case_residual(lf_case* c, double r[3]);
  * the caller.  Synchronises the stream.                                   */
 lf_status lf_case_residual_noalloc(lf_case* c, double r[3]);
 /* Step in blocks of check_every until max r <= tol (or all r = 0); in FP32
- * also stop "at the rounding floor" when max r <= 1e-6 and the last four
- * checks set no new minimum of max r (noise, not slow decay).  r_final receives the last r;
- * *rule (may be NULL) LF_STOP_TOL or LF_STOP_FLOOR.  LF_ENOTCONV at
- * max_steps.                                                              */
+ * also stop "at the rounding floor": max r <= 1e-6, the last four checks set
+ * no new minimum of max r (noise, not slow decay), and the slowest mode,
+ * extrapolated from the decade of decay above the floor (its per-check
+ * factor lambda), has since fallen to a remaining relative change
+ * r lambda / (1 - lambda) <= 2e-6.  r_final receives the last r; *rule (may
+ * be NULL) LF_STOP_TOL or LF_STOP_FLOOR.  LF_ENOTCONV at max_steps.        */
 lf_status lf_case_run_to_steady(lf_case* c, double tol, int check_every,
                                 int64_t max_steps, int64_t* steps_taken,
                                 double r_final[3], int* rule);
@@ -303,7 +305,10 @@ lf_status lf_batch_create(lf_ctx* ctx, int n, const lf_case_desc* descs,
 lf_status lf_batch_destroy(lf_batch* b);
 lf_status lf_batch_workspace_bytes(const lf_batch* b, size_t* bytes);
 lf_status lf_batch_bind_workspace(lf_batch* b, void* dev_ptr, size_t bytes);
-/* Rows per wave tile for cavity idx (-1: all cavities).                   */
+/* Rows per wave tile for cavity idx (-1: all cavities); 0 = by load, the
+ * default without an autotuner table: 4 while the live cavities yield at
+ * least 8192 tiles at 4 rows, else 2 if that reaches it, else 1 (re-chosen
+ * whenever the live set changes).                                         */
 lf_status lf_batch_set_band(lf_batch* b, int idx, int rows);
 /* Initial state per cavity from n host pointers each (NULL array or NULL
  * entry = 0), as lf_case_init.  All cavities become live.                 */

@@ -23,19 +23,7 @@ static inline size_t lf_align_up(size_t v, size_t a) { return (v + a - 1) / a * 
 // lattice parameters from Ra, Pr, U_char (0 = default rule), T_ref (NaN = 0)
 lf_status lf_derive_params(const lf_physics* ph, int ny, int split, double out[8]);
 
-// FP32 rounding floor of the residual: the largest residual is <= 1e-6 and
-// the last four checks set no new minimum (noise around a floor, not a slow
-// decay, which keeps setting new minima)
-#include <vector>
-static inline bool lf_at_floor(const std::vector<double>& h) {
-  const size_t n = h.size();
-  if (n < 6 || h[n - 1] > 1e-6) return false;
-  double before = h[0];
-  for (size_t k = 1; k + 4 < n; ++k) before = h[k] < before ? h[k] : before;
-  for (size_t k = n - 4; k < n; ++k)
-    if (h[k] < before) return false;
-  return true;
-}
+#include "lf_stop.h"
 
 // band heights chosen per cavity-height class by the autotuner (0 = none)
 struct lf_tuning {

@@ -83,6 +83,11 @@ def test_prediction_path_vs_fp64(lf, ws, ctx, net):
 
 
 def test_warm_and_cold_reach_the_same_steady_state(lf, ws, ctx, net):
+    """Six held-out sweep cavities (ny <= 64) from the cold and from the
+    learned start, each run to the same stop rule: every run stops by the
+    rule (not the step limit), warm and cold Nusselt numbers agree to 1e-4,
+    and the learned start gains: the median warm/cold step ratio is below
+    0.8."""
     held = cavity_sweep(6, SEED_HELDOUT, max_ny=64)
     T0 = [perturbation(c["nx"], c["ny"], c["seed"]) for c in held]
     res = ws.compare(ctx, net, held, T0, max_steps=1_500_000, chunk=500_000)
@@ -90,3 +95,6 @@ def test_warm_and_cold_reach_the_same_steady_state(lf, ws, ctx, net):
         assert np.all((rules == lf.STOP_TOL) | (rules == lf.STOP_FLOOR)), res
     dnu = np.abs(res["nu_warm"] - res["nu_cold"]) / np.abs(res["nu_cold"])
     assert dnu.max() <= 1e-4, (dnu, res)
+    ratio = res["steps_warm"] / res["steps_cold"]
+    print(f"warm/cold steps {ratio.round(3).tolist()}, max dNu/Nu {dnu.max():.2e}", flush=True)
+    assert np.median(ratio) < 0.8, (ratio, res)

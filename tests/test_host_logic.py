@@ -86,3 +86,56 @@ def test_close_waits_for_the_library_stream_before_destroying():
     assert o._h is None and o.workspace is None
     lf._release(o, lambda h: calls.append(("destroy", h)))  # a second close is a no-op
     assert calls == ["sync", ("destroy", 7)]
+
+
+def _floor_rule_driver(tmp_path):
+    src = tmp_path / "floor.cpp"
+    src.write_text(
+        '#include "lf_stop.h"\n#include <cstdio>\n'
+        "int main() { int n; if (scanf(\"%d\", &n) != 1) return 1; std::vector<double> h(n);\n"
+        "  for (auto& x : h) if (scanf(\"%lf\", &x) != 1) return 1;\n"
+        "  std::vector<double> p;\n"
+        "  for (int k = 0; k < n; ++k) { p.push_back(h[k]);\n"
+        "    if (lf_at_floor(p)) { printf(\"%d\\n\", k + 1); return 0; } }\n"
+        "  printf(\"0\\n\"); return 0; }\n")
+    exe = tmp_path / "floor"
+    subprocess.run(["g++", "-O1", "-std=c++17", "-I",
+                    os.path.join(ROOT, "paper_1908_08386_amd", "csrc"), str(src), "-o", str(exe)],
+                   check=True)
+    return exe
+
+
+def _fires(exe, h):
+    r = subprocess.run([str(exe)], input=f"{len(h)} " + " ".join(repr(float(x)) for x in h),
+                       capture_output=True, text=True, check=True)
+    return int(r.stdout)
+
+
+def test_fp32_floor_rule_waits_for_the_slow_mode(tmp_path):
+    """The FP32 floor stop: a residual that decays geometrically (factor lam
+    per check) onto a noise floor of 1e-7 stops once the mode's extrapolated
+    remaining change, h lam / (1 - lam) at the floor times lam per further
+    check, is <= 2e-6; not as soon as the floor is reached.  A run whose
+    residual stays above 1e-6, or keeps decaying, never stops by this rule."""
+    exe = _floor_rule_driver(tmp_path)
+    rng = np.random.default_rng(3)
+    for lam, n in ((0.97, 900), (0.999, 17000)):
+        k = np.arange(n)
+        mode = 1e-2 * lam ** k
+        h = mode + 1e-7 * (1.0 + 0.3 * rng.random(n))
+        fired = _fires(exe, h)
+        assert fired > 0, lam
+        # the remaining change of the mode where the rule fired
+        rest = mode[fired - 1] * lam / (1.0 - lam)
+        assert rest <= 2e-6 * 1.5, (lam, fired, rest)
+        # the old rule (floor and four checks without a new minimum) fired
+        # with the mode still ~1e-7 lam / (1 - lam) from settled
+        onset = int(np.argmax(h <= 2 * h.min()))
+        assert fired - onset > 5, (lam, fired, onset)
+    # fast decay onto the floor: no slow mode to wait for
+    h = 1e-3 * 0.5 ** np.arange(60) + 1e-7 * (1.0 + 0.3 * rng.random(60))
+    fired = _fires(exe, h)
+    assert 0 < fired <= int(np.argmax(h <= 2 * h.min())) + 8
+    # above 1e-6: never; a clean decay that keeps setting minima: never
+    assert _fires(exe, 2e-6 * (1.0 + 0.3 * rng.random(200))) == 0
+    assert _fires(exe, 1e-3 * 0.9 ** np.arange(300)) == 0
