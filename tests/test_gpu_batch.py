@@ -149,3 +149,72 @@ def test_batch_errors(lf, ctx):
     with pytest.raises(lf.LFError) as e:
         b.run_to_steady(check_every=999)
     assert e.value.status == lf.LF_EINVAL
+
+
+def first_of_each_class(sweep):
+    """Draw index of the first cavity of every (ny, aspect) class."""
+    seen = {}
+    for k, c in enumerate(sweep):
+        seen.setdefault((c["ny"], c["aspect"]), k)
+    return sorted(seen.values())
+
+
+def test_sweep_classes_against_the_oracle(lf, ctx):
+    """The first cavity of each of the 28 (ny, aspect) classes of the
+    256-cavity sweep (ny 64 .. 512, aspect 1 .. 4, the largest 2048 x 512
+    among them; 5.4 M nodes), stepped together as one FP32 batch for 1000
+    steps from their seeded T0, each against the FP64 oracle element by
+    element: u, v, T and the Nusselt numbers within 1e-4."""
+    sweep = cavity_sweep(256)
+    picks = first_of_each_class(sweep)
+    assert len(picks) == 28 and 35 in picks  # draw 35 is the 2048 x 512 cavity
+    cases = [sweep[k] for k in picks]
+    T0 = [perturbation(c["nx"], c["ny"], c["seed"]) for c in cases]
+    b = lf.Batch(ctx, cases, "f32").init(T0)
+    b.step(1000)
+    oracle.set_threads(16)
+    for k, c in enumerate(cases):
+        print(f"sweep class ny {c['ny']} aspect {c['aspect']} (draw {picks[k]})", flush=True)
+        o = oracle.Case(c["nx"], c["ny"]).set_physics(c["Ra"], c["Pr"]).set_cavity_walls()
+        o.init(T0[k]).step(1000)
+        assert abs(b.params(k)["nu"] - o.params["nu"]) < 1e-15
+        for f in ("u", "v", "T"):
+            e = rel_linf(b.fetch(k, f), o.fetch(f))
+            assert e <= 1e-4, (picks[k], f, e)
+        nb, no = b.nusselt(k), o.nusselt()
+        for key in ("nu_hot", "nu_cold"):
+            assert abs(nb[key] - no[key]) <= 1e-4 * abs(no[key]), (picks[k], key)
+    b.close()
+
+
+GOLDEN_SWEEP = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                            "sweep_steady_64.npz")
+
+
+def test_smallest_sweep_cavities_to_steady_state(lf, ctx):
+    """The three ny = 64 classes of the sweep (aspect 1, 2, 3), run together
+    as one FP32 batch to steady state by the library's own stop rule (1e-8,
+    or the FP32 floor once the slowest mode has settled), against the FP64
+    oracle's steady state (residual 1e-8; tests/golden/sweep_steady_64.npz):
+    u, v, T and the Nusselt numbers within 1e-4."""
+    if not os.path.exists(GOLDEN_SWEEP):
+        pytest.skip("golden steady states not generated")
+    gd = np.load(GOLDEN_SWEEP)
+    sweep = cavity_sweep(256)
+    draws = [int(k) for k in gd["draws"]]
+    cases = [sweep[k] for k in draws]
+    b = lf.Batch(ctx, cases, "f32").init([perturbation(c["nx"], c["ny"], c["seed"])
+                                          for c in cases])
+    steps, rules, r = b.run_to_steady(tol=1e-8, check_every=1000, max_steps=5_000_000)
+    for i, k in enumerate(draws):
+        print(f"draw {k}: {steps[i]} steps (oracle {int(gd[f'steps_{k}'])}), rule {rules[i]}",
+              flush=True)
+        assert rules[i] in (lf.STOP_TOL, lf.STOP_FLOOR)
+        for f in ("u", "v", "T"):
+            e = rel_linf(b.fetch(i, f), gd[f"{f}_{k}"].astype(np.float64))
+            assert e <= 1e-4, (k, f, e)
+        nu = b.nusselt(i)
+        ref = gd[f"nu_{k}"]
+        assert abs(nu["nu_hot"] - ref[0]) <= 1e-4 * abs(ref[0]), k
+        assert abs(nu["nu_cold"] - ref[1]) <= 1e-4 * abs(ref[1]), k
+    b.close()

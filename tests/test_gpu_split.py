@@ -139,6 +139,48 @@ def test_split_full_size_first_steps(lf, ctx):
 
 
 @pytest.mark.parametrize("iface", [0, 1])
+def test_split_256_over_5000_steps(lf, ctx, iface):
+    """256 x 256 split cavity, Ra 1e6, Pr 0.71, seeded T0 (uniform +-1e-6),
+    5000 steps with each closure (non-equilibrium extrapolation, finite-
+    difference gradients): the interface of Eq 91-95 exchanging every step
+    while the boundary layers form.  FP64 within 1e-10 and FP32 within 1e-4
+    of the oracle, element by element on u, v, T and rho, and the Nusselt
+    numbers."""
+    oracle.set_threads(16)
+    n = 256
+    T0 = perturbation(n, n, 1908083860)
+    o = oracle.DDCase(n, n, oracle.SPLIT, iface).set_physics(1e6, 0.71).set_cavity_walls()
+    o.init(T0)
+    o.step(5000)
+    no = o.nusselt()
+    for prec, tol in (("f64", 1e-10), ("f32", 1e-4)):
+        print(f"split 256^2 iface {iface} {prec}: 5000 steps", flush=True)
+        g = lf.Case(ctx, n, n, prec, mode=lf.MODE_SPLIT, iface=iface)
+        g.set_physics(1e6, 0.71).set_cavity_walls().init(T0)
+        assert abs(g.params()["nu"] - o.params["nu"]) < 1e-15
+        g.step(5000)
+        check(g, o, tol)
+        ng = g.nusselt()
+        for k in ("nu_hot", "nu_cold", "nu_hot_max"):
+            assert abs(ng[k] - no[k]) <= tol * abs(no[k]), (prec, k)
+        g.close()
+
+
+@pytest.mark.parametrize("iface", [0, 1])
+def test_split_full_size_200_steps(lf, ctx, iface):
+    """4096 x 4096 split cavity, Ra 1e6, FP32, in the benchmark's launch
+    configuration, 200 steps with each closure: element-wise parity with the
+    oracle on u, v, T within 1e-4 of each field's maximum."""
+    oracle.set_threads(16)
+    n = 4096
+    print(f"split 4096^2 iface {iface}: 200 steps", flush=True)
+    g, o = pair(lf, ctx, n, n, "f32", iface, Ra=1e6, T0=perturbation(n, n, 1908083860))
+    g.step(200)
+    o.step(200)
+    check(g, o, 1e-4, ("u", "v", "T"))
+
+
+@pytest.mark.parametrize("iface", [0, 1])
 def test_split_steady_state_parity(lf, ctx, iface):
     """64 x 64, Ra 1e4, FP64, both closures run to a 1e-9 residual (the
     level of Eq 93 gives the split mode a fixed point): the steady fields
