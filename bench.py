@@ -1,16 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of the coupled LBM-FVM step on one MI355X.
 
-Workload: the 512 x 512 side-heated cavity, Ra 1e6, Pr 0.71, FP32
-distributions and temperature, seeded T0 perturbation (uniform +-1e-6).
-One benchmark step is one coupled time step (pull-stream, moments, QUICK FV
-energy update, collision with buoyancy) plus, as in the run-to-steady loop,
-a residual check every 1000 steps and the wall Nusselt numbers at the end.
+Workload (the headline): the batched sweep of 256 side-heated cavities of
+uneven size, aspect ratio, Ra and Pr (ny from 64 to 512, aspect 1 to 4, so
+up to 2048 x 512; log10 Ra uniform in [3, 6]; Pr 0.71 or 7; splitmix64 seed
+1908083864; 50.7 M nodes), FP32 populations and temperature, every cavity
+live.  One benchmark step is one batched coupled time step of every cavity
+(pull-stream with bounce-back, moments, QUICK FV energy update, collision
+with buoyancy: one launch), plus the batched residual once per 1000 steps as
+in the run-to-steady loop.  The timed region holds only enqueued steps (and
+those residuals); inputs are resident in HBM before it starts.
 
 Prints one JSON line: MLUPS (node updates per second / 1e6) over the timed
-steps, the roofline of the fused step kernel (algorithmic bytes over the
-kernel's mean duration, measured with HIP events on the library's stream),
-and the FP64 CPU oracle timed on this host on a bounded sample.
+steps, the roofline of the batched step kernel (algorithmic bytes over its
+mean duration from HIP events on the library's stream), the FP64 CPU oracle
+timed on this host on a bounded sample of the same cavities, and extra
+points: the 512^2 cavity (cache-resident), the 4096^2 cavity, the split
+mode with either closure, the single methods, grid setting 2, LBM-MCM, the
+lid-driven cavity and the time to steady state from the cold and the
+learned start.
 """
 import argparse
 import hashlib
@@ -25,7 +33,7 @@ sys.path.insert(0, ROOT)
 METRIC = "coupled LBM-FVM MLUPS + %HBM peak; time-to-steady (warm vs cold) at Nu 1e-4"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 BYTES_PER_LU_F32 = 80.0        # 9 f read + 9 f write + T read + T write, 4 B each
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_hybrid_step_traffic.json")
+PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SRC = os.path.join(ROOT, "paper_1908_08386_amd", "csrc", "k_hybrid.hip")
 
 
@@ -34,42 +42,96 @@ def kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(nx, ny):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+def measured_traffic(name, key):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, or
     None when it is missing or was taken on a different kernel source."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(os.path.join(PROFILES, name)) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     if t.get("kernel_sha256_16") != kernel_hash():
         return None
-    return t.get("bytes_per_launch", {}).get(f"{nx}x{ny}")
+    return t.get("bytes_per_launch", {}).get(key)
 
 
-def cpu_baseline(nx, ny, T0, seconds):
+def cpu_baseline(cases, T0s, seconds, steps_each):
+    """The FP64 oracle stepping cavities of the sweep in draw order, each
+    `steps_each` steps, until `seconds` of stepping have been spent; node
+    updates per second of stepping (set-up excluded, as on the GPU)."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     used = oracle.set_threads(threads)
-    o = oracle.Case(nx, ny).set_physics(1e6, 0.71).set_cavity_walls().init(T0)
-    o.step(5)
-    t0 = time.perf_counter()
-    steps = 0
-    while time.perf_counter() - t0 < seconds:
-        o.step(10)
-        steps += 10
-    dt = time.perf_counter() - t0
-    return {"value": round(nx * ny * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": used,
+    lu, spent, k = 0, 0.0, 0
+    while k < len(cases) and spent < seconds:
+        c = cases[k]
+        o = oracle.Case(c["nx"], c["ny"]).set_physics(c["Ra"], c["Pr"]).set_cavity_walls()
+        o.init(T0s[k])
+        t0 = time.perf_counter()
+        o.step(steps_each)
+        spent += time.perf_counter() - t0
+        lu += c["nx"] * c["ny"] * steps_each
+        k += 1
+    return {"value": round(lu / spent / 1e6, 3), "unit": "MLUPS", "cores": used,
             "kind": "oracle",
-            "sample": f"{nx}x{ny} Ra 1e6 cavity, FP64 oracle (3 plain sweeps/step, OpenMP), "
-                      f"{steps} steps in {dt:.1f} s"}
+            "sample": f"cavities 0..{k - 1} of the {len(cases)}-cavity sweep (draw order), "
+                      f"{steps_each} steps each, FP64 oracle (3 plain sweeps per step, OpenMP): "
+                      f"{lu / 1e6:.1f} M node updates in {spent:.1f} s"}
+
+
+def oracle_timing():
+    """The FP64 oracle on this host's cores, one thread and all threads, on
+    the workloads the library is measured on (context for the GPU figures):
+    the 64^2 cavity's 10 000 steps, the 512^2 cavity's first 20 000 steps,
+    the 4096^2 split cavity's first steps (200 on all threads, 5 on one),
+    and every cavity of the 256-cavity sweep for 20 steps."""
+    import oracle
+    from synth_inputs import SEED_C2, cavity_sweep, perturbation
+    allc = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    out = {"host_threads": allc}
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        fn()
+        return time.perf_counter() - t0
+
+    for th in (1, allc):
+        used = oracle.set_threads(th)
+        o = oracle.Case(64, 64).set_physics(1e4, 0.71).set_cavity_walls().init()
+        dt = timed(lambda: o.step(10000))
+        out[f"cavity64_10000_steps_{used}t"] = {"seconds": round(dt, 3),
+                                                "mlups": round(64 * 64 * 1e4 / dt / 1e6, 2)}
+        n, k = 512, (20000 if th == allc else 2000)
+        o = oracle.Case(n, n).set_physics(1e6, 0.71).set_cavity_walls()
+        o.init(perturbation(n, n, SEED_C2))
+        dt = timed(lambda: o.step(k))
+        out[f"cavity512_{k}_steps_{used}t"] = {"seconds": round(dt, 3),
+                                               "mlups": round(n * n * k / dt / 1e6, 2)}
+        n, k = 4096, (200 if th == allc else 5)
+        d = oracle.DDCase(n, n, oracle.SPLIT, oracle.IFACE_NEQ).set_physics(1e6, 0.71)
+        d.set_cavity_walls().init(perturbation(n, n, SEED_C2))
+        dt = timed(lambda: d.step(k))
+        out[f"split4096_{k}_steps_{used}t"] = {"seconds": round(dt, 3),
+                                               "mlups": round(n * n * k / dt / 1e6, 2)}
+        del d
+        sweep = cavity_sweep(256)
+        cs = sweep if th == allc else sweep[:16]
+        lu, spent = 0, 0.0
+        for c in cs:
+            o = oracle.Case(c["nx"], c["ny"]).set_physics(c["Ra"], c["Pr"]).set_cavity_walls()
+            o.init(perturbation(c["nx"], c["ny"], c["seed"]))
+            spent += timed(lambda: o.step(20))
+            lu += c["nx"] * c["ny"] * 20
+        out[f"sweep_{len(cs)}_cavities_20_steps_{used}t"] = {"seconds": round(spent, 3),
+                                                             "mlups": round(lu / spent / 1e6, 2)}
+    return out
 
 
 def time_to_steady(lf, ctx, n, T0, heldout):
     """Cold start against the learned initial guess, same stop rule (residual
-    1e-8 per 1000 steps or the FP32 floor rule): the n x n cavity of the main
-    workload, then a batch of held-out cavities of the sweep distribution.
-    Warm times include the network's prediction and the resampling."""
+    1e-8 per 1000 steps or the FP32 floor rule): the n x n cavity, then a
+    batch of held-out cavities of the sweep distribution.  Warm times include
+    the network's prediction and the resampling."""
     import numpy as np
     import torch
 
@@ -87,6 +149,7 @@ def time_to_steady(lf, ctx, n, T0, heldout):
                      "seconds_warm": round(r["seconds_warm"], 3),
                      "speedup": round(r["seconds_cold"] / r["seconds_warm"], 3),
                      "steps_cold": int(r["steps_cold"][0]), "steps_warm": int(r["steps_warm"][0]),
+                     "us_per_step_cold": round(r["seconds_cold"] / r["steps_cold"][0] * 1e6, 3),
                      "rule_cold": int(r["rules_cold"][0]), "rule_warm": int(r["rules_warm"][0]),
                      "nu_cold": float(r["nu_cold"][0]), "nu_warm": float(r["nu_warm"][0]),
                      "dnu_rel": float(abs(r["nu_warm"][0] - r["nu_cold"][0]) / abs(r["nu_cold"][0]))}
@@ -113,20 +176,25 @@ def time_to_steady(lf, ctx, n, T0, heldout):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=2000)
-    ap.add_argument("--n", type=int, default=512, help="cavity size (n x n)")
-    ap.add_argument("--profile-steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=256,
+                    help="cavities of the sweep in the headline workload")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="only time the FP64 oracle on this host (one thread and all threads)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time the headline workload only (for profiler runs)")
     ap.add_argument("--traffic-probe", action="store_true",
-                    help="only run a few steps at 512^2 and 4096^2 and a 1 GiB device copy "
-                         "(the calibration kernel), for rocprofv3 counter collection")
+                    help="only a 1 GiB device copy (the calibration kernel) and a few steps of "
+                         "the sweep, the 512^2 and the 4096^2 cavity, for rocprofv3 counters")
+    ap.add_argument("--n", type=int, default=512, help="the single cavity point (n x n)")
     ap.add_argument("--split-point", type=int, default=4096,
-                    help="also time the domain-decomposed mode on an n x n cavity (0 = skip)")
+                    help="also time the divided modes and the single methods on an n x n "
+                         "cavity (0 = skip)")
     ap.add_argument("--hbm-point", type=int, default=4096,
-                    help="also time the kernel on an n x n cavity whose working set is far "
-                         "larger than the on-die caches (0 = skip)")
+                    help="also time Mode H on an n x n cavity (0 = skip)")
     ap.add_argument("--lid-point", type=int, default=160,
                     help="also run the lid-driven split cavity (n x n, Re 100) to steady state "
                          "(0 = skip)")
@@ -134,9 +202,6 @@ def main():
                     help="also time cold and learned (warm) starts to steady state (0 = skip)")
     ap.add_argument("--heldout", type=int, default=16,
                     help="held-out cavities (ny <= 128) in the batched warm/cold comparison")
-    ap.add_argument("--batch-point", type=int, default=256,
-                    help="also time one launch per step over this many heterogeneous cavities "
-                         "of the sweep distribution (0 = skip)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -144,11 +209,20 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.oracle_timing:
+        print(json.dumps({"oracle_timing": oracle_timing()}), flush=True)
+        return
+
     import numpy as np
     import torch
 
     import paper_1908_08386_amd as lf
-    from synth_inputs import SEED_C2, perturbation
+    from synth_inputs import SEED_BATCH, SEED_C2, cavity_sweep, perturbation
+
+    cases = cavity_sweep(args.batch)
+    nodes = sum(c["nx"] * c["ny"] for c in cases)
+    T0s = [perturbation(c["nx"], c["ny"], c["seed"]) for c in cases]
+    ctx = lf.Context(0)
 
     if args.traffic_probe:
         # calibration: a plain device copy of exactly 1 GiB (read 1 GiB, write 1 GiB)
@@ -158,28 +232,31 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-        ctx = lf.Context(0)
+        bt = lf.Batch(ctx, cases, "f32")
+        bt.init(T0s)
+        bt.step(10)
+        torch.cuda.synchronize()
+        bt.close()
         for m, k in ((512, 10), (4096, 5)):
             c = lf.Case(ctx, m, m, "f32").set_physics(1e6, 0.71).set_cavity_walls()
             c.init(perturbation(m, m, SEED_C2)).step(k)
             torch.cuda.synchronize()
-            del c
+            c.close()
         print(json.dumps({"traffic_probe": "done"}), flush=True)
         return
 
-    n = args.n
-    T0 = perturbation(n, n, SEED_C2)
-    ctx = lf.Context(0)
-    c = lf.Case(ctx, n, n, "f32").set_physics(1e6, 0.71).set_cavity_walls().init(T0)
+    # ---- headline: the batched sweep, every cavity live ----------------------
+    bt = lf.Batch(ctx, cases, "f32")
+    bt.init(T0s)
 
     def run(k):
         done = 0
         while done < k:
             m = min(1000, k - done)
-            c.step(m)
+            bt.step(m)
             done += m
             if m == 1000:
-                c.residual()
+                bt.residual()
 
     run(args.warmup)
     stream = ctx.stream  # the stream the library launches on
@@ -189,18 +266,14 @@ def main():
     ev0.record(stream)
     run(args.steps)
     ev1.record(stream)
-    nu = c.nusselt()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    mlups = n * n * args.steps / dt / 1e6
+    mlups = nodes * args.steps / dt / 1e6
     # mean step-kernel duration over the timed region (HIP events on the
-    # library's stream; the region also holds one residual per 1000 steps)
+    # library's stream; the region holds the residuals of every 1000 steps)
     avg_ms = ev0.elapsed_time(ev1) / args.steps
-    _, min_ms, max_ms = c.profile_steps(args.profile_steps)
-    bytes_launch = BYTES_PER_LU_F32 * n * n
+    bytes_launch = BYTES_PER_LU_F32 * nodes
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(n, n)
-
     out = {
         "metric": METRIC,
         "value": round(mlups, 2),
@@ -213,19 +286,43 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": f"synthetic: T0 = 1e-6 (2U - 1), U from splitmix64 seed {SEED_C2}, u0 = 0",
-        "config": {"workload": f"{n}x{n} side-heated cavity, Ra 1e6, Pr 0.71, FP32, "
-                               "coupled D2Q9 BGK + QUICK FV energy (Mode H)",
-                   "nx": n, "ny": n, "Ra": 1e6, "Pr": 0.71, "U_char": c.params()["U_char"],
-                   "residual_every": 1000, "nu_hot_end": round(nu["nu_hot"], 6)},
+        "data": f"synthetic: {len(cases)} cavities drawn from splitmix64 seed {SEED_BATCH}; "
+                "T0 = 1e-6 (2U - 1) per cavity (own seed), u0 = 0",
+        "config": {"workload": f"batched sweep of {len(cases)} side-heated cavities, every one "
+                               "live: ny in {64, 96, 128, 192, 256, 384, 512}, aspect 1..4 "
+                               "(up to 2048 x 512), log10 Ra in [3, 6], Pr 0.71 or 7, FP32, "
+                               "coupled D2Q9 BGK + QUICK FV energy (Mode H), one launch per "
+                               "step",
+                   "cavities": len(cases), "nodes": nodes, "largest": [2048, 512],
+                   "residual_every": 1000},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "k_hybrid_step<float>",
-                     "kernel_ms_avg": round(avg_ms, 6), "kernel_ms_min": round(min_ms, 6),
-                     "bytes_per_launch": bytes_launch,
-                     "note": "512^2 FP32 working set (21 MB) is resident in the 256 MB "
-                             "Infinity Cache; see roofline_hbm for an HBM-bound size"},
+                     "traffic": measured_traffic("k_batch_step_traffic.json", "sweep256"),
+                     "kernel": "k_batch_step<float>",
+                     "kernel_ms_avg": round(avg_ms, 6), "bytes_per_launch": bytes_launch},
     }
+    bt.close()
+    del bt
+
+    if args.headline_only:
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline(cases, T0s, args.cpu_seconds, 50)
+        print(json.dumps(out), flush=True)
+        return
+
+    # ---- the 512^2 cavity: cache-resident, so no HBM claim -------------------
+    n = args.n
+    T0 = perturbation(n, n, SEED_C2)
+    c = lf.Case(ctx, n, n, "f32").set_physics(1e6, 0.71).set_cavity_walls().init(T0)
+    c.step(200)
+    a_ms, lo_ms, hi_ms = c.profile_steps(4000)
+    out["cavity_point"] = {"workload": f"{n}x{n} side-heated cavity, Ra 1e6, Pr 0.71, FP32, Mode H "
+                                       "(21 MB: resident in the 256 MB Infinity Cache, latency-"
+                                       "bound; not an HBM figure)",
+                           "kernel_ms_avg": round(a_ms, 6), "kernel_ms_min": round(lo_ms, 6),
+                           "mlups": round(n * n / (a_ms * 1e-3) / 1e6, 1),
+                           "U_char": c.params()["U_char"]}
+    c.close()
     del c
 
     if args.hbm_point:
@@ -239,38 +336,47 @@ def main():
         out["roofline_hbm"] = {"bound": "hbm", "workload": f"{m}x{m} cavity FP32 Mode H",
                                "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": round(ach / HBM_PEAK_GBS, 4),
-                               "traffic": measured_traffic(m, m),
+                               "traffic": measured_traffic("k_hybrid_step_traffic.json",
+                                                           f"{m}x{m}"),
                                "kernel_ms_avg": round(a_ms, 5), "bytes_per_launch": b,
                                "mlups": round(m * m / (a_ms * 1e-3) / 1e6, 1)}
+        big.close()
         del big
 
     if args.split_point:
         m = args.split_point
-        sp = lf.Case(ctx, m, m, "f32", mode=lf.MODE_SPLIT).set_physics(1e6, 0.71)
-        sp.set_cavity_walls().init(perturbation(m, m, SEED_C2))
-        sp.step(10)
-        a_ms, _, _ = sp.profile_steps(200)
-        # algorithmic bytes: LBM half 112 B/node (9 f + 5 g, read + write),
-        # FV half 32 B/cell (u, v, p, T read + write): 72 B per node on average
-        b = 72.0 * m * m
-        ach = b / (a_ms * 1e-3) / 1e9
-        out["split_point"] = {"workload": f"{m}x{m} split cavity (LBM west half, FV east half), "
-                                          "Ra 1e6, Pr 0.71, FP32, NEE interface",
-                              "ms_per_step": round(a_ms, 5),
-                              "mlups": round(m * m / (a_ms * 1e-3) / 1e6, 1),
-                              "achieved_GBs_at_72B": round(ach, 1),
-                              "frac_of_8TBs": round(ach / HBM_PEAK_GBS, 4),
-                              "U_char": sp.params()["U_char"]}
-        del sp
+        # the split cavity with either closure (config: LBM west half, FV east
+        # half); algorithmic bytes: LBM half 112 B/node (9 f + 5 g, read +
+        # write), FV half 32 B/cell (u, v, p, T read + write): 72 B on average
+        for key, iface, name in (("split_point", lf.IFACE_NEQ_EXTRAP, "non-equilibrium "
+                                  "extrapolation"),
+                                 ("split_fd_point", lf.IFACE_FD_GRADIENT, "finite-difference "
+                                  "velocity gradients")):
+            sp = lf.Case(ctx, m, m, "f32", mode=lf.MODE_SPLIT, iface=iface).set_physics(1e6, 0.71)
+            sp.set_cavity_walls().init(perturbation(m, m, SEED_C2))
+            sp.step(10)
+            a_ms, _, _ = sp.profile_steps(200)
+            ach = 72.0 * m * m / (a_ms * 1e-3) / 1e9
+            out[key] = {"workload": f"{m}x{m} split cavity (LBM west half, FV east half), "
+                                    f"Ra 1e6, Pr 0.71, FP32, interface by {name}",
+                        "ms_per_step": round(a_ms, 5),
+                        "mlups": round(m * m / (a_ms * 1e-3) / 1e6, 1),
+                        "achieved_GBs_at_72B": round(ach, 1),
+                        "frac_of_8TBs": round(ach / HBM_PEAK_GBS, 4),
+                        "U_char": sp.params()["U_char"]}
+            sp.close()
+            del sp
         # the horizontal division of the same cavity (Fig. 17b)
         sh = lf.Case(ctx, m, m, "f32", mode=lf.MODE_SPLIT_H).set_physics(1e6, 0.71)
         sh.set_cavity_walls().init(perturbation(m, m, SEED_C2))
         sh.step(10)
         a_ms, _, _ = sh.profile_steps(200)
         out["split_h_point"] = {"workload": f"{m}x{m} cavity divided horizontally (LBM lower half, "
-                                            "FV upper half), Ra 1e6, Pr 0.71, FP32, NEE interface",
+                                            "FV upper half), Ra 1e6, Pr 0.71, FP32, non-equilibrium "
+                                            "extrapolation",
                                 "ms_per_step": round(a_ms, 5),
                                 "mlups": round(m * m / (a_ms * 1e-3) / 1e6, 1)}
+        sh.close()
         del sh
         # the single methods of the same comparison on the whole cavity
         # (algorithmic bytes: FV 32 B/cell, LBM 112 B/node)
@@ -287,13 +393,11 @@ def main():
                         "mlups": round(m * m / (a_ms * 1e-3) / 1e6, 1),
                         f"achieved_GBs_at_{int(bpn)}B": round(ach, 1),
                         "frac_of_8TBs": round(ach / HBM_PEAK_GBS, 4)}
+            pc.close()
             del pc
-
-    if args.split_point:
         # Mode H on grid setting 2: lattice on all nodes, temperature on 2 x 2
         # control volumes, one implicit energy step per 2NX = m lattice steps
         # (timed over whole cycles, so the energy step is included)
-        m = args.split_point
         g2 = lf.Case(ctx, m, m, "f32", mode=lf.MODE_HYBRID_GS2).set_physics(1e6, 0.71)
         g2.set_cavity_walls().init(perturbation(m, m, SEED_C2))
         g2.step(m)
@@ -306,22 +410,23 @@ def main():
                             "mlups": round(m * m / (a_ms * 1e-3) / 1e6, 1),
                             "achieved_GBs_at_76B": round(ach, 1),
                             "frac_of_8TBs": round(ach / HBM_PEAK_GBS, 4)}
+        g2.close()
         del g2
-
-    if args.split_point:
         # LBM-MCM (Sec. 6): 128^2, one Monte Carlo solve of 1024 walkers per
         # node after every 100 lattice steps, timed over whole cycles
-        m, S, N = 128, 100, 1024
-        mc = lf.Case(ctx, m, m, "f32", mode=lf.MODE_LBM_MCM).set_physics(1e4, 0.71)
-        mc.set_cavity_walls().set_mcm(S, N).init(perturbation(m, m, SEED_C2))
+        mm, S, N = 128, 100, 1024
+        mc = lf.Case(ctx, mm, mm, "f32", mode=lf.MODE_LBM_MCM).set_physics(1e4, 0.71)
+        mc.set_cavity_walls().set_mcm(S, N).init(perturbation(mm, mm, SEED_C2))
         mc.step(S)
         a_ms, _, _ = mc.profile_steps(S)
-        out["mcm_point"] = {"workload": f"{m}x{m} cavity, LBM-MCM, Ra 1e4, Pr 0.71, FP32 lattice, "
-                                        f"{N} walkers per node, one solve per {S} lattice steps",
+        out["mcm_point"] = {"workload": f"{mm}x{mm} cavity, LBM-MCM, Ra 1e4, Pr 0.71, FP32 "
+                                        f"lattice, {N} walkers per node, one solve per {S} "
+                                        "lattice steps",
                             "ms_per_cycle": round(a_ms * S, 3),
                             "ms_per_step": round(a_ms, 5),
-                            "mlups": round(m * m / (a_ms * 1e-3) / 1e6, 1),
+                            "mlups": round(mm * mm / (a_ms * 1e-3) / 1e6, 1),
                             "capped_walkers": mc.mcm_capped()}
+        mc.close()
         del mc
 
     if args.lid_point:
@@ -352,32 +457,14 @@ def main():
                             "ms_per_step": round(wall * 1e3 / max(st, 1), 5),
                             "vortex_centre": [round(float(cx), 5), round(float(cy), 5)],
                             "ref35_centre": [0.6172, 0.7344]}
+        ld.close()
         del ld
-
-    if args.batch_point:
-        from synth_inputs import cavity_sweep
-        cases = cavity_sweep(args.batch_point)
-        nodes = sum(cc["nx"] * cc["ny"] for cc in cases)
-        bt = lf.Batch(ctx, cases, "f32")
-        bt.init([perturbation(cc["nx"], cc["ny"], cc["seed"]) for cc in cases])
-        bt.step(10)
-        a_ms = bt.profile_steps(100)
-        b = BYTES_PER_LU_F32 * nodes
-        ach = b / (a_ms * 1e-3) / 1e9
-        out["batch_point"] = {"workload": f"{len(cases)} heterogeneous side-heated cavities "
-                                          "(ny 64..512, A 1..4, Ra 1e3..1e6, Pr 0.71/7), FP32, "
-                                          "all active, one launch per step",
-                              "nodes": nodes, "ms_per_step": round(a_ms, 5),
-                              "mlups": round(nodes / (a_ms * 1e-3) / 1e6, 1),
-                              "achieved_GBs_at_80B": round(ach, 1),
-                              "frac_of_8TBs": round(ach / HBM_PEAK_GBS, 4)}
-        del bt
 
     if args.time_to_steady:
         out["time_to_steady"] = time_to_steady(lf, ctx, n, T0, args.heldout)
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(n, n, T0, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(cases, T0s, args.cpu_seconds, 50)
     print(json.dumps(out), flush=True)
 
 

@@ -271,7 +271,10 @@ class Context:
             self._h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: module globals may be gone
+            pass
 
 
 class Case:
@@ -303,7 +306,10 @@ class Case:
         _release(self, _lib.lf_case_destroy if _lib is not None else None)
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: module globals may be gone
+            pass
 
     # ---- set-up ------------------------------------------------------------
     def set_physics(self, Ra, Pr, U_char=0.0, T_ref=float("nan"), conv=CONV_QUICK,
@@ -495,7 +501,10 @@ class Batch:
         _release(self, _lib.lf_batch_destroy if _lib is not None else None)
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: module globals may be gone
+            pass
 
     def set_band(self, rows: int, idx: int = -1):
         _check(_lib.lf_batch_set_band(self._h, int(idx), int(rows)), "lf_batch_set_band")
@@ -661,7 +670,10 @@ class Net:
         _release(self, _lib.lf_net_destroy if _lib is not None else None)
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: module globals may be gone
+            pass
 
     def layer_shapes(self):
         """(Cout, Cin) of the ten convolutions, in the flat parameter order."""
