@@ -97,7 +97,11 @@ enum { LF_CONV_QUICK = 0, LF_CONV_CENTRAL = 1, LF_CONV_UPWIND = 2 };
 enum { LF_WALL_NOSLIP = 0, LF_WALL_PERIODIC = 1 };
 enum { LF_T_DIRICHLET = 0, LF_T_ADIABATIC = 1, LF_T_PERIODIC = 2 };
 enum { LF_SIDE_W = 0, LF_SIDE_E = 1, LF_SIDE_S = 2, LF_SIDE_N = 3 };
-enum { LF_FIELD_U = 0, LF_FIELD_V = 1, LF_FIELD_T = 2, LF_FIELD_RHO = 3 };
+/* fields of *_fetch: LF_FIELD_P is the kinematic pressure c_s^2 (rho - 1):
+ * the FV zone's p in the split modes, the lattice's in the LBM zone and Mode
+ * H (from the density of the last step; in FP32 its absolute rounding is
+ * that of rho near 1, ~4e-8)                                             */
+enum { LF_FIELD_U = 0, LF_FIELD_V = 1, LF_FIELD_T = 2, LF_FIELD_RHO = 3, LF_FIELD_P = 4 };
 /* run_to_steady stop rules (r_final[3] of lf_case_run_to_steady)          */
 enum { LF_STOP_TOL = 1, LF_STOP_FLOOR = 2 };
 

@@ -45,9 +45,9 @@ CONV_QUICK, CONV_CENTRAL, CONV_UPWIND = 0, 1, 2
 WALL_NOSLIP, WALL_PERIODIC = 0, 1
 T_DIRICHLET, T_ADIABATIC, T_PERIODIC = 0, 1, 2
 W, E, S, N = 0, 1, 2, 3
-FIELD_U, FIELD_V, FIELD_T, FIELD_RHO = 0, 1, 2, 3
+FIELD_U, FIELD_V, FIELD_T, FIELD_RHO, FIELD_P = 0, 1, 2, 3, 4
 STOP_TOL, STOP_FLOOR = 1, 2
-_FIELDS = {"u": FIELD_U, "v": FIELD_V, "T": FIELD_T, "rho": FIELD_RHO}
+_FIELDS = {"u": FIELD_U, "v": FIELD_V, "T": FIELD_T, "rho": FIELD_RHO, "p": FIELD_P}
 _STATUS = {0: "LF_OK", 1: "LF_EINVAL", 2: "LF_ENOMEM", 3: "LF_EWORKSPACE", 4: "LF_EDEVICE",
            5: "LF_EUNSTABLE", 6: "LF_EDIVERGED", 7: "LF_ENOTCONV", 8: "LF_ESTATE",
            9: "LF_ENOTIMPL"}

@@ -163,13 +163,15 @@ __global__ __launch_bounds__(kThreads) void k_mass_partial(int nx, int ny, int p
 template <typename real>
 __global__ __launch_bounds__(kThreads) void k_unpack(int nx, int ny, int pitch,
                                                      const real* __restrict__ src, void* dst,
-                                                     int as_f64) {
+                                                     int as_f64, int pressure) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= nx) return;
   const real v = src[j * pitch + i];
-  if (as_f64) static_cast<double*>(dst)[j * nx + i] = (double)v;
-  else static_cast<real*>(dst)[j * nx + i] = v;
+  // pressure: kinematic p = c_s^2 (rho - 1) from the density plane
+  const double d = pressure ? ((double)v - 1.0) / 3.0 : (double)v;
+  if (as_f64) static_cast<double*>(dst)[j * nx + i] = d;
+  else static_cast<real*>(dst)[j * nx + i] = pressure ? (real)d : v;
 }
 
 }  // namespace
@@ -202,10 +204,10 @@ hipError_t launch_mass(const Grid& g, const real* f, const real* T, double* part
 
 template <typename real>
 hipError_t launch_unpack(const Grid& g, const real* plane, void* dst, int as_f64,
-                         hipStream_t s) {
+                         hipStream_t s, int pressure) {
   dim3 grid((g.nx + kThreads - 1) / kThreads, g.ny);
   hipLaunchKernelGGL(k_unpack<real>, grid, dim3(kThreads), 0, s, g.nx, g.ny, g.pitch, plane,
-                     dst, as_f64);
+                     dst, as_f64, pressure);
   return hipGetLastError();
 }
 
@@ -216,7 +218,7 @@ hipError_t launch_unpack(const Grid& g, const real* plane, void* dst, int as_f64
                                            double*, hipStream_t);                          \
   template hipError_t launch_mass<real>(const Grid&, const real*, const real*, double*,    \
                                         int, double*, hipStream_t);                        \
-  template hipError_t launch_unpack<real>(const Grid&, const real*, void*, int, hipStream_t);
+  template hipError_t launch_unpack<real>(const Grid&, const real*, void*, int, hipStream_t, int);
 LF_INST(float)
 LF_INST(double)
 #undef LF_INST

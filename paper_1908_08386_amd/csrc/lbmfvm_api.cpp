@@ -876,12 +876,13 @@ lf_status lf_case_fetch(lf_case* c, int field, void* dst, size_t dst_bytes, int 
   const size_t pb = align_up((size_t)c->g.plane * c->es, 256);
   size_t off;
   switch (field) {
-    case LF_FIELD_RHO: off = c->off_mom; break;
+    case LF_FIELD_RHO: case LF_FIELD_P: off = c->off_mom; break;
     case LF_FIELD_U: off = c->off_mom + pb; break;
     case LF_FIELD_V: off = c->off_mom + 2 * pb; break;
     case LF_FIELD_T: off = c->off_T[c->cur]; break;
     default: return fail(LF_EINVAL, "bad field %d", field);
   }
+  const int pressure = field == LF_FIELD_P ? 1 : 0;
   hipStream_t s = c->ctx->stream;
   void* target = dst_is_device ? dst : (void*)(c->ws + c->off_stage);
   lf::Grid g = c->g;
@@ -889,13 +890,14 @@ lf_status lf_case_fetch(lf_case* c, int field, void* dst, size_t dst_bytes, int 
     g = dense_grid(c);
     lf_status st = c->desc.precision == LF_F32 ? split_dense<float>(c) : split_dense<double>(c);
     if (st != LF_OK) return st;
-    const int plane_of[4] = {1, 2, 3, 0};  // U, V, T, RHO -> dense planes rho, u, v, T
+    // U, V, T, RHO, P -> dense planes rho, u, v, T (P from rho)
+    const int plane_of[5] = {1, 2, 3, 0, 0};
     off = c->off_dense + (size_t)plane_of[field] * (size_t)g.plane * c->es;
   }
   if (c->desc.precision == LF_F32)
-    HIP_TRY(lf::launch_unpack<float>(g, fptr<float>(c, off), target, as_f64, s));
+    HIP_TRY(lf::launch_unpack<float>(g, fptr<float>(c, off), target, as_f64, s, pressure));
   else
-    HIP_TRY(lf::launch_unpack<double>(g, fptr<double>(c, off), target, as_f64, s));
+    HIP_TRY(lf::launch_unpack<double>(g, fptr<double>(c, off), target, as_f64, s, pressure));
   if (!dst_is_device) {
     HIP_TRY(hipMemcpyAsync(dst, target, need, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));

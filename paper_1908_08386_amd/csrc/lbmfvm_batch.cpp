@@ -633,7 +633,7 @@ lf_status lf_batch_fetch(lf_batch* b, int idx, int field, void* dst, size_t dst_
   const size_t pb = lf_align_up((size_t)c.plane * b->es, 256);
   size_t off;
   switch (field) {
-    case LF_FIELD_RHO: off = c.off_mom; break;
+    case LF_FIELD_RHO: case LF_FIELD_P: off = c.off_mom; break;
     case LF_FIELD_U: off = c.off_mom + pb; break;
     case LF_FIELD_V: off = c.off_mom + 2 * pb; break;
     case LF_FIELD_T: off = c.off_T[c.cur]; break;
@@ -646,10 +646,11 @@ lf_status lf_batch_fetch(lf_batch* b, int idx, int field, void* dst, size_t dst_
   g.plane = c.plane;
   hipStream_t s = b->ctx->stream;
   void* target = dst_is_device ? dst : (void*)(b->ws + b->off_stage);
+  const int pressure = field == LF_FIELD_P ? 1 : 0;
   if (b->precision == LF_F32)
-    LF_HIP_TRY(lf::launch_unpack<float>(g, (float*)(b->ws + off), target, as_f64, s));
+    LF_HIP_TRY(lf::launch_unpack<float>(g, (float*)(b->ws + off), target, as_f64, s, pressure));
   else
-    LF_HIP_TRY(lf::launch_unpack<double>(g, (double*)(b->ws + off), target, as_f64, s));
+    LF_HIP_TRY(lf::launch_unpack<double>(g, (double*)(b->ws + off), target, as_f64, s, pressure));
   if (!dst_is_device) {
     LF_HIP_TRY(hipMemcpyAsync(dst, target, need, hipMemcpyDeviceToHost, s));
     LF_HIP_TRY(hipStreamSynchronize(s));

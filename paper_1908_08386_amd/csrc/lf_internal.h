@@ -116,7 +116,7 @@ hipError_t launch_mass(const Grid& g, const real* f, const real* T,
 // Dense copy of one plane into dst ([ny][nx]) as double or as real.
 template <typename real>
 hipError_t launch_unpack(const Grid& g, const real* plane, void* dst,
-                         int as_f64, hipStream_t s);
+                         int as_f64, hipStream_t s, int pressure = 0);
 
 }  // namespace lf
 

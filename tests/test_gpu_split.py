@@ -360,3 +360,25 @@ def test_horizontal_division_ragged_fp64(lf, ctx):
     with pytest.raises(lf.LFError) as e:
         lf.Case(ctx, 64, 65, mode=lf.MODE_SPLIT_H)  # odd divided extent
     assert e.value.status == lf.LF_EINVAL
+
+
+@pytest.mark.parametrize("mode", ["split", "pure_fv"])
+def test_pressure_fetch(lf, ctx, mode):
+    """LF_FIELD_P: the kinematic pressure c_s^2 (rho - 1), which in the FV
+    zone is its own p (the oracle's raw FV pressure) and in the LBM zone the
+    lattice pressure; FP64, 64 x 48, 600 steps."""
+    oracle.set_threads(8)
+    nx, ny = 64, 48
+    T0 = perturbation(nx, ny, 33, amp=0.1)
+    gm, om = (lf.MODE_SPLIT, oracle.SPLIT) if mode == "split" else (lf.MODE_PURE_FV, oracle.PURE_FV)
+    g = lf.Case(ctx, nx, ny, "f64", mode=gm).set_physics(1e5, 0.71).set_cavity_walls().init(T0)
+    o = oracle.DDCase(nx, ny, om).set_physics(1e5, 0.71).set_cavity_walls().init(T0)
+    g.step(600)
+    o.step(600)
+    p = g.fetch("p")
+    ref = (o.fetch("rho") - 1.0) / 3.0
+    assert np.abs(p - ref).max() <= 1e-10 * np.abs(ref).max()
+    s = nx // 2
+    raw = o.fetch("p")  # the FV cells' own pressure
+    assert np.abs(p[:, s:] - raw[:, s:]).max() <= 1e-10 * np.abs(raw[:, s:]).max()
+    assert np.abs(p - (g.fetch("rho") - 1.0) / 3.0).max() <= 1e-15
