@@ -10,15 +10,18 @@
 //              and the east wall face): u on x-faces [ny][pitch_F], v on
 //              y-faces [ny+1][pitch_F], p and T at centres [ny][pitch_F];
 //   shared columns c0, c0+1, c0+2 = ib.
-// One step is eight launches on one stream:
+// One step is nine launches on one stream:
 //   k_dd_ghost_rows, k_dd_ghost_fold  ghost columns of the FV zone from the LBM moments of the
 //                 previous step (two-point averages; the mean of the inflow
 //                 face is removed: global continuity of the FV zone) and
 //                 rho0 = mean LBM density over the shared columns (Eq 91-93);
-//   k_dd_momentum u*, v* (QUICK convection, central diffusion, pressure
-//                 gradient, buoyancy on v faces; Eq 74-75 explicit);
-//   k_dd_press_energy  p <- p - c_s^2 div u*, and the conservative QUICK
-//                 energy balance on u* (Eq 76);
+//   k_dd_fv       the interior of the FV zone in one pass: u*, v* (QUICK
+//                 convection, central diffusion, pressure gradient,
+//                 buoyancy; Eq 74-75 explicit), then p <- p - c_s^2 div u*
+//                 and the conservative QUICK energy balance on u* (Eq 76);
+//   k_dd_momentum_frame, k_dd_press_energy_frame  the same on the frame
+//                 of faces and cells the walls' mirror and ghost rules or
+//                 the inflow face reach;
 //   k_dd_pbar_rows, k_dd_pbar_fold  mean FV pressure over the shared columns,
 //                 and the mass the LBM zone is about to gain through the
 //                 links to x_b (its running total is the zone's mass change
@@ -36,8 +39,8 @@
 // The north wall may slide along +x (the lid-driven cavity of Sec. 3.3):
 // moving-wall bounce-back in the LBM zone, ghost u = 2 u_lid - u_edge in the
 // FV zone.
-// The LBM zone is 112 B per node (FP32) and the FV zone streams u, v, p, T
-// twice; the interface work is O(ny).
+// The LBM zone is 112 B per node (FP32), the FV zone 32 B per cell (u, v, p,
+// T read and written once); the interface work is O(ny).
 // The single-method cavities of the Sec. 4.2 comparison run the same zone
 // kernels on the whole box: FV only (momentum + pressure/energy, with the
 // west wall's mirror and ghost rules) or LBM only (k_dd_lbm with an east
@@ -111,7 +114,8 @@ struct SplitArgs {
   real* __restrict__ us;  // u*
   real* __restrict__ vs;  // v*
   real* __restrict__ Tn;
-  real* __restrict__ p;
+  const real* __restrict__ pin;  // pressure of the last step
+  real* __restrict__ p;          // pressure of this step
   int pF;
   // interface scalars (double): [0] rho0, [1] p_bar, [2] the LBM zone's mass
   // change since init, from [kIfacePart] the per-block sums of the ghost and
@@ -176,7 +180,7 @@ __device__ __forceinline__ real T_at(const SplitArgs<real>& a, const real* T, in
 }
 template <typename real>
 __device__ __forceinline__ real P_at(const SplitArgs<real>& a, int x, int j) {
-  return a.p[j * a.pF + fidx(a, x)];
+  return a.pin[j * a.pF + fidx(a, x)];
 }
 
 // 1. ghost columns from the LBM moments of the previous step; rho0.
@@ -272,10 +276,6 @@ __global__ __launch_bounds__(kGhostBlock) void k_dd_ghost_fold(SplitArgs<real> a
 
 // ---- field access relative to a thread's face / cell (x, j) ------------
 // GenAcc applies the wall mirror and ghost rules of U_at, V_at and T_at.
-// DirAcc serves waves whose stencils stay inside the stored FV zone: all
-// FV arrays share one layout, so a lane keeps one byte offset (row j - 2,
-// column x - 2), the row shift is a wave-uniform SGPR offset and the column
-// shift is folded into the load instruction.
 template <typename real>
 struct GenAcc {
   const SplitArgs<real>& a;
@@ -286,45 +286,6 @@ struct GenAcc {
   __device__ real vs(int dx, int dy) const { return V_at(a, a.vs, x + dx, j + dy); }
   __device__ real T(int dx, int dy) const { return T_at(a, a.T, x + dx, j + dy); }
   __device__ real p(int dx, int dy) const { return P_at(a, x + dx, j + dy); }
-};
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t fv_rsrc(const void* p, unsigned bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
-                                           0x00020000);
-}
-template <typename real>
-__device__ __forceinline__ real fv_load(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-  if constexpr (sizeof(real) == 4) {
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
-  } else {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
-  }
-}
-
-template <typename real>
-struct DirAcc {
-  __amdgpu_buffer_rsrc_t ru, rv, rus, rvs, rT, rp;
-  int vo, rowb;
-  __device__ DirAcc(const SplitArgs<real>& a, int x, int j) {
-    const unsigned bytes = (unsigned)((size_t)(a.ny + 1) * a.pF * sizeof(real));
-    ru = fv_rsrc(a.u, bytes);
-    rv = fv_rsrc(a.v, bytes);
-    rus = fv_rsrc(a.us, bytes);
-    rvs = fv_rsrc(a.vs, bytes);
-    rT = fv_rsrc(a.T, bytes);
-    rp = fv_rsrc(a.p, bytes);
-    vo = ((j - 2) * a.pF + fidx(a, x) - 2) * (int)sizeof(real);
-    rowb = a.pF * (int)sizeof(real);
-  }
-  __device__ real ld(__amdgpu_buffer_rsrc_t r, int dx, int dy) const {
-    return fv_load<real>(r, vo + (dx + 2) * (int)sizeof(real), (dy + 2) * rowb);
-  }
-  __device__ real u(int dx, int dy) const { return ld(ru, dx, dy); }
-  __device__ real v(int dx, int dy) const { return ld(rv, dx, dy); }
-  __device__ real us(int dx, int dy) const { return ld(rus, dx, dy); }
-  __device__ real vs(int dx, int dy) const { return ld(rvs, dx, dy); }
-  __device__ real T(int dx, int dy) const { return ld(rT, dx, dy); }
-  __device__ real p(int dx, int dy) const { return ld(rp, dx, dy); }
 };
 
 // face value of the convection scheme (Eq 76's QUICK, or central / upwind),
@@ -344,100 +305,101 @@ __device__ __forceinline__ real face_value(real uf, real ll, real l, real r, rea
 
 // 2. momentum: u* on x-faces c0+1 .. nx-1, v* on y-faces 1 .. ny-1 of the
 //    FV cells; wall and prescribed faces copied (face c0: the inflow face
-//    of the split cavity, or the west wall).  INNER: no such face in the
-//    wave.
+//    of the split cavity, or the west wall).
+// u* at a regular x-face (x, j) from an accessor centred there (Eq 74-75,
+// explicit): convection of u by QUICK (or central / upwind), central
+// diffusion, the pressure gradient, and buoyancy on x-faces when gravity
+// points along -x.  Every path that forms a face (the per-face kernels and
+// the fused march) goes through these functions, so a face gets the same
+// bits whichever path forms it.
+template <typename real, int CONV, typename Acc>
+__device__ __forceinline__ real ustar_val(const SplitArgs<real>& a, const Acc& F) {
+  const real nu = a.nu;
+  real Fc[2], Gc[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int dm = k - 1;  // cell m = x - 1 + k
+    const real ub = real(0.5) * (F.u(dm, 0) + F.u(dm + 1, 0));
+    const real uh = face_value<real, CONV>(ub, F.u(dm - 1, 0), F.u(dm, 0), F.u(dm + 1, 0),
+                                           F.u(dm + 2, 0));
+    Fc[k] = ub * uh;
+    const real vb = real(0.5) * (F.v(-1, k) + F.v(0, k));  // y-face j + k
+    const real uh2 = face_value<real, CONV>(vb, F.u(0, k - 2), F.u(0, k - 1), F.u(0, k),
+                                            F.u(0, k + 1));
+    Gc[k] = vb * uh2;
+  }
+  const real uc = F.u(0, 0);
+  const real lap = F.u(1, 0) + F.u(-1, 0) + F.u(0, 1) + F.u(0, -1) - real(4) * uc;
+  const real dp = F.p(0, 0) - F.p(-1, 0);
+  real out = uc - (Fc[1] - Fc[0]) - (Gc[1] - Gc[0]) + nu * lap - dp;
+  if (a.gdir) {  // buoyancy on the x-face from the two adjacent cells
+    const real Tfx = real(0.5) * (F.T(-1, 0) + F.T(0, 0));
+    out = out + a.gbeta * (Tfx - a.Tref);
+  }
+  return out;
+}
+
+// v* at a regular y-face (x, jf) from an accessor centred there
+template <typename real, int CONV, typename Acc>
+__device__ __forceinline__ real vstar_val(const SplitArgs<real>& a, const Acc& F) {
+  const real nu = a.nu;
+  real Fc[2], Gc[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int dm = k - 1;  // cell row m = jf - 1 + k
+    const real vb = real(0.5) * (F.v(0, dm) + F.v(0, dm + 1));
+    const real vh = face_value<real, CONV>(vb, F.v(0, dm - 1), F.v(0, dm), F.v(0, dm + 1),
+                                           F.v(0, dm + 2));
+    Fc[k] = vb * vh;
+    const real ub = real(0.5) * (F.u(k, -1) + F.u(k, 0));  // x-face x + k
+    const real vh2 = face_value<real, CONV>(ub, F.v(k - 2, 0), F.v(k - 1, 0), F.v(k, 0),
+                                            F.v(k + 1, 0));
+    Gc[k] = ub * vh2;
+  }
+  const real vc = F.v(0, 0);
+  const real lap = F.v(1, 0) + F.v(-1, 0) + F.v(0, 1) + F.v(0, -1) - real(4) * vc;
+  const real dp = F.p(0, 0) - F.p(0, -1);
+  const real Tf = real(0.5) * (F.T(0, -1) + F.T(0, 0));
+  real out = vc - (Gc[1] - Gc[0]) - (Fc[1] - Fc[0]) + nu * lap - dp;
+  if (!a.gdir) out = out + a.gbeta * (Tf - a.Tref);
+  return out;
+}
+
 template <typename real, int CONV, bool INNER, typename Acc>
 __device__ __forceinline__ void momentum_at(const SplitArgs<real>& a, const Acc& F, int x,
-                                            int j) {
-  const real nu = a.nu;
+                                            int j, bool do_u, bool do_v) {
   const int o = j * a.pF + fidx(a, x);
   // ---- u* at face (x, j)
-  if (INNER || j < a.ny) {
+  if (do_u && (INNER || j < a.ny)) {
     real out;
     if (!INNER && x == a.c0) {
       out = a.u[o];       // prescribed inflow face
     } else if (!INNER && x == a.nx) {
       out = real(0);      // east wall
     } else {
-      real Fc[2], Gc[2];
-#pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        const int dm = k - 1;  // cell m = x - 1 + k
-        const real ub = real(0.5) * (F.u(dm, 0) + F.u(dm + 1, 0));
-        const real uh = face_value<real, CONV>(ub, F.u(dm - 1, 0), F.u(dm, 0), F.u(dm + 1, 0),
-                                               F.u(dm + 2, 0));
-        Fc[k] = ub * uh;
-        const real vb = real(0.5) * (F.v(-1, k) + F.v(0, k));  // y-face j + k
-        const real uh2 = face_value<real, CONV>(vb, F.u(0, k - 2), F.u(0, k - 1), F.u(0, k),
-                                                F.u(0, k + 1));
-        Gc[k] = vb * uh2;
-      }
-      const real uc = F.u(0, 0);
-      const real lap = F.u(1, 0) + F.u(-1, 0) + F.u(0, 1) + F.u(0, -1) - real(4) * uc;
-      const real dp = F.p(0, 0) - F.p(-1, 0);
-      out = uc - (Fc[1] - Fc[0]) - (Gc[1] - Gc[0]) + nu * lap - dp;
-      if (a.gdir) {  // buoyancy on the x-face from the two adjacent cells
-        const real Tfx = real(0.5) * (F.T(-1, 0) + F.T(0, 0));
-        out = out + a.gbeta * (Tfx - a.Tref);
-      }
+      out = ustar_val<real, CONV>(a, F);
     }
     a.us[o] = out;
   }
   // ---- v* at face (x, j) for cells x < nx
-  if (INNER || x < a.nx) {
+  if (do_v && (INNER || x < a.nx)) {
     real out = real(0);
-    if (INNER || (j > 0 && j < a.ny)) {
-      real Fc[2], Gc[2];
-#pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        const int dm = k - 1;  // cell row m = j - 1 + k
-        const real vb = real(0.5) * (F.v(0, dm) + F.v(0, dm + 1));
-        const real vh = face_value<real, CONV>(vb, F.v(0, dm - 1), F.v(0, dm), F.v(0, dm + 1),
-                                               F.v(0, dm + 2));
-        Fc[k] = vb * vh;
-        const real ub = real(0.5) * (F.u(k, -1) + F.u(k, 0));  // x-face x + k
-        const real vh2 = face_value<real, CONV>(ub, F.v(k - 2, 0), F.v(k - 1, 0), F.v(k, 0),
-                                                F.v(k + 1, 0));
-        Gc[k] = ub * vh2;
-      }
-      const real vc = F.v(0, 0);
-      const real lap = F.v(1, 0) + F.v(-1, 0) + F.v(0, 1) + F.v(0, -1) - real(4) * vc;
-      const real dp = F.p(0, 0) - F.p(0, -1);
-      const real Tf = real(0.5) * (F.T(0, -1) + F.T(0, 0));
-      out = vc - (Gc[1] - Gc[0]) - (Fc[1] - Fc[0]) + nu * lap - dp;
-      if (!a.gdir) out = out + a.gbeta * (Tf - a.Tref);
-    }
+    if (INNER || (j > 0 && j < a.ny)) out = vstar_val<real, CONV>(a, F);
     a.vs[o] = out;
   }
 }
 
-template <typename real, int CONV>
-__global__ __launch_bounds__(256) void k_dd_momentum(SplitArgs<real> a) {
-  const int x0 = a.c0 + blockIdx.x * blockDim.x;
-  const int x = x0 + threadIdx.x;  // c0 .. nx
-  const int j = blockIdx.y;        // 0 .. ny
-  if (x > a.nx) return;
-  // u* reaches u, v two faces away and p, T one cell away in x and y:
-  // the wave's faces are inner when they are clear of the inflow face, the
-  // east wall's mirror and the walls' ghost rows (uniform per wave)
-  const int xw = x0 + (int)(threadIdx.x & ~63u);
-  const bool inner = xw >= a.c0 + (a.west_wall ? 2 : 1) && xw + 63 <= a.nx - 3 && j >= 2 &&
-                     j <= a.ny - 3;
-  if (inner) momentum_at<real, CONV, true>(a, DirAcc<real>(a, x, j), x, j);
-  else momentum_at<real, CONV, false>(a, GenAcc<real>{a, x, j}, x, j);
-}
-
-// 3. pressure (artificial compressibility, beta = c_s^2) and energy on u*
+// 3. pressure (artificial compressibility, beta = c_s^2) and energy on u*:
+// new p and T of cell (x, j) from an accessor of u*, v* and T centred there
 template <typename real, int CONV, bool INNER, typename Acc>
-__device__ __forceinline__ void press_energy_at(const SplitArgs<real>& a, const Acc& F, int x,
-                                                int j) {
+__device__ __forceinline__ void press_energy_val(const SplitArgs<real>& a, const Acc& F, int x,
+                                                 int j, real pin, real Tc, real& pnew,
+                                                 real& Tnew) {
   const real al = a.alpha;
   const real ue = (!INNER && x == a.nx - 1) ? real(0) : F.us(1, 0);
   const real uw = F.us(0, 0);
   const real vn = F.vs(0, 1), vsd = F.vs(0, 0);
-  const int o = j * a.pF + fidx(a, x);
-  a.p[o] = a.p[o] - real(1) / real(3) * ((ue - uw) + (vn - vsd));
-  const real Tc = a.T[o];
+  pnew = pin - real(1) / real(3) * ((ue - uw) + (vn - vsd));
   real Fx[2], Gy[2];
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
@@ -463,21 +425,205 @@ __device__ __forceinline__ void press_energy_at(const SplitArgs<real>& a, const 
       Gy[k] = fmad(vf, th, -al * (F.T(0, k) - F.T(0, k - 1)));
     }
   }
-  a.Tn[o] = Tc - (Fx[1] - Fx[0]) - (Gy[1] - Gy[0]);
+  Tnew = Tc - (Fx[1] - Fx[0]) - (Gy[1] - Gy[0]);
+}
+
+template <typename real, int CONV, bool INNER, typename Acc>
+__device__ __forceinline__ void press_energy_at(const SplitArgs<real>& a, const Acc& F, int x,
+                                                int j) {
+  const int o = j * a.pF + fidx(a, x);
+  real pn, Tn;
+  press_energy_val<real, CONV, INNER>(a, F, x, j, a.pin[o], a.T[o], pn, Tn);
+  a.p[o] = pn;
+  a.Tn[o] = Tn;
+}
+
+// ---- fused FV step of the interior (one pass) ---------------------------
+// A 64-lane wave owns the columns x0 .. x0 + 63 (x0 = xa + 59 s for strip
+// s) and marches a band of rows upward; lanes 2 .. 60 are its cells, the
+// others halos (QUICK reaches two cells, and u* at a cell's east face is
+// formed by the lane to its right).  Each lane keeps a rolling window of its
+// own column (u on rows j-2 .. j+2, v on faces j-1 .. j+3, p on rows j, j+1,
+// T on rows j-2 .. j+2); values of neighbouring columns come by cross-lane
+// permutes.  Per row a lane forms u* on its cell's west face and v* on its
+// north face, then the cell's new p and T, and loads one row of u, v, p and
+// T: the FV zone's 32 bytes per cell, read and written once.  Strips and
+// bands clear of the inflow face, the walls and their mirror and ghost
+// rules only; the rest (the frame) runs the per-face / per-cell kernels,
+// which form shared faces with the same arithmetic.
+constexpr int kFvOut = 59;
+
+// The fused region and the frame around it (set on the host, fv_region):
+// strips of kFvOut cells whose lane 0 sits at column xa + kFvOut s, bands of
+// `band` rows from row 2; fused cells X0 .. X1 on rows 2 .. ny - 3 (X0 > X1:
+// none).  The frame's positions: nbt bottom / top rows over the nfc face
+// columns, then the middle rows over wl columns west of X0 and wr east of X1.
+struct FvRegion {
+  int nst, band, nbands;
+  int xa, X0, X1;
+  int nfc, nbt, wl, wr, nframe;
+};
+
+template <typename real>
+__device__ __forceinline__ real lane_get(real v, int d) {
+  return d > 0 ? __shfl_down(v, d, 64) : d < 0 ? __shfl_up(v, -d, 64) : v;
+}
+
+// window accessors: u* at (x, j) and v* at (x, j + 1) from the window of
+// row j (wu: rows j-2 .. j+2, wv: faces j-1 .. j+3, wp: rows j, j+1, wT:
+// rows j-2 .. j+2), and the cell (x, j) from its faces' u*, v*
+template <typename real>
+struct WinU {
+  const real (&wu)[5], (&wv)[5], (&wp)[2], (&wT)[5];
+  __device__ real u(int dx, int dy) const { return dy == 0 ? lane_get(wu[2], dx) : wu[2 + dy]; }
+  __device__ real v(int dx, int dy) const { return lane_get(wv[1 + dy], dx); }
+  __device__ real p(int dx, int) const { return lane_get(wp[0], dx); }
+  __device__ real T(int dx, int) const { return lane_get(wT[2], dx); }
+};
+template <typename real>
+struct WinV {
+  const real (&wu)[5], (&wv)[5], (&wp)[2], (&wT)[5];
+  __device__ real v(int dx, int dy) const { return dy == 0 ? lane_get(wv[2], dx) : wv[2 + dy]; }
+  __device__ real u(int dx, int dy) const { return lane_get(wu[3 + dy], dx); }
+  __device__ real p(int, int dy) const { return wp[1 + dy]; }
+  __device__ real T(int, int dy) const { return wT[3 + dy]; }
+};
+template <typename real>
+struct WinE {
+  real usw, use, vss, vsn;
+  const real (&wT)[5];
+  __device__ real us(int dx, int) const { return dx == 0 ? usw : use; }
+  __device__ real vs(int, int dy) const { return dy == 0 ? vss : vsn; }
+  __device__ real T(int dx, int dy) const { return dy == 0 ? lane_get(wT[2], dx) : wT[2 + dy]; }
+};
+
+template <typename real, int CONV>
+__global__ __launch_bounds__(256) void k_dd_fv(SplitArgs<real> a, FvRegion R) {
+  // blocks renumbered so that each XCD works on a contiguous range of waves
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int per = nb / 8, rem = nb % 8, xcd = b % 8;
+  const int lb = xcd * per + (xcd < rem ? xcd : rem) + b / 8;
+  const int wave = __builtin_amdgcn_readfirstlane(lb * 4 + (int)(threadIdx.x >> 6));
+  if (wave >= R.nst * R.nbands) return;
+  const int lane = threadIdx.x & 63;
+  const int strip = wave % R.nst, bnd = wave / R.nst;
+  const int x = R.xa + kFvOut * strip + lane;
+  const int j0 = 2 + bnd * R.band;
+  const int j1 = min(j0 + R.band, a.ny - 2);
+  const bool out = lane >= 2 && lane <= 60;
+  const int pF = a.pF, c = fidx(a, x);
+  const real* __restrict__ U = a.u;
+  const real* __restrict__ V = a.v;
+  const real* __restrict__ Pi = a.pin;
+  const real* __restrict__ TT = a.T;
+  real u[5], v[5], p[2], T[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    u[k] = U[(j0 - 2 + k) * pF + c];
+    v[k] = V[(j0 - 1 + k) * pF + c];
+    T[k] = TT[(j0 - 2 + k) * pF + c];
+  }
+  p[0] = Pi[j0 * pF + c];
+  p[1] = Pi[(j0 + 1) * pF + c];
+  // v* on the band's south face j0: the window of row j0 - 1
+  real vsouth;
+  {
+    real u1[5], v1[5], p1[2], T1[5];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      u1[k + 1] = u[k];
+      v1[k + 1] = v[k];
+      T1[k + 1] = T[k];
+    }
+    u1[0] = u[0];  // row j0 - 3: not used by v* on face j0
+    v1[0] = V[(j0 - 2) * pF + c];
+    T1[0] = T[0];  // row j0 - 3: not used
+    p1[0] = Pi[(j0 - 1) * pF + c];
+    p1[1] = p[0];
+    vsouth = vstar_val<real, CONV>(a, WinV<real>{u1, v1, p1, T1});
+  }
+  for (int j = j0; j < j1; ++j) {
+    // the next row's inputs, requested before this row's arithmetic
+    const bool more = j + 1 < j1;
+    real un = real(0), vn = real(0), pn = real(0), Tn = real(0);
+    if (more) {
+      un = U[(j + 3) * pF + c];
+      vn = V[(j + 4) * pF + c];
+      pn = Pi[(j + 2) * pF + c];
+      Tn = TT[(j + 3) * pF + c];
+    }
+    const real us = ustar_val<real, CONV>(a, WinU<real>{u, v, p, T});
+    const real vnorth = vstar_val<real, CONV>(a, WinV<real>{u, v, p, T});
+    const real ue = __shfl_down(us, 1, 64);
+    real pnew, Tnew;
+    press_energy_val<real, CONV, true>(a, WinE<real>{us, ue, vsouth, vnorth, T}, x, j, p[0],
+                                       T[2], pnew, Tnew);
+    if (out) {
+      const int o = j * pF + c;
+      a.us[o] = us;
+      a.vs[o + pF] = vnorth;
+      a.p[o] = pnew;
+      a.Tn[o] = Tnew;
+    }
+    if (!more) break;
+    vsouth = vnorth;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      u[k] = u[k + 1];
+      v[k] = v[k + 1];
+      T[k] = T[k + 1];
+    }
+    u[4] = un;
+    v[4] = vn;
+    T[4] = Tn;
+    p[0] = p[1];
+    p[1] = pn;
+  }
+}
+
+// the frame around the fused region: per-face momentum and per-cell
+// pressure and energy, one thread per face or cell position of the frame,
+// the faces and cells the fused march forms skipped.  Positions: rows
+// 0 .. 2 and ny - 2 .. ny over every face column c0 .. nx (all rows when
+// ny < 5), then rows 3 .. ny - 3 over the columns outside [X0, X1].
+template <typename real>
+__device__ __forceinline__ void frame_xy(const SplitArgs<real>& a, const FvRegion& R, int idx,
+                                         int& x, int& j) {
+  const int nA = R.nbt * R.nfc;
+  if (idx < nA) {
+    const int r = idx / R.nfc;
+    x = a.c0 + idx % R.nfc;
+    j = (R.nbt < 6 || r < 3) ? r : a.ny - 5 + r;
+    return;
+  }
+  idx -= nA;
+  const int w = R.wl + R.wr;
+  const int k = idx % w;
+  x = k < R.wl ? a.c0 + k : R.X1 + 1 + (k - R.wl);
+  j = 3 + idx / w;
 }
 
 template <typename real, int CONV>
-__global__ __launch_bounds__(256) void k_dd_press_energy(SplitArgs<real> a) {
-  const int x0 = a.c0 + blockIdx.x * blockDim.x;
-  const int x = x0 + threadIdx.x;
-  const int j = blockIdx.y;
-  if (x >= a.nx) return;
-  // T reaches two cells away in x and y, u*, v* one face (uniform per wave)
-  const int xw = x0 + (int)(threadIdx.x & ~63u);
-  const bool inner = xw >= a.c0 + (a.west_wall ? 2 : 0) && xw + 63 <= a.nx - 3 && j >= 2 &&
-                     j <= a.ny - 3;
-  if (inner) press_energy_at<real, CONV, true>(a, DirAcc<real>(a, x, j), x, j);
-  else press_energy_at<real, CONV, false>(a, GenAcc<real>{a, x, j}, x, j);
+__global__ __launch_bounds__(256) void k_dd_momentum_frame(SplitArgs<real> a, FvRegion R) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= R.nframe) return;
+  int x, j;
+  frame_xy(a, R, idx, x, j);
+  const bool incols = x >= R.X0 && x <= R.X1;
+  const bool do_u = !(incols && j >= 2 && j <= a.ny - 3);
+  const bool do_v = !(incols && j >= 3 && j <= a.ny - 2);
+  momentum_at<real, CONV, false>(a, GenAcc<real>{a, x, j}, x, j, do_u, do_v);
+}
+
+template <typename real, int CONV>
+__global__ __launch_bounds__(256) void k_dd_press_energy_frame(SplitArgs<real> a, FvRegion R) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= R.nframe) return;
+  int x, j;
+  frame_xy(a, R, idx, x, j);
+  if (x >= a.nx || j >= a.ny) return;                               // face-only positions
+  if (x >= R.X0 && x <= R.X1 && j >= 2 && j <= a.ny - 3) return;  // the fused march's cell
+  press_energy_at<real, CONV, false>(a, GenAcc<real>{a, x, j}, x, j);
 }
 
 // 4. p_bar: mean new FV pressure over the shared columns; and the net mass
@@ -762,7 +908,7 @@ __global__ __launch_bounds__(256) void k_dd_output(SplitArgs<real> a, real* __re
     u = real(0.5) * (a.u[o] + ue);
     v = real(0.5) * (a.v[o] + a.v[(j + 1) * a.pF + fidx(a, x)]);
     t = a.T[o];
-    r = real(1) + real(3) * a.p[o];
+    r = real(1) + real(3) * a.pin[o];
   }
   out[d] = r;
   out[n + d] = a.transposed ? v : u;
@@ -1180,7 +1326,8 @@ static SplitArgs<real> make_args(const SplitGeom& G, const SplitPtrs<real>& P, c
   a.us = P.u[nxt];
   a.vs = P.v[nxt];
   a.Tn = P.T[nxt];
-  a.p = P.p;
+  a.pin = P.p[cur];
+  a.p = P.p[nxt];
   a.pF = G.pF;
   a.iface = P.iface;
   a.nx = G.nx;
@@ -1215,14 +1362,57 @@ static SplitArgs<real> make_args(const SplitGeom& G, const SplitPtrs<real>& P, c
   return a;
 }
 
+// Fused region for a band height: strips need the whole 64-lane window
+// inside the stored columns (x0 + 63 <= nx - 1) and at least one row
+// clear of the walls' ghost rules (ny >= 5).
+static FvRegion fv_region(const SplitGeom& G, int band) {
+  FvRegion r{};
+  r.xa = G.c0 - 1 + (G.fv_only ? 1 : 0);
+  const int span = G.nx - 64 - r.xa;
+  r.nst = (span < 0 || G.ny < 5) ? 0 : span / kFvOut + 1;
+  r.band = band;
+  r.nbands = r.nst ? (G.ny - 4 + band - 1) / band : 0;
+  if (r.nst) {
+    r.X0 = r.xa + 2;
+    r.X1 = r.xa + kFvOut * r.nst + 1;
+  } else {
+    r.X0 = G.nx + 1;
+    r.X1 = G.nx;
+  }
+  r.nfc = G.nx - G.c0 + 1;
+  r.nbt = G.ny + 1 < 6 ? G.ny + 1 : 6;
+  const int nmid = G.ny - 5 > 0 ? G.ny - 5 : 0;
+  r.wl = r.X0 - G.c0;
+  r.wr = G.nx - r.X1;
+  r.nframe = r.nbt * r.nfc + nmid * (r.wl + r.wr);
+  return r;
+}
+
+// rows per wave of the fused march: the longest of 16, 8, 4 that still
+// gives the chip 2048 waves (the halo rows cost 4.5 row loads per band)
+static FvRegion fv_region_auto(const SplitGeom& G) {
+  int band = 16;
+  FvRegion r = fv_region(G, band);
+  while (band > 4 && r.nst * r.nbands < 2048) {
+    band /= 2;
+    r = fv_region(G, band);
+  }
+  return r;
+}
+
+template <typename real, int CONV>
+static void launch_fv(const SplitArgs<real>& a, const FvRegion& R, hipStream_t s) {
+  const int nw = R.nst * R.nbands;
+  if (nw > 0) hipLaunchKernelGGL((k_dd_fv<real, CONV>), dim3((nw + 3) / 4), dim3(256), 0, s, a, R);
+  const dim3 gf((R.nframe + 255) / 256);
+  hipLaunchKernelGGL((k_dd_momentum_frame<real, CONV>), gf, dim3(256), 0, s, a, R);
+  hipLaunchKernelGGL((k_dd_press_energy_frame<real, CONV>), gf, dim3(256), 0, s, a, R);
+}
+
 template <typename real>
 hipError_t launch_split_step(const SplitGeom& G, const SplitPtrs<real>& P, const SplitParams& S,
                              int cur, int mom_all, hipStream_t s) {
   const SplitArgs<real> a = make_args<real>(G, P, S, cur, mom_all);
-  // interior FV blocks address their arrays with 32-bit byte offsets
-  if ((size_t)(G.ny + 1) * G.pF * sizeof(real) >= ((size_t)1 << 31)) return hipErrorInvalidValue;
-  const int nfc = G.nx - G.c0 + 1;  // FV columns c0 .. nx
-  const dim3 gm((nfc + 255) / 256, G.ny + 1), ge((nfc + 255) / 256, G.ny);
   const dim3 gl((a.nl + 63) / 64, (G.ny + 3) / 4);
   if (G.lbm_only) {  // one zone kernel per step
     hipLaunchKernelGGL(k_dd_lbm<real>, gl, dim3(256), 0, s, a);
@@ -1235,16 +1425,10 @@ hipError_t launch_split_step(const SplitGeom& G, const SplitPtrs<real>& P, const
     hipLaunchKernelGGL(k_dd_ghost_fold<real>, dim3((G.ny + kGhostBlock - 1) / kGhostBlock),
                        dim3(kGhostBlock), 0, s, a, ngb);
   }
-  if (S.conv == 1) {
-    hipLaunchKernelGGL((k_dd_momentum<real, 1>), gm, dim3(256), 0, s, a);
-    hipLaunchKernelGGL((k_dd_press_energy<real, 1>), ge, dim3(256), 0, s, a);
-  } else if (S.conv == 2) {
-    hipLaunchKernelGGL((k_dd_momentum<real, 2>), gm, dim3(256), 0, s, a);
-    hipLaunchKernelGGL((k_dd_press_energy<real, 2>), ge, dim3(256), 0, s, a);
-  } else {
-    hipLaunchKernelGGL((k_dd_momentum<real, 0>), gm, dim3(256), 0, s, a);
-    hipLaunchKernelGGL((k_dd_press_energy<real, 0>), ge, dim3(256), 0, s, a);
-  }
+  const FvRegion R = fv_region_auto(G);
+  if (S.conv == 1) launch_fv<real, 1>(a, R, s);
+  else if (S.conv == 2) launch_fv<real, 2>(a, R, s);
+  else launch_fv<real, 0>(a, R, s);
   if (split) {
     const int npb = (G.ny + kGhostBlock - 1) / kGhostBlock;
     hipLaunchKernelGGL(k_dd_pbar_rows<real>, dim3(npb), dim3(kGhostBlock), 0, s, a);

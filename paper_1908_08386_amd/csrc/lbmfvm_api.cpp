@@ -53,7 +53,7 @@ struct lf_case {
   bool split;
   lf::SplitGeom sg;
   lf::SplitParams sp;
-  size_t off_sf[2], off_sg[2], off_smom, off_sxf, off_su[2], off_sv[2], off_sT[2], off_sp,
+  size_t off_sf[2], off_sg[2], off_smom, off_sxf, off_su[2], off_sv[2], off_sT[2], off_sp[2],
       off_siface, off_dense, off_dsnap;
   // grid setting 2: the coarse planes, lattice steps per energy step and
   // line sweeps per energy step
@@ -87,7 +87,8 @@ static void layout_split(lf_case* c) {
   for (int k = 0; k < 2; ++k) { c->off_su[k] = o; o += pbF; }
   for (int k = 0; k < 2; ++k) { c->off_sv[k] = o; o += pbF; }
   for (int k = 0; k < 2; ++k) { c->off_sT[k] = o; o += pbF; }
-  c->off_sp = o; o += pbF;
+  c->off_sp[0] = o; o += pbF;
+  c->off_sp[1] = o; o += pbF;
   // interface scalars, then two sums per 256-row block of the ghost kernel
   c->off_siface = o; o += align_up((size_t)(8 + 2 * ((G.ny + 1 + 255) / 256)) * sizeof(double), 256);
   for (int k = 0; k < 10; ++k) {
@@ -123,7 +124,8 @@ static lf::SplitPtrs<real> split_ptrs(lf_case* c) {
   (void)pbL;
   P.mom = (real*)(c->ws + c->off_smom);
   P.xf = (real*)(c->ws + c->off_sxf);
-  P.p = (real*)(c->ws + c->off_sp);
+  P.p[0] = (real*)(c->ws + c->off_sp[0]);
+  P.p[1] = (real*)(c->ws + c->off_sp[1]);
   P.iface = (double*)(c->ws + c->off_siface);
   for (int k = 0; k < 10; ++k) P.gc[k] = (real*)(c->ws + c->off_gs2[k]);
   P.mcm_count = (int*)(c->ws + c->off_mcm_count);

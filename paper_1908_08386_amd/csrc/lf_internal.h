@@ -152,7 +152,7 @@ struct SplitPtrs {
   real* u[2];   // x-faces, ny rows * pF
   real* v[2];   // y-faces, (ny + 1) rows * pF
   real* T[2];   // centres
-  real* p;      // centres
+  real* p[2];   // centres (ping-pong: each FV step reads one and writes the other)
   double* iface;  // [0] rho0, [1] p_bar, [2] LBM zone mass minus its value at
                   // init (carried across steps), from [8] two sums per 256 rows
   // grid setting 2, NYc rows * pC each: T (iterate A), T (iterate B),
