@@ -55,6 +55,8 @@ def main(argv=None):
     ap.add_argument("--max-ny-train", type=int, default=128)
     ap.add_argument("--heldout-n", type=int, default=128)
     ap.add_argument("--max-ny-eval", type=int, default=0, help="0 = full drawn sizes")
+    ap.add_argument("--heldout-range", default="",
+                    help="evaluate only draws A:B of the held-out set (split long evaluations)")
     ap.add_argument("--res", type=int, default=128)
     ap.add_argument("--widths", default="32,32,64,64,128")
     ap.add_argument("--epochs", type=int, default=150)
@@ -131,14 +133,19 @@ def main(argv=None):
 
 
 def evaluate(a, ctx, net, report):
-    log(f"step: held-out comparison ({a.heldout_n} cavities)")
     held = cavity_sweep(a.heldout_n, SEED_HELDOUT, max_ny=a.max_ny_eval or None)
+    lo, hi = 0, len(held)
+    if a.heldout_range:
+        lo, hi = (int(x) for x in a.heldout_range.split(":"))
+        held = held[lo:hi]
+    log(f"step: held-out comparison (draws {lo}..{hi - 1} of {a.heldout_n})")
     T0h = [perturbation(c["nx"], c["ny"], c["seed"]) for c in held]
     res = ws.compare(ctx, net, held, T0h, max_steps=a.max_steps, log=log)
     dnu = np.abs(res["nu_warm"] - res["nu_cold"]) / np.abs(res["nu_cold"])
     ratio = res["steps_warm"] / np.maximum(res["steps_cold"], 1)
     report["heldout"] = {
-        "n": a.heldout_n, "max_ny": a.max_ny_eval or 512,
+        "n": a.heldout_n, "draws": [lo, hi], "max_ny": a.max_ny_eval or 512,
+        "max_steps": a.max_steps,
         "seconds_cold": round(res["seconds_cold"], 2), "seconds_warm": round(res["seconds_warm"], 2),
         "seconds_predict": round(res["seconds_predict"], 3),
         "speedup_wall": round(res["seconds_cold"] / res["seconds_warm"], 3),
