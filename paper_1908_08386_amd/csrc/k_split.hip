@@ -10,7 +10,7 @@
 //              and the east wall face): u on x-faces [ny][pitch_F], v on
 //              y-faces [ny+1][pitch_F], p and T at centres [ny][pitch_F];
 //   shared columns c0, c0+1, c0+2 = ib.
-// One step is nine launches on one stream:
+// One step is seven launches on one stream:
 //   k_dd_ghost_rows, k_dd_ghost_fold  ghost columns of the FV zone from the LBM moments of the
 //                 previous step (two-point averages; the mean of the inflow
 //                 face is removed: global continuity of the FV zone) and
@@ -19,9 +19,9 @@
 //                 convection, central diffusion, pressure gradient,
 //                 buoyancy; Eq 74-75 explicit), then p <- p - c_s^2 div u*
 //                 and the conservative QUICK energy balance on u* (Eq 76);
-//   k_dd_momentum_frame, k_dd_press_energy_frame  the same on the frame
-//                 of faces and cells the walls' mirror and ghost rules or
-//                 the inflow face reach;
+//                 the frame of faces and cells the walls' mirror and ghost
+//                 rules or the inflow face reach is formed by other blocks of
+//                 the same launch;
 //   k_dd_pbar_rows, k_dd_pbar_fold  mean FV pressure over the shared columns,
 //                 and the mass the LBM zone is about to gain through the
 //                 links to x_b (its running total is the zone's mass change
@@ -365,30 +365,6 @@ __device__ __forceinline__ real vstar_val(const SplitArgs<real>& a, const Acc& F
   return out;
 }
 
-template <typename real, int CONV, bool INNER, typename Acc>
-__device__ __forceinline__ void momentum_at(const SplitArgs<real>& a, const Acc& F, int x,
-                                            int j, bool do_u, bool do_v) {
-  const int o = j * a.pF + fidx(a, x);
-  // ---- u* at face (x, j)
-  if (do_u && (INNER || j < a.ny)) {
-    real out;
-    if (!INNER && x == a.c0) {
-      out = a.u[o];       // prescribed inflow face
-    } else if (!INNER && x == a.nx) {
-      out = real(0);      // east wall
-    } else {
-      out = ustar_val<real, CONV>(a, F);
-    }
-    a.us[o] = out;
-  }
-  // ---- v* at face (x, j) for cells x < nx
-  if (do_v && (INNER || x < a.nx)) {
-    real out = real(0);
-    if (INNER || (j > 0 && j < a.ny)) out = vstar_val<real, CONV>(a, F);
-    a.vs[o] = out;
-  }
-}
-
 // 3. pressure (artificial compressibility, beta = c_s^2) and energy on u*:
 // new p and T of cell (x, j) from an accessor of u*, v* and T centred there
 template <typename real, int CONV, bool INNER, typename Acc>
@@ -428,45 +404,65 @@ __device__ __forceinline__ void press_energy_val(const SplitArgs<real>& a, const
   Tnew = Tc - (Fx[1] - Fx[0]) - (Gy[1] - Gy[0]);
 }
 
-template <typename real, int CONV, bool INNER, typename Acc>
-__device__ __forceinline__ void press_energy_at(const SplitArgs<real>& a, const Acc& F, int x,
-                                                int j) {
-  const int o = j * a.pF + fidx(a, x);
-  real pn, Tn;
-  press_energy_val<real, CONV, INNER>(a, F, x, j, a.pin[o], a.T[o], pn, Tn);
-  a.p[o] = pn;
-  a.Tn[o] = Tn;
-}
-
-// ---- fused FV step of the interior (one pass) ---------------------------
-// A 64-lane wave owns the columns x0 .. x0 + 63 (x0 = xa + 59 s for strip
-// s) and marches a band of rows upward; lanes 2 .. 60 are its cells, the
-// others halos (QUICK reaches two cells, and u* at a cell's east face is
-// formed by the lane to its right).  Each lane keeps a rolling window of its
-// own column (u on rows j-2 .. j+2, v on faces j-1 .. j+3, p on rows j, j+1,
-// T on rows j-2 .. j+2); values of neighbouring columns come by cross-lane
+// ---- FV step in one launch ----------------------------------------------
+// The interior: a 64-lane wave owns the columns x0 .. x0 + 63 of a strip
+// and marches a band of rows upward; lanes 2 .. 60 are its cells, the others
+// halos (QUICK reaches two cells, and u* at a cell's east face is formed by
+// the lane to its right).  Each lane keeps a rolling window of its own
+// column (u on rows j-2 .. j+2, v on faces j-1 .. j+3, p on rows j, j+1, T
+// on rows j-2 .. j+2); values of neighbouring columns come by cross-lane
 // permutes.  Per row a lane forms u* on its cell's west face and v* on its
-// north face, then the cell's new p and T, and loads one row of u, v, p and
-// T: the FV zone's 32 bytes per cell, read and written once.  Strips and
-// bands clear of the inflow face, the walls and their mirror and ghost
-// rules only; the rest (the frame) runs the per-face / per-cell kernels,
-// which form shared faces with the same arithmetic.
+// north face, then the cell's new p and T, while the loads of the row two
+// ahead are in flight: the FV zone's 32 bytes per cell, read and written
+// once.  Strips start at xa + 59 s; when they do not reach column nx - 4 a
+// last strip at nx - 64 forms the cells east of X1 only.
+// The frame (cells and faces the walls' mirror and ghost rules or the inflow
+// face reach) is formed in the same launch by other blocks, one thread per
+// face / cell position, each forming the faces its cell needs itself: the
+// march and the frame share no memory within the launch, and a face both
+// form is formed by the same arithmetic from the same values.
 constexpr int kFvOut = 59;
 
-// The fused region and the frame around it (set on the host, fv_region):
-// strips of kFvOut cells whose lane 0 sits at column xa + kFvOut s, bands of
-// `band` rows from row 2; fused cells X0 .. X1 on rows 2 .. ny - 3 (X0 > X1:
-// none).  The frame's positions: nbt bottom / top rows over the nfc face
-// columns, then the middle rows over wl columns west of X0 and wr east of X1.
+// The fused region and the frame (set on the host, fv_region): nst strips of
+// kFvOut cells whose lane 0 sits at column xa + kFvOut s, plus npart = 1 last
+// strip at nx - 64 writing cells x > xcut only; bands of `band` rows from
+// row 2; fused cells X0 .. X1 on rows 2 .. ny - 3 (X0 > X1: none).  The
+// frame's positions: nbt bottom / top rows over the nfc face columns, then
+// the middle rows over wl columns west of X0 and wr east of X1; its nfrb
+// blocks come first in the grid.
 struct FvRegion {
-  int nst, band, nbands;
+  int nst, npart, xcut, band, nbands, nwaves;
   int xa, X0, X1;
-  int nfc, nbt, wl, wr, nframe;
+  int nfc, nbt, wl, wr, nframe, nfrb;
 };
 
 template <typename real>
 __device__ __forceinline__ real lane_get(real v, int d) {
   return d > 0 ? __shfl_down(v, d, 64) : d < 0 ? __shfl_up(v, -d, 64) : v;
+}
+
+// raw buffer access: a per-lane byte offset (the column) and a wave-uniform
+// one (the row); the record size bounds every access
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t fv_rsrc(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
+                                           0x00020000);
+}
+template <typename real>
+__device__ __forceinline__ real fv_load(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  if constexpr (sizeof(real) == 4) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  } else {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  }
+}
+template <typename real>
+__device__ __forceinline__ void fv_store(real v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  if constexpr (sizeof(real) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+  } else {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+  }
 }
 
 // window accessors: u* at (x, j) and v* at (x, j + 1) from the window of
@@ -496,96 +492,33 @@ struct WinE {
   __device__ real vs(int, int dy) const { return dy == 0 ? vss : vsn; }
   __device__ real T(int dx, int dy) const { return dy == 0 ? lane_get(wT[2], dx) : wT[2 + dy]; }
 };
+// a frame cell: the faces' u*, v* it formed, T through the ghost rules
+template <typename real>
+struct FrameE {
+  real usw, use, vss, vsn;
+  GenAcc<real> g;
+  __device__ real us(int dx, int) const { return dx == 0 ? usw : use; }
+  __device__ real vs(int, int dy) const { return dy == 0 ? vss : vsn; }
+  __device__ real T(int dx, int dy) const { return g.T(dx, dy); }
+};
 
+// u* on x-face (x, j < ny) and v* on y-face (x < nx, jf) with the rules of
+// the prescribed inflow face, the walls and their mirror and ghost rules
 template <typename real, int CONV>
-__global__ __launch_bounds__(256) void k_dd_fv(SplitArgs<real> a, FvRegion R) {
-  // blocks renumbered so that each XCD works on a contiguous range of waves
-  const int nb = gridDim.x, b = blockIdx.x;
-  const int per = nb / 8, rem = nb % 8, xcd = b % 8;
-  const int lb = xcd * per + (xcd < rem ? xcd : rem) + b / 8;
-  const int wave = __builtin_amdgcn_readfirstlane(lb * 4 + (int)(threadIdx.x >> 6));
-  if (wave >= R.nst * R.nbands) return;
-  const int lane = threadIdx.x & 63;
-  const int strip = wave % R.nst, bnd = wave / R.nst;
-  const int x = R.xa + kFvOut * strip + lane;
-  const int j0 = 2 + bnd * R.band;
-  const int j1 = min(j0 + R.band, a.ny - 2);
-  const bool out = lane >= 2 && lane <= 60;
-  const int pF = a.pF, c = fidx(a, x);
-  const real* __restrict__ U = a.u;
-  const real* __restrict__ V = a.v;
-  const real* __restrict__ Pi = a.pin;
-  const real* __restrict__ TT = a.T;
-  real u[5], v[5], p[2], T[5];
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    u[k] = U[(j0 - 2 + k) * pF + c];
-    v[k] = V[(j0 - 1 + k) * pF + c];
-    T[k] = TT[(j0 - 2 + k) * pF + c];
-  }
-  p[0] = Pi[j0 * pF + c];
-  p[1] = Pi[(j0 + 1) * pF + c];
-  // v* on the band's south face j0: the window of row j0 - 1
-  real vsouth;
-  {
-    real u1[5], v1[5], p1[2], T1[5];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      u1[k + 1] = u[k];
-      v1[k + 1] = v[k];
-      T1[k + 1] = T[k];
-    }
-    u1[0] = u[0];  // row j0 - 3: not used by v* on face j0
-    v1[0] = V[(j0 - 2) * pF + c];
-    T1[0] = T[0];  // row j0 - 3: not used
-    p1[0] = Pi[(j0 - 1) * pF + c];
-    p1[1] = p[0];
-    vsouth = vstar_val<real, CONV>(a, WinV<real>{u1, v1, p1, T1});
-  }
-  for (int j = j0; j < j1; ++j) {
-    // the next row's inputs, requested before this row's arithmetic
-    const bool more = j + 1 < j1;
-    real un = real(0), vn = real(0), pn = real(0), Tn = real(0);
-    if (more) {
-      un = U[(j + 3) * pF + c];
-      vn = V[(j + 4) * pF + c];
-      pn = Pi[(j + 2) * pF + c];
-      Tn = TT[(j + 3) * pF + c];
-    }
-    const real us = ustar_val<real, CONV>(a, WinU<real>{u, v, p, T});
-    const real vnorth = vstar_val<real, CONV>(a, WinV<real>{u, v, p, T});
-    const real ue = __shfl_down(us, 1, 64);
-    real pnew, Tnew;
-    press_energy_val<real, CONV, true>(a, WinE<real>{us, ue, vsouth, vnorth, T}, x, j, p[0],
-                                       T[2], pnew, Tnew);
-    if (out) {
-      const int o = j * pF + c;
-      a.us[o] = us;
-      a.vs[o + pF] = vnorth;
-      a.p[o] = pnew;
-      a.Tn[o] = Tnew;
-    }
-    if (!more) break;
-    vsouth = vnorth;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      u[k] = u[k + 1];
-      v[k] = v[k + 1];
-      T[k] = T[k + 1];
-    }
-    u[4] = un;
-    v[4] = vn;
-    T[4] = Tn;
-    p[0] = p[1];
-    p[1] = pn;
-  }
+__device__ __forceinline__ real face_u(const SplitArgs<real>& a, int x, int j) {
+  if (x == a.c0) return a.u[j * a.pF + fidx(a, x)];
+  if (x == a.nx) return real(0);
+  return ustar_val<real, CONV>(a, GenAcc<real>{a, x, j});
+}
+template <typename real, int CONV>
+__device__ __forceinline__ real face_v(const SplitArgs<real>& a, int x, int jf) {
+  if (jf == 0 || jf == a.ny) return real(0);
+  return vstar_val<real, CONV>(a, GenAcc<real>{a, x, jf});
 }
 
-// the frame around the fused region: per-face momentum and per-cell
-// pressure and energy, one thread per face or cell position of the frame,
-// the faces and cells the fused march forms skipped.  Positions: rows
-// 0 .. 2 and ny - 2 .. ny over every face column c0 .. nx (all rows when
-// ny < 5), then rows 3 .. ny - 3 over the columns outside [X0, X1].
+// frame position idx: rows 0 .. 2 and ny - 2 .. ny over every face column
+// c0 .. nx (all rows when ny < 5), then rows 3 .. ny - 3 over the columns
+// outside [X0, X1]
 template <typename real>
 __device__ __forceinline__ void frame_xy(const SplitArgs<real>& a, const FvRegion& R, int idx,
                                          int& x, int& j) {
@@ -604,26 +537,145 @@ __device__ __forceinline__ void frame_xy(const SplitArgs<real>& a, const FvRegio
 }
 
 template <typename real, int CONV>
-__global__ __launch_bounds__(256) void k_dd_momentum_frame(SplitArgs<real> a, FvRegion R) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void fv_frame(const SplitArgs<real>& a, const FvRegion& R, int idx) {
   if (idx >= R.nframe) return;
   int x, j;
   frame_xy(a, R, idx, x, j);
   const bool incols = x >= R.X0 && x <= R.X1;
-  const bool do_u = !(incols && j >= 2 && j <= a.ny - 3);
-  const bool do_v = !(incols && j >= 3 && j <= a.ny - 2);
-  momentum_at<real, CONV, false>(a, GenAcc<real>{a, x, j}, x, j, do_u, do_v);
+  const bool cell = x < a.nx && j < a.ny && !(incols && j >= 2 && j <= a.ny - 3);
+  const bool do_u = j < a.ny && !(incols && j >= 2 && j <= a.ny - 3);
+  const bool do_v = x < a.nx && !(incols && j >= 3 && j <= a.ny - 2);
+  const int o = j * a.pF + fidx(a, x);
+  real uw = real(0), vsd = real(0);
+  if (do_u) {
+    uw = face_u<real, CONV>(a, x, j);
+    a.us[o] = uw;
+  }
+  if (x < a.nx) {
+    vsd = face_v<real, CONV>(a, x, j);
+    if (do_v) a.vs[o] = vsd;
+  }
+  if (!cell) return;
+  const real ue = face_u<real, CONV>(a, x + 1, j);
+  const real vn = face_v<real, CONV>(a, x, j + 1);
+  real pn, Tn;
+  press_energy_val<real, CONV, false>(a, FrameE<real>{uw, ue, vsd, vn, GenAcc<real>{a, x, j}}, x,
+                                      j, a.pin[o], a.T[o], pn, Tn);
+  a.p[o] = pn;
+  a.Tn[o] = Tn;
 }
 
 template <typename real, int CONV>
-__global__ __launch_bounds__(256) void k_dd_press_energy_frame(SplitArgs<real> a, FvRegion R) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= R.nframe) return;
-  int x, j;
-  frame_xy(a, R, idx, x, j);
-  if (x >= a.nx || j >= a.ny) return;                               // face-only positions
-  if (x >= R.X0 && x <= R.X1 && j >= 2 && j <= a.ny - 3) return;  // the fused march's cell
-  press_energy_at<real, CONV, false>(a, GenAcc<real>{a, x, j}, x, j);
+__global__ __launch_bounds__(256) void k_dd_fv(SplitArgs<real> a, FvRegion R) {
+  // blocks renumbered so that each XCD works on a contiguous range
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int per = nb / 8, rem = nb % 8, xcd = b % 8;
+  const int lb = xcd * per + (xcd < rem ? xcd : rem) + b / 8;
+  if (lb < R.nfrb) {
+    fv_frame<real, CONV>(a, R, lb * 256 + (int)threadIdx.x);
+    return;
+  }
+  const int wave = __builtin_amdgcn_readfirstlane((lb - R.nfrb) * 4 + (int)(threadIdx.x >> 6));
+  if (wave >= R.nwaves) return;
+  const int lane = threadIdx.x & 63;
+  const int ns = R.nst + R.npart;
+  const int strip = wave % ns, bnd = wave / ns;
+  const bool part = strip == R.nst;
+  const int x = (part ? a.nx - 64 : R.xa + kFvOut * strip) + lane;
+  const int j0 = 2 + bnd * R.band;
+  const int j1 = min(j0 + R.band, a.ny - 2);
+  const bool out = lane >= 2 && lane <= 60 && (!part || x > R.xcut);
+  const unsigned bytes = (unsigned)((size_t)(a.ny + 1) * a.pF * sizeof(real));
+  const __amdgpu_buffer_rsrc_t rU = fv_rsrc(a.u, bytes), rV = fv_rsrc(a.v, bytes),
+                               rP = fv_rsrc(a.pin, bytes), rT = fv_rsrc(a.T, bytes);
+  const int vo = fidx(a, x) * (int)sizeof(real), rowb = a.pF * (int)sizeof(real);
+  real u[5], v[5], p[2], T[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    u[k] = fv_load<real>(rU, vo, (j0 - 2 + k) * rowb);
+    v[k] = fv_load<real>(rV, vo, (j0 - 1 + k) * rowb);
+    T[k] = fv_load<real>(rT, vo, (j0 - 2 + k) * rowb);
+  }
+  p[0] = fv_load<real>(rP, vo, j0 * rowb);
+  p[1] = fv_load<real>(rP, vo, (j0 + 1) * rowb);
+  // v* on the band's south face j0: the window of row j0 - 1
+  real vsouth;
+  {
+    real u1[5], v1[5], p1[2], T1[5];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      u1[k + 1] = u[k];
+      v1[k + 1] = v[k];
+      T1[k + 1] = T[k];
+    }
+    u1[0] = u[0];  // row j0 - 3: not used by v* on face j0
+    T1[0] = T[0];  // row j0 - 3: not used
+    v1[0] = fv_load<real>(rV, vo, (j0 - 2) * rowb);
+    p1[0] = fv_load<real>(rP, vo, (j0 - 1) * rowb);
+    p1[1] = p[0];
+    vsouth = vstar_val<real, CONV>(a, WinV<real>{u1, v1, p1, T1});
+  }
+  // every window load has landed (vmcnt 0): the march's loop then starts
+  // with no load of its own in flight
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  const __amdgpu_buffer_rsrc_t rUs = fv_rsrc(a.us, bytes), rVs = fv_rsrc(a.vs, bytes),
+                               rPn = fv_rsrc(a.p, bytes), rTn = fv_rsrc(a.Tn, bytes);
+  // the values the window takes on when it moves up to row r: u row r+2,
+  // v face r+3, p row r+1, T row r+2.  Loads and stores are issued
+  // unconditionally (rows past the band clamped to stored ones, lanes that
+  // own no cell storing to an offset past the buffer's record size, which
+  // the hardware drops), so every trip issues the same memory operations
+  // and the waits for a row's loads count exactly the operations after them.
+  const int rmax = a.ny - 3;
+  auto issue = [&](real (&q)[4], int r) {
+    r = min(r, rmax);
+    q[0] = fv_load<real>(rU, vo, (r + 2) * rowb);
+    q[1] = fv_load<real>(rV, vo, (r + 3) * rowb);
+    q[2] = fv_load<real>(rP, vo, (r + 1) * rowb);
+    q[3] = fv_load<real>(rT, vo, (r + 2) * rowb);
+  };
+  const int vst = out ? vo : (int)0x80000000;
+  auto advance = [&](const real (&q)[4]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      u[k] = u[k + 1];
+      v[k] = v[k + 1];
+      T[k] = T[k + 1];
+    }
+    u[4] = q[0];
+    v[4] = q[1];
+    p[0] = p[1];
+    p[1] = q[2];
+    T[4] = q[3];
+  };
+  auto row = [&](int j) {
+    const real us = ustar_val<real, CONV>(a, WinU<real>{u, v, p, T});
+    const real vnorth = vstar_val<real, CONV>(a, WinV<real>{u, v, p, T});
+    const real ue = __shfl_down(us, 1, 64);
+    real pnew, Tnew;
+    press_energy_val<real, CONV, true>(a, WinE<real>{us, ue, vsouth, vnorth, T}, x, j, p[0],
+                                       T[2], pnew, Tnew);
+    fv_store(us, rUs, vst, j * rowb);
+    fv_store(vnorth, rVs, vst, (j + 1) * rowb);
+    fv_store(pnew, rPn, vst, j * rowb);
+    fv_store(Tnew, rTn, vst, j * rowb);
+    vsouth = vnorth;
+  };
+  // two rows per trip: the loads of both are issued at the top of the trip,
+  // so that each set is in flight over one or two rows of arithmetic and no
+  // load is still in flight across the loop's back edge
+  real qa[4] = {real(0), real(0), real(0), real(0)};
+  real qb[4] = {real(0), real(0), real(0), real(0)};
+  for (int j = j0;; j += 2) {
+    issue(qa, j + 1);
+    issue(qb, j + 2);
+    row(j);
+    if (j + 1 >= j1) break;
+    advance(qa);
+    row(j + 1);
+    if (j + 2 >= j1) break;
+    advance(qb);
+  }
 }
 
 // 4. p_bar: mean new FV pressure over the shared columns; and the net mass
@@ -1363,37 +1415,41 @@ static SplitArgs<real> make_args(const SplitGeom& G, const SplitPtrs<real>& P, c
 }
 
 // Fused region for a band height: strips need the whole 64-lane window
-// inside the stored columns (x0 + 63 <= nx - 1) and at least one row
-// clear of the walls' ghost rules (ny >= 5).
+// inside the stored columns (x0 + 63 <= nx - 1) and at least one row clear
+// of the walls' ghost rules (ny >= 5).
 static FvRegion fv_region(const SplitGeom& G, int band) {
   FvRegion r{};
   r.xa = G.c0 - 1 + (G.fv_only ? 1 : 0);
   const int span = G.nx - 64 - r.xa;
   r.nst = (span < 0 || G.ny < 5) ? 0 : span / kFvOut + 1;
   r.band = band;
-  r.nbands = r.nst ? (G.ny - 4 + band - 1) / band : 0;
   if (r.nst) {
+    r.xcut = r.xa + kFvOut * r.nst + 1;  // east end of the whole strips
+    r.npart = r.xcut < G.nx - 4 ? 1 : 0;
+    r.nbands = (G.ny - 4 + band - 1) / band;
     r.X0 = r.xa + 2;
-    r.X1 = r.xa + kFvOut * r.nst + 1;
+    r.X1 = G.nx - 4;
   } else {
     r.X0 = G.nx + 1;
     r.X1 = G.nx;
   }
+  r.nwaves = (r.nst + r.npart) * r.nbands;
   r.nfc = G.nx - G.c0 + 1;
   r.nbt = G.ny + 1 < 6 ? G.ny + 1 : 6;
   const int nmid = G.ny - 5 > 0 ? G.ny - 5 : 0;
   r.wl = r.X0 - G.c0;
   r.wr = G.nx - r.X1;
   r.nframe = r.nbt * r.nfc + nmid * (r.wl + r.wr);
+  r.nfrb = (r.nframe + 255) / 256;
   return r;
 }
 
-// rows per wave of the fused march: the longest of 16, 8, 4 that still
-// gives the chip 2048 waves (the halo rows cost 4.5 row loads per band)
+// rows per wave of the march: the longest of 16, 8, 4 that still gives the
+// chip 2048 waves (a band's halo costs 4.5 row loads)
 static FvRegion fv_region_auto(const SplitGeom& G) {
   int band = 16;
   FvRegion r = fv_region(G, band);
-  while (band > 4 && r.nst * r.nbands < 2048) {
+  while (band > 4 && r.nwaves < 2048) {
     band /= 2;
     r = fv_region(G, band);
   }
@@ -1402,17 +1458,16 @@ static FvRegion fv_region_auto(const SplitGeom& G) {
 
 template <typename real, int CONV>
 static void launch_fv(const SplitArgs<real>& a, const FvRegion& R, hipStream_t s) {
-  const int nw = R.nst * R.nbands;
-  if (nw > 0) hipLaunchKernelGGL((k_dd_fv<real, CONV>), dim3((nw + 3) / 4), dim3(256), 0, s, a, R);
-  const dim3 gf((R.nframe + 255) / 256);
-  hipLaunchKernelGGL((k_dd_momentum_frame<real, CONV>), gf, dim3(256), 0, s, a, R);
-  hipLaunchKernelGGL((k_dd_press_energy_frame<real, CONV>), gf, dim3(256), 0, s, a, R);
+  const int nb = R.nfrb + (R.nwaves + 3) / 4;
+  hipLaunchKernelGGL((k_dd_fv<real, CONV>), dim3(nb), dim3(256), 0, s, a, R);
 }
 
 template <typename real>
 hipError_t launch_split_step(const SplitGeom& G, const SplitPtrs<real>& P, const SplitParams& S,
                              int cur, int mom_all, hipStream_t s) {
   const SplitArgs<real> a = make_args<real>(G, P, S, cur, mom_all);
+  // the march addresses the FV arrays with 32-bit byte offsets
+  if ((size_t)(G.ny + 1) * G.pF * sizeof(real) >= ((size_t)1 << 31)) return hipErrorInvalidValue;
   const dim3 gl((a.nl + 63) / 64, (G.ny + 3) / 4);
   if (G.lbm_only) {  // one zone kernel per step
     hipLaunchKernelGGL(k_dd_lbm<real>, gl, dim3(256), 0, s, a);
