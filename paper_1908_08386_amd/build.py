@@ -21,9 +21,8 @@ LIB = os.path.join(HERE, "liblbmfvm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["lbmfvm_api.cpp", "k_hybrid.hip", "k_reduce.hip"]
-OPTIONAL = ["k_split.hip", "k_batch.hip", "k_net.hip", "lbmfvm_batch.cpp", "lbmfvm_net.cpp",
-            "lbmfvm_split.cpp", "autotune.cpp"]
+SOURCES = ["lbmfvm_api.cpp", "lbmfvm_batch.cpp", "lbmfvm_net.cpp",
+           "k_hybrid.hip", "k_reduce.hip", "k_split.hip", "k_net.hip"]
 
 # packed FP32 arithmetic is switched off for all device code
 CFLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
@@ -33,9 +32,10 @@ CFLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
 
 
 def sources():
-    out = [s for s in SOURCES]
-    out += [s for s in OPTIONAL if os.path.exists(os.path.join(CSRC, s))]
-    return out
+    missing = [s for s in SOURCES if not os.path.exists(os.path.join(CSRC, s))]
+    if missing:
+        raise FileNotFoundError(f"library sources missing: {missing}")
+    return list(SOURCES)
 
 
 def _compile(src: str) -> str:

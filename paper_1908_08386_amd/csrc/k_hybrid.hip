@@ -45,12 +45,12 @@ __device__ __forceinline__ float fma_<float>(float a, float b, float c) {
 constexpr int kOut = 62;  // output columns per wave (lanes 1..62)
 
 // Minimum waves per SIMD the step kernel is compiled for (register budget):
-// 5 for FP32 (up to 96 VGPRs, room for two rows in flight without spills);
-// FP64 is left its full register file.
-#ifndef LF_STEP_WAVES_F32
-#define LF_STEP_WAVES_F32 5
-#endif
-#define LF_STEP_WAVES(real) (sizeof(real) == 4 ? LF_STEP_WAVES_F32 : 2)
+// for FP32 4 when waves march bands of several rows (up to 128 VGPRs: two
+// rows in flight), 5 when every wave forms a single row (up to 96 VGPRs,
+// nothing to hold ahead; small grids, where all waves are resident at once
+// and the step is the issue time of the slowest); FP64 is left its full
+// register file.
+#define LF_STEP_WAVES(real, ROW1) (sizeof(real) == 4 ? ((ROW1) ? 5 : 4) : 2)
 
 // D2Q9 (Eq 4, Eq 9): 0 rest, 1 E, 2 N, 3 W, 4 S, 5 NE, 6 NW, 7 SW, 8 SE.
 __host__ __device__ constexpr int ex(int q) {
@@ -75,9 +75,9 @@ struct StepArgs {
   real* __restrict__ fout;
   const real* __restrict__ Tin;
   real* __restrict__ Tout;
-  // low words of a compensated (hi + lo) temperature, or null
-  const real* __restrict__ Tlo_in;
-  real* __restrict__ Tlo_out;
+  // low-word codes of a compensated (hi + lo) temperature, or null
+  const tlo_t* __restrict__ Tlo_in;
+  tlo_t* __restrict__ Tlo_out;
   real* __restrict__ mom;
   int plane;  // elements per plane
   int nx, ny, pitch, band, nstrips, nwaves;
@@ -120,6 +120,22 @@ __device__ __forceinline__ void t_update(real hi, real lo, real delta, real& nhi
   nhi = s + l2;
   nlo = l2 - (nhi - s);
 }
+
+// The low word is stored as a signed byte k with lo = k 2^-8 ulp(hi), where
+// ulp(hi) = 2^(e - 24) for hi = m 2^e, 1/2 <= |m| < 1: the pair resolves T to
+// 2^-32 of its binade at 5 bytes per node instead of 8.  The renormalised
+// pair has |lo| <= ulp(hi) / 2, so |k| <= 128 (clamped to 127).  Only FP32
+// runs carry a low word; the FP64 forms exist for the templates.
+__device__ __forceinline__ int lo_encode(float hi, float lo) {
+  const int e = __builtin_amdgcn_frexp_expf(hi);
+  const float k = __builtin_rintf(__builtin_ldexpf(lo, 32 - e));
+  return (int)__builtin_fminf(__builtin_fmaxf(k, -127.0f), 127.0f);
+}
+__device__ __forceinline__ float lo_decode(float hi, int k) {
+  return __builtin_ldexpf((float)k, __builtin_amdgcn_frexp_expf(hi) - 32);
+}
+__device__ __forceinline__ int lo_encode(double, double) { return 0; }
+__device__ __forceinline__ double lo_decode(double, int) { return 0.0; }
 
 // Moments of 9 streamed (shifted) populations.
 template <typename real>
@@ -313,9 +329,9 @@ __device__ void march_general(const StepArgs<real>& a, int lane, int i, int j0, 
   const real uwW = a.uw[0], uwE = a.uw[1], uwS = a.uw[2], uwN = a.uw[3];
   const real* __restrict__ fin = a.fin;
   const real* __restrict__ Tin = a.Tin;
-  // the low words of a compensated T are read from T itself (and ignored)
-  // when absent, which keeps the loads unconditional
-  const real* tlo = a.Tlo_in ? a.Tlo_in : a.Tin;
+  // the low-word codes of a compensated T are read from T itself (and
+  // ignored) when absent, which keeps the loads unconditional
+  const tlo_t* tlo = a.Tlo_in ? a.Tlo_in : (const tlo_t*)a.Tin;
 #define LF_PULL(r, f, d, u, v) \
   gen_pull<real, XP, YP>(fin, nx, ny, P, plane, ic, (r), uwW, uwE, uwS, uwN, f, d, u, v)
 #define LF_T1(r) gen_T<real, YP>(Tin, P, ny, ic, (r), g1W, g1E, TwW, TwE, fixS, fixN, TwS, TwN)
@@ -333,7 +349,7 @@ __device__ void march_general(const StepArgs<real>& a, int lane, int i, int j0, 
   real t2 = LF_T1(j0), t3 = LF_T1(j0 + 1);
   real t4 = LF_T1(j0 + 2);
   real tx2 = LF_T2(j0);
-  real lo = tlo[j0 * P + ic];
+  int lo = tlo[j0 * P + ic];
 
   for (int j = j0; j < j1; ++j) {
     const real tW1 = __shfl_up(t2, 1, 64);
@@ -358,7 +374,7 @@ __device__ void march_general(const StepArgs<real>& a, int lane, int i, int j0, 
     const real Fn = (!YP && j == ny - 1) ? wN : fnn;
     real Tnew, Tlo = real(0);
     if (a.Tlo_in) {
-      t_update(t2, lo, -(Fe - Fw) - (Fn - Fs), Tnew, Tlo);
+      t_update(t2, lo_decode(t2, lo), -(Fe - Fw) - (Fn - Fs), Tnew, Tlo);
     } else {
       Tnew = t2 - (Fe - Fw) - (Fn - Fs);
     }
@@ -366,7 +382,7 @@ __device__ void march_general(const StepArgs<real>& a, int lane, int i, int j0, 
       const int o = j * P + i;
       collide(a, fc, dr_c, ux_c, uy_c, Tnew, [&](int q, real v) { a.fout[q * plane + o] = v; });
       store_node(a, o, Tnew, dr_c, ux_c, uy_c);
-      if (a.Tlo_out) a.Tlo_out[j * P + i] = Tlo;
+      if (a.Tlo_out) a.Tlo_out[j * P + i] = (tlo_t)lo_encode(Tnew, Tlo);
     }
     if (j + 1 == j1) break;
     uy_p = uy_c;
@@ -481,8 +497,12 @@ __device__ void march_interior(const StepArgs<real>& a, int lane, int i, int j0,
   const __amdgpu_buffer_rsrc_t rT = make_rsrc(a.Tin, pbytes);
   const __amdgpu_buffer_rsrc_t wf = make_rsrc(a.fout, fbytes);
   const __amdgpu_buffer_rsrc_t wT = make_rsrc(a.Tout, pbytes);
-  // low words of a compensated T (read from T itself, and ignored, when absent)
-  const __amdgpu_buffer_rsrc_t rL = make_rsrc(a.Tlo_in ? a.Tlo_in : a.Tin, pbytes);
+  // low-word codes of a compensated T, one byte per node (read from T
+  // itself, and ignored, when absent)
+  const __amdgpu_buffer_rsrc_t rL =
+      make_rsrc(a.Tlo_in ? (const void*)a.Tlo_in : (const void*)a.Tin, (unsigned)a.plane);
+  const __amdgpu_buffer_rsrc_t wL =
+      make_rsrc(a.Tlo_out ? (const void*)a.Tlo_out : (const void*)a.Tout, (unsigned)a.plane);
   int sq[9];  // uniform byte offset of direction q's upstream node
 #pragma unroll
   for (int q = 0; q < 9; ++q) sq[q] = (q * a.plane - ey(q) * P - ex(q)) * es;
@@ -539,8 +559,12 @@ __device__ void march_interior(const StepArgs<real>& a, int lane, int i, int j0,
   real t5 = T_row((DIR > 0 ? r5 < a.ny : r5 >= 0) ? r5 : js + 2 * DIR);
   // the column beyond the halo lanes and the low words, one row ahead
   auto tx_row = [&](int r) { return bload<real>(rT, (r * P + i) * es + xoff, 0); };
-  auto lo_row = [&](int r) { return bload<real>(rL, (r * P + i) * es, 0); };
-  real txa = tx_row(js), loa = lo_row(js);
+  // (the column is the per-lane offset, the row a wave-uniform one)
+  auto lo_row = [&](int r) {
+    return (int)(signed char)__builtin_amdgcn_raw_buffer_load_b8(rL, i, r * P, 0);
+  };
+  real txa = tx_row(js);
+  int loa = lo_row(js);
   wall_fix(D);
   wall_fix(A);
   moments(D, d_unused, u_unused, uy_p);
@@ -554,7 +578,8 @@ __device__ void march_interior(const StepArgs<real>& a, int lane, int i, int j0,
     real dr_n, ux_n, uy_n;
     wall_fix(fn);
     moments(fn, dr_n, ux_n, uy_n);
-    const real tx = txa, lo = loa;
+    const real tx = txa;
+    const int lo = loa;
     if (inside(j + DIR)) {
       txa = tx_row(j + DIR);
       loa = lo_row(j + DIR);
@@ -584,7 +609,7 @@ __device__ void march_interior(const StepArgs<real>& a, int lane, int i, int j0,
     const real dFy = DIR > 0 ? Fa - Fb : Fb - Fa;
     real Tnew, Tlo = real(0);
     if (a.Tlo_in) {
-      t_update(t2, lo, -(Fe - Fw) - dFy, Tnew, Tlo);
+      t_update(t2, lo_decode(t2, lo), -(Fe - Fw) - dFy, Tnew, Tlo);
     } else {
       Tnew = t2 - (Fe - Fw) - dFy;
     }
@@ -592,7 +617,9 @@ __device__ void march_interior(const StepArgs<real>& a, int lane, int i, int j0,
       const int vo = (j * P + i) * es;
       collide(a, fc, dr_c, ux_c, uy_c, Tnew,
               [&](int q, real v) { bstore<real>(v, wf, vo, q * a.plane * es); });
-      if (a.Tlo_out) a.Tlo_out[j * P + i] = Tlo;
+      if (a.Tlo_out)
+        __builtin_amdgcn_raw_buffer_store_b8((unsigned char)lo_encode(Tnew, Tlo), wL, i, j * P,
+                                             LF_STORE_AUX);
       bstore<real>(Tnew, wT, vo, 0);
       if (a.mom) {
         const int o = j * P + i;
@@ -624,8 +651,9 @@ __device__ void march_interior(const StepArgs<real>& a, int lane, int i, int j0,
   }
 }
 
-template <typename real, int CONV>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LF_STEP_WAVES(real))))
+// ROW1: every wave forms one row (a.band == 1).
+template <typename real, int CONV, bool ROW1>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LF_STEP_WAVES(real, ROW1))))
 void k_hybrid_step(StepArgs<real> a) {
   // Blocks are dealt round-robin to the 8 XCDs; renumber them so that each
   // XCD works on a contiguous range of strips and bands, which keeps the
@@ -636,13 +664,14 @@ void k_hybrid_step(StepArgs<real> a) {
   // uniform per wave: held in an SGPR, so are the strip, band and row bounds
   const int wave = __builtin_amdgcn_readfirstlane(lb * (blockDim.x >> 6) + (threadIdx.x >> 6));
   if (wave >= a.nwaves) return;
-  const int lane = threadIdx.x & 63;
   const int strip = wave % a.nstrips;
   const int bnd = wave / a.nstrips;
+  const int lane = threadIdx.x & 63;
   const int c0 = strip * kOut;   // first output column
   const int i = c0 + lane - 1;   // this lane's column
-  const int j0 = bnd * a.band;
-  const int j1 = min(j0 + a.band, a.ny);
+  const int band = ROW1 ? 1 : a.band;
+  const int j0 = bnd * band;
+  const int j1 = ROW1 ? j0 + 1 : min(j0 + band, a.ny);
   const bool rows_in = j0 - 1 >= 2 && j1 <= a.ny - 2;
   // strips holding the west / east wall: the wall column an output lane with
   // room for the column beyond it, and no periodic seam
@@ -677,13 +706,15 @@ void k_hybrid_step(StepArgs<real> a) {
 // replayed; the number of live tiles is read from device memory, so the
 // same graph serves a shrinking set of unconverged cavities.
 // The batched kernel is compiled for 4 waves per SIMD (up to 128 VGPRs): with
-// the side-wall marches it needs 108 and would spill at 5.  Measured on the
+// the side-wall marches it needs 120 and would spill at 5.  Measured on the
 // 256-cavity sweep, 1.076 ms per step at 4 waves with the side-wall marches
-// against 1.131 ms at 5 waves with the general march on those strips.
-#define LF_BATCH_WAVES(real) (sizeof(real) == 4 ? 4 : 2)
+// against 1.131 ms at 5 waves with the general march on those strips.  When
+// every live tile is a single row (ROW1: a small live set), nothing is held
+// ahead and the kernel fits 5 waves.
+#define LF_BATCH_WAVES(real, ROW1) (sizeof(real) == 4 ? ((ROW1) ? 5 : 4) : 2)
 
-template <typename real, int CONV>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LF_BATCH_WAVES(real))))
+template <typename real, int CONV, bool ROW1>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LF_BATCH_WAVES(real, ROW1))))
 void k_batch_step(const TileDesc* __restrict__ tiles, const int* __restrict__ ntiles,
                   const CavDesc<real>* __restrict__ cavs, int parity, int write_mom) {
   // The grid is sized for the largest tile table (band 1, all cavities
@@ -737,7 +768,7 @@ void k_batch_step(const TileDesc* __restrict__ tiles, const int* __restrict__ nt
   const int lane = threadIdx.x & 63;
   const int c0 = t.strip * kOut;
   const int i = c0 + lane - 1;
-  const int j0 = t.j0, j1 = t.j1;
+  const int j0 = t.j0, j1 = ROW1 ? t.j0 + 1 : t.j1;
   const bool rows_in = j0 - 1 >= 2 && j1 <= a.ny - 2;
   const bool interior = c0 - 1 >= 1 && c0 + kOut <= a.nx - 2 && rows_in;
   // strips holding the west / east wall, as in the single-cavity kernel
@@ -826,7 +857,7 @@ __global__ __launch_bounds__(256) void k_init(int nx, int ny, int pitch, int pla
                                               real* __restrict__ f, real* __restrict__ T,
                                               real* __restrict__ mom,
                                               real* __restrict__ snap,
-                                              real* __restrict__ Tlo) {
+                                              tlo_t* __restrict__ Tlo) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= nx) return;
@@ -840,7 +871,7 @@ __global__ __launch_bounds__(256) void k_init(int nx, int ny, int pitch, int pla
     f[q * plane + o] = real(wq<double>(q) * (3.0 * eu + 4.5 * eu * eu - usq));
   }
   T[o] = real(t);
-  if (Tlo) Tlo[o] = real(t - (double)real(t));
+  if (Tlo) Tlo[o] = (tlo_t)lo_encode(real(t), real(t - (double)real(t)));
   mom[o] = real(1);
   mom[plane + o] = real(u);
   mom[2 * plane + o] = real(v);
@@ -854,7 +885,7 @@ __global__ __launch_bounds__(256) void k_init(int nx, int ny, int pitch, int pla
 template <typename real>
 hipError_t launch_hybrid_step(const Grid& g, const WallSet& w, const HybridParams& p,
                               const real* fin, real* fout, const real* Tin, real* Tout,
-                              const real* Tlo_in, real* Tlo_out, real* mom, int band,
+                              const tlo_t* Tlo_in, tlo_t* Tlo_out, real* mom, int band,
                               hipStream_t s) {
   StepArgs<real> a;
   a.Tlo_in = Tlo_in;
@@ -887,18 +918,27 @@ hipError_t launch_hybrid_step(const Grid& g, const WallSet& w, const HybridParam
   a.gx = real(p.gx);
   a.gy = real(p.gy);
   const int blocks = (a.nwaves + 3) / 4;
-  if (p.conv == 1)
-    hipLaunchKernelGGL((k_hybrid_step<real, 1>), dim3(blocks), dim3(256), 0, s, a);
-  else if (p.conv == 2)
-    hipLaunchKernelGGL((k_hybrid_step<real, 2>), dim3(blocks), dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_hybrid_step<real, 0>), dim3(blocks), dim3(256), 0, s, a);
+  if (a.band == 1) {
+    if (p.conv == 1)
+      hipLaunchKernelGGL((k_hybrid_step<real, 1, true>), dim3(blocks), dim3(256), 0, s, a);
+    else if (p.conv == 2)
+      hipLaunchKernelGGL((k_hybrid_step<real, 2, true>), dim3(blocks), dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_hybrid_step<real, 0, true>), dim3(blocks), dim3(256), 0, s, a);
+  } else {
+    if (p.conv == 1)
+      hipLaunchKernelGGL((k_hybrid_step<real, 1, false>), dim3(blocks), dim3(256), 0, s, a);
+    else if (p.conv == 2)
+      hipLaunchKernelGGL((k_hybrid_step<real, 2, false>), dim3(blocks), dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_hybrid_step<real, 0, false>), dim3(blocks), dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 
 template <typename real>
 hipError_t launch_init(const Grid& g, const double* T0, const double* u0, const double* v0,
-                       real* f, real* T, real* mom, real* snap, real* Tlo, hipStream_t s) {
+                       real* f, real* T, real* mom, real* snap, tlo_t* Tlo, hipStream_t s) {
   dim3 grid((g.nx + 255) / 256, g.ny);
   hipLaunchKernelGGL(k_init<real>, grid, dim3(256), 0, s, g.nx, g.ny, g.pitch,
                      (int)g.plane, T0, u0, v0, f, T, mom, snap, Tlo);
@@ -908,18 +948,22 @@ hipError_t launch_init(const Grid& g, const double* T0, const double* u0, const 
 template <typename real>
 hipError_t launch_batch_step(const TileDesc* tiles, const int* ntiles, int max_tiles,
                              const CavDesc<real>* cavs, int parity, int write_mom, int conv,
-                             hipStream_t s) {
+                             int row1, hipStream_t s) {
   const int blocks = (max_tiles + 3) / 4;
   if (blocks < 1) return hipSuccess;
-  if (conv == 1)
-    hipLaunchKernelGGL((k_batch_step<real, 1>), dim3(blocks), dim3(256), 0, s, tiles, ntiles,
-                       cavs, parity, write_mom);
-  else if (conv == 2)
-    hipLaunchKernelGGL((k_batch_step<real, 2>), dim3(blocks), dim3(256), 0, s, tiles, ntiles,
-                       cavs, parity, write_mom);
-  else
-    hipLaunchKernelGGL((k_batch_step<real, 0>), dim3(blocks), dim3(256), 0, s, tiles, ntiles,
-                       cavs, parity, write_mom);
+#define LF_BATCH_LAUNCH(C, R1)                                                                \
+  hipLaunchKernelGGL((k_batch_step<real, C, R1>), dim3(blocks), dim3(256), 0, s, tiles, ntiles, \
+                     cavs, parity, write_mom)
+  if (row1) {
+    if (conv == 1) LF_BATCH_LAUNCH(1, true);
+    else if (conv == 2) LF_BATCH_LAUNCH(2, true);
+    else LF_BATCH_LAUNCH(0, true);
+  } else {
+    if (conv == 1) LF_BATCH_LAUNCH(1, false);
+    else if (conv == 2) LF_BATCH_LAUNCH(2, false);
+    else LF_BATCH_LAUNCH(0, false);
+  }
+#undef LF_BATCH_LAUNCH
   return hipGetLastError();
 }
 
@@ -936,9 +980,11 @@ hipError_t launch_batch_residual(const ResidTile* rt, const int* nrt, int max_rt
 }
 
 template hipError_t launch_batch_step<float>(const TileDesc*, const int*, int,
-                                             const CavDesc<float>*, int, int, int, hipStream_t);
+                                             const CavDesc<float>*, int, int, int, int,
+                                             hipStream_t);
 template hipError_t launch_batch_step<double>(const TileDesc*, const int*, int,
-                                              const CavDesc<double>*, int, int, int, hipStream_t);
+                                              const CavDesc<double>*, int, int, int, int,
+                                              hipStream_t);
 template hipError_t launch_batch_residual<float>(const ResidTile*, const int*, int, const FoldDesc*,
                                                  const int*, int, const CavDesc<float>*, double*,
                                                  double*, hipStream_t);
@@ -948,13 +994,13 @@ template hipError_t launch_batch_residual<double>(const ResidTile*, const int*, 
                                                   hipStream_t);
 template hipError_t launch_hybrid_step<float>(const Grid&, const WallSet&, const HybridParams&,
                                               const float*, float*, const float*, float*,
-                                              const float*, float*, float*, int, hipStream_t);
+                                              const tlo_t*, tlo_t*, float*, int, hipStream_t);
 template hipError_t launch_hybrid_step<double>(const Grid&, const WallSet&, const HybridParams&,
                                                const double*, double*, const double*, double*,
-                                               const double*, double*, double*, int, hipStream_t);
+                                               const tlo_t*, tlo_t*, double*, int, hipStream_t);
 template hipError_t launch_init<float>(const Grid&, const double*, const double*, const double*,
-                                       float*, float*, float*, float*, float*, hipStream_t);
+                                       float*, float*, float*, float*, tlo_t*, hipStream_t);
 template hipError_t launch_init<double>(const Grid&, const double*, const double*, const double*,
-                                        double*, double*, double*, double*, double*, hipStream_t);
+                                        double*, double*, double*, double*, tlo_t*, hipStream_t);
 
 }  // namespace lf

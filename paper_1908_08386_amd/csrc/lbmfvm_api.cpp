@@ -90,7 +90,10 @@ static void layout_split(lf_case* c) {
   c->off_sp[0] = o; o += pbF;
   c->off_sp[1] = o; o += pbF;
   // interface scalars, then two sums per 256-row block of the ghost kernel
-  c->off_siface = o; o += align_up((size_t)(8 + 2 * ((G.ny + 1 + 255) / 256)) * sizeof(double), 256);
+  // interface scalars, then per 256 rows two ghost sums of each parity and
+  // two p_bar sums
+  c->off_siface = o;
+  o += align_up((size_t)(8 + 6 * ((G.ny + 1 + 255) / 256)) * sizeof(double), 256);
   for (int k = 0; k < 10; ++k) {
     c->off_gs2[k] = o;
     if (G.gs2) o += align_up((size_t)G.pC * G.NYc * c->es, 256);
@@ -286,9 +289,10 @@ static void layout(lf_case* c) {
   c->off_mom = o; o += 3 * pb;
   c->off_snap = o; o += 3 * pb;
   c->off_Tlo[0] = c->off_Tlo[1] = 0;
-  if (c->tcomp) {
-    c->off_Tlo[0] = o; o += pb;
-    c->off_Tlo[1] = o; o += pb;
+  if (c->tcomp) {  // one byte per node and plane
+    const size_t pl = align_up((size_t)g.plane, 256);
+    c->off_Tlo[0] = o; o += pl;
+    c->off_Tlo[1] = o; o += pl;
   }
   c->off_part = o; o += align_up((size_t)c->nblk * 8 * sizeof(double), 256);
   c->off_out = o; o += 256 * sizeof(double);
@@ -633,7 +637,7 @@ lf_status lf_case_init(lf_case* c, const double* T0, const double* u0, const dou
     HIP_TRY(lf::launch_init<float>(c->g, dT, du, dv, fptr<float>(c, c->off_f[0]),
                                    fptr<float>(c, c->off_T[0]), fptr<float>(c, c->off_mom),
                                    fptr<float>(c, c->off_snap),
-                                   c->tcomp ? fptr<float>(c, c->off_Tlo[0]) : nullptr, s));
+                                   c->tcomp ? (lf::tlo_t*)(c->ws + c->off_Tlo[0]) : nullptr, s));
   } else {
     HIP_TRY(lf::launch_init<double>(c->g, dT, du, dv, fptr<double>(c, c->off_f[0]),
                                     fptr<double>(c, c->off_T[0]), fptr<double>(c, c->off_mom),
@@ -648,14 +652,12 @@ lf_status lf_case_init(lf_case* c, const double* T0, const double* u0, const dou
 
 static int auto_band(const lf_case* c) {
   if (c->ctx->band > 0) return c->ctx->band;
-  // Rows per wave: short marches keep many waves in flight, long ones
-  // re-pull fewer halo rows.  Measured on MI355X: 4 rows is best once the
-  // grid yields >= 8192 waves (e.g. 2048^2 and up), otherwise 2, then 1
-  // (512^2 is latency-bound and wants the most waves).
-  const long long strips = (c->g.nx + 61) / 62;
-  for (int band = 4; band > 1; band /= 2)
-    if (strips * ((c->g.ny + band - 1) / band) >= 8192) return band;
-  return 1;
+  // Rows per wave: single rows run the step kernel's 5-wave form (nothing
+  // held ahead) and keep the most waves in flight; bands of 4 rows re-pull
+  // fewer halo rows.  Measured on MI355X (us per step, band 1 / 2 / 4):
+  // 768^2 11.4 / 13.0 / -, 1024^2 17.0 / 19.5 / -, 1536^2 38.8 / 38.2 / 37.3,
+  // 2048^2 100.3 / 88.7 / 86.7, 4096^2 - / 359 / 327 (8 rows: 334).
+  return lf_rows_per_wave((long long)((c->g.nx + 61) / 62) * c->g.ny);
 }
 
 }  // extern "C"
@@ -670,8 +672,8 @@ static lf_status step_impl(lf_case* c, int64_t n) {
     HIP_TRY(lf::launch_hybrid_step<real>(
         c->g, c->w, c->p, fptr<real>(c, c->off_f[a]), fptr<real>(c, c->off_f[b]),
         fptr<real>(c, c->off_T[a]), fptr<real>(c, c->off_T[b]),
-        c->tcomp ? fptr<real>(c, c->off_Tlo[a]) : nullptr,
-        c->tcomp ? fptr<real>(c, c->off_Tlo[b]) : nullptr, mom, band, s));
+        c->tcomp ? (lf::tlo_t*)(c->ws + c->off_Tlo[a]) : nullptr,
+        c->tcomp ? (lf::tlo_t*)(c->ws + c->off_Tlo[b]) : nullptr, mom, band, s));
     c->cur = b;
   }
   c->steps += n;

@@ -75,8 +75,9 @@ struct lf_batch {
   std::vector<lf::FoldDesc> folds;
   int counts[3];
   std::vector<unsigned char> cavdesc;
+  int row1;  // every live tile is a single row (the step kernel's 5-wave form)
   hipGraphExec_t gexec;
-  int graph_K;
+  int graph_K, graph_row1;
   bool inited;
 };
 
@@ -96,9 +97,10 @@ static void batch_layout(lf_batch* b) {
     c.off_mom = o; o += 3 * pb;
     c.off_snap = o; o += 3 * pb;
     c.off_Tlo[0] = c.off_Tlo[1] = 0;
-    if (b->tcomp) {
-      c.off_Tlo[0] = o; o += pb;
-      c.off_Tlo[1] = o; o += pb;
+    if (b->tcomp) {  // one byte per node and plane
+      const size_t pl = lf_align_up((size_t)c.plane, 256);
+      c.off_Tlo[0] = o; o += pl;
+      c.off_Tlo[1] = o; o += pl;
     }
   }
   b->max_tiles = 0;
@@ -136,8 +138,8 @@ static void fill_desc(lf_batch* b) {
     d[k].f[1] = (real*)(b->ws + c.off_f[1]);
     d[k].T[0] = (real*)(b->ws + c.off_T[0]);
     d[k].T[1] = (real*)(b->ws + c.off_T[1]);
-    d[k].Tlo[0] = b->tcomp ? (real*)(b->ws + c.off_Tlo[0]) : nullptr;
-    d[k].Tlo[1] = b->tcomp ? (real*)(b->ws + c.off_Tlo[1]) : nullptr;
+    d[k].Tlo[0] = b->tcomp ? (lf::tlo_t*)(b->ws + c.off_Tlo[0]) : nullptr;
+    d[k].Tlo[1] = b->tcomp ? (lf::tlo_t*)(b->ws + c.off_Tlo[1]) : nullptr;
     d[k].mom = (real*)(b->ws + c.off_mom);
     d[k].snap = (real*)(b->ws + c.off_snap);
     d[k].nx = c.nx;
@@ -158,20 +160,16 @@ static void fill_desc(lf_batch* b) {
 }
 
 // rebuild and upload the live tables and the descriptors
-// Rows per wave tile for the cavities whose band is chosen by load: 4 while
-// the live set yields >= 8192 tiles at 4 rows (enough waves to keep every
-// CU's memory pipes busy), else 2 if that reaches it, else 1, so that a
-// small live set (a single 512^2 cavity, or the last unconverged cavities of
-// a sweep) still spreads over the whole chip.  Measured: one 512^2 cavity
-// 14.1 -> 9.7 us per step (band 4 -> 1), the full sweep unchanged.
+// Rows per wave tile for the cavities whose band is chosen by load: the
+// single-cavity rule (lf_rows_per_wave) applied to the live set's rows, so
+// that a small live set (a single 512^2 cavity, or the last unconverged
+// cavities of a sweep) runs single rows spread over the whole chip and the
+// full sweep bands of 4.
 static int load_band(const lf_batch* b) {
-  long long w4 = 0, w2 = 0;
+  long long w1 = 0;
   for (const auto& c : b->cav)
-    if (c.active && c.band == 0) {
-      w4 += tiles_of(c, 4);
-      w2 += tiles_of(c, 2);
-    }
-  return w4 >= 8192 ? 4 : w2 >= 8192 ? 2 : 1;
+    if (c.active && c.band == 0) w1 += tiles_of(c, 1);
+  return lf_rows_per_wave(w1);
 }
 
 static lf_status upload_tables(lf_batch* b) {
@@ -210,6 +208,9 @@ static lf_status upload_tables(lf_batch* b) {
     b->folds.push_back(f);
   }
   if ((int)b->tiles.size() > b->max_tiles) return lf_fail(LF_EINVAL, "tile table overflow");
+  b->row1 = 1;
+  for (const auto& t : b->tiles)
+    if (t.j1 - t.j0 != 1) b->row1 = 0;
   b->counts[0] = (int)b->tiles.size();
   b->counts[1] = (int)b->rts.size();
   b->counts[2] = (int)b->folds.size();
@@ -245,7 +246,7 @@ static hipError_t enqueue_steps(lf_batch* b, int64_t k0, int64_t n, bool write_m
     hipError_t e = lf::launch_batch_step<real>(
         (const lf::TileDesc*)(b->ws + b->off_tiles), (const int*)(b->ws + b->off_ntiles),
         b->max_tiles, d, (int)((k0 + k) & 1), (write_mom_last && k == n - 1) ? 1 : 0, 0,
-        b->ctx->stream);
+        b->row1, b->ctx->stream);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -274,9 +275,10 @@ static void drop_graph(lf_batch* b) {
   b->graph_K = 0;
 }
 
-// K steps (K even) followed by the batched residual, captured once
+// K steps (K even) followed by the batched residual, captured once per K and
+// per form of the step kernel
 static lf_status ensure_graph(lf_batch* b, int K) {
-  if (b->gexec && b->graph_K == K) return LF_OK;
+  if (b->gexec && b->graph_K == K && b->graph_row1 == b->row1) return LF_OK;
   drop_graph(b);
   hipStream_t s = b->ctx->stream;
   LF_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -295,6 +297,7 @@ static lf_status ensure_graph(lf_batch* b, int K) {
     return lf_fail(LF_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
   }
   b->graph_K = K;
+  b->graph_row1 = b->row1;
   return LF_OK;
 }
 
@@ -439,7 +442,7 @@ static lf_status init_impl(lf_batch* b, const double* const* T0, const double* c
       LF_HIP_TRY(lf::launch_init<float>(g, dT, du, dv, (float*)(b->ws + c.off_f[0]),
                                         (float*)(b->ws + c.off_T[0]), (float*)(b->ws + c.off_mom),
                                         (float*)(b->ws + c.off_snap),
-                                        b->tcomp ? (float*)(b->ws + c.off_Tlo[0]) : nullptr, s));
+                                        b->tcomp ? (lf::tlo_t*)(b->ws + c.off_Tlo[0]) : nullptr, s));
     else
       LF_HIP_TRY(lf::launch_init<double>(g, dT, du, dv, (double*)(b->ws + c.off_f[0]),
                                          (double*)(b->ws + c.off_T[0]),
@@ -560,6 +563,9 @@ lf_status lf_batch_run_to_steady(lf_batch* b, double tol, int check_every, int64
     }
     if (changed) {
       st = upload_tables(b);
+      if (st != LF_OK) return st;
+      // the live set's rows per tile may have changed the step kernel's form
+      st = ensure_graph(b, check_every);
       if (st != LF_OK) return st;
     }
   }

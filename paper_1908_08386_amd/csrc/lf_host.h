@@ -20,6 +20,15 @@ lf_status lf_fail(lf_status st, const char* fmt, ...);
 
 static inline size_t lf_align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Rows per wave of the Mode H step for a grid (or live set) that yields
+// `row_waves` waves at one row per wave: single rows (the step kernel's
+// 5-wave form) up to three waves per wave slot of the chip (256 CUs x 4
+// SIMDs x 8 slots), else bands of 4 rows (measured on MI355X: 1024^2 runs
+// best in single rows, 1536^2 and up in bands of 4).
+static inline int lf_rows_per_wave(long long row_waves) {
+  return row_waves <= 24576 ? 1 : 4;
+}
+
 // lattice parameters from Ra, Pr, U_char (0 = default rule), T_ref (NaN = 0)
 lf_status lf_derive_params(const lf_physics* ph, int ny, int split, double out[8]);
 

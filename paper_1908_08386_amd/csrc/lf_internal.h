@@ -7,6 +7,10 @@
 
 namespace lf {
 
+// Low word of a compensated FP32 temperature T = hi + lo, stored as a signed
+// byte: lo in units of 2^-8 ulp(hi), one byte per node and plane.
+typedef signed char tlo_t;
+
 // Wall description as the kernels see it (sides W, E, S, N).
 struct WallSet {
   int xper, yper;     // periodic along x / y
@@ -43,7 +47,7 @@ template <typename real>
 struct CavDesc {
   real* f[2];
   real* T[2];
-  real* Tlo[2];  // compensated temperature low words, or null
+  tlo_t* Tlo[2];  // compensated temperature low words (codes), or null
   real* mom;   // rho, u, v planes
   real* snap;  // residual snapshot u, v, T planes
   int nx, ny, pitch, plane;
@@ -63,9 +67,10 @@ struct FoldDesc {
 };
 
 template <typename real>
+// row1: every live tile is a single row (j1 = j0 + 1)
 hipError_t launch_batch_step(const TileDesc* tiles, const int* ntiles, int max_tiles,
                              const CavDesc<real>* cavs, int parity, int write_mom, int conv,
-                             hipStream_t s);
+                             int row1, hipStream_t s);
 // residual sums per live cavity into out[cav * 8 + 0 .. 6]
 template <typename real>
 hipError_t launch_batch_residual(const ResidTile* rt, const int* nrt, int max_rt,
@@ -76,21 +81,22 @@ hipError_t launch_batch_residual(const ResidTile* rt, const int* nrt, int max_rt
 // One fused Mode H step: pull-stream + bounce-back + moments + explicit FV
 // energy update + BGK collision with buoyancy.  f planes are stored shifted
 // (f - w_q).  mom (rho, u, v planes) is written only when non-null.
-// Tlo_in / Tlo_out: low words of a compensated temperature (or null).
+// Tlo_in / Tlo_out: low-word codes of a compensated temperature (or null;
+// FP32 only).
 template <typename real>
 hipError_t launch_hybrid_step(const Grid& g, const WallSet& w,
                               const HybridParams& p, const real* fin,
                               real* fout, const real* Tin, real* Tout,
-                              const real* Tlo_in, real* Tlo_out,
+                              const tlo_t* Tlo_in, tlo_t* Tlo_out,
                               real* mom, int band, hipStream_t s);
 
 // f = f_eq(1, u0) - w, T = T0, mom = (1, u0, v0), snapshots = (u0, v0, T0)
 // from dense double staging arrays (u0 / v0 may be null for zero).
-// Tlo (or null) receives T0 - T in the case precision.
+// Tlo (or null) receives the code of T0 - T (FP32 only).
 template <typename real>
 hipError_t launch_init(const Grid& g, const double* T0, const double* u0,
                        const double* v0, real* f, real* T, real* mom,
-                       real* snap, real* Tlo, hipStream_t s);
+                       real* snap, tlo_t* Tlo, hipStream_t s);
 
 // Residual partial sums: per block six FP64 sums
 // {sum (u-us)^2, sum u^2, sum (v-vs)^2, sum v^2, sum (T-Ts)^2, sum T^2}
@@ -153,8 +159,9 @@ struct SplitPtrs {
   real* v[2];   // y-faces, (ny + 1) rows * pF
   real* T[2];   // centres
   real* p[2];   // centres (ping-pong: each FV step reads one and writes the other)
-  double* iface;  // [0] rho0, [1] p_bar, [2] LBM zone mass minus its value at
-                  // init (carried across steps), from [8] two sums per 256 rows
+  double* iface;  // interface scalars (the LBM zone's mass change since init
+                  // and its running sum), from [8] per 256 rows the ghost sums
+                  // of both step parities and the p_bar sums
   // grid setting 2, NYc rows * pC each: T (iterate A), T (iterate B),
   // a_P, a_W, a_E, a_S, a_N, b, and the Thomas sweep's c', r'
   real* gc[10];

@@ -102,7 +102,7 @@ def test_batch_run_to_steady_fp64_matches_oracle(lf, ctx):
 
 
 def test_batch_run_to_steady_fp32_sweep_sample(lf, ctx):
-    """Eight cavities of the sweep distribution, capped at 96 rows, FP32:
+    """Eight cavities of the sweep distribution, capped at 64 rows, FP32:
     each stops by the tolerance or the FP32 floor rule, with Nu within 1e-4
     of the FP64 oracle's steady value."""
     oracle.set_threads(8)
