@@ -173,6 +173,34 @@ def time_to_steady(lf, ctx, n, T0, heldout):
     return res
 
 
+def split_closures(lf, ctx, m, out):
+    """The m x m divided cavity with either closure, timed on the library's
+    stream (HIP events around 200 steps); adds split_point and
+    split_fd_point to out."""
+    from synth_inputs import SEED_C2, perturbation
+    # the split cavity with either closure (config: LBM west half, FV east
+    # half); algorithmic bytes: LBM half 112 B/node (9 f + 5 g, read +
+    # write), FV half 32 B/cell (u, v, p, T read + write): 72 B on average
+    for key, iface, name in (("split_point", lf.IFACE_NEQ_EXTRAP, "non-equilibrium "
+                              "extrapolation"),
+                             ("split_fd_point", lf.IFACE_FD_GRADIENT, "finite-difference "
+                              "velocity gradients")):
+        sp = lf.Case(ctx, m, m, "f32", mode=lf.MODE_SPLIT, iface=iface).set_physics(1e6, 0.71)
+        sp.set_cavity_walls().init(perturbation(m, m, SEED_C2))
+        sp.step(10)
+        a_ms, _, _ = sp.profile_steps(200)
+        ach = 72.0 * m * m / (a_ms * 1e-3) / 1e9
+        out[key] = {"workload": f"{m}x{m} split cavity (LBM west half, FV east half), "
+                                f"Ra 1e6, Pr 0.71, FP32, interface by {name}",
+                    "ms_per_step": round(a_ms, 5),
+                    "mlups": round(m * m / (a_ms * 1e-3) / 1e6, 1),
+                    "achieved_GBs_at_72B": round(ach, 1),
+                    "frac_of_8TBs": round(ach / HBM_PEAK_GBS, 4),
+                    "U_char": sp.params()["U_char"]}
+        sp.close()
+        del sp
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,6 +212,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--oracle-timing", action="store_true",
                     help="only time the FP64 oracle on this host (one thread and all threads)")
+    ap.add_argument("--split-only", action="store_true",
+                    help="time only the divided cavity (both closures) at --split-point")
     ap.add_argument("--headline-only", action="store_true",
                     help="time the headline workload only (for profiler runs)")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -243,6 +273,12 @@ def main():
             torch.cuda.synchronize()
             c.close()
         print(json.dumps({"traffic_probe": "done"}), flush=True)
+        return
+
+    if args.split_only:
+        out = {"workload": "divided cavity only"}
+        split_closures(lf, ctx, args.split_point or 4096, out)
+        print(json.dumps(out), flush=True)
         return
 
     # ---- headline: the batched sweep, every cavity live ----------------------
@@ -345,27 +381,7 @@ def main():
 
     if args.split_point:
         m = args.split_point
-        # the split cavity with either closure (config: LBM west half, FV east
-        # half); algorithmic bytes: LBM half 112 B/node (9 f + 5 g, read +
-        # write), FV half 32 B/cell (u, v, p, T read + write): 72 B on average
-        for key, iface, name in (("split_point", lf.IFACE_NEQ_EXTRAP, "non-equilibrium "
-                                  "extrapolation"),
-                                 ("split_fd_point", lf.IFACE_FD_GRADIENT, "finite-difference "
-                                  "velocity gradients")):
-            sp = lf.Case(ctx, m, m, "f32", mode=lf.MODE_SPLIT, iface=iface).set_physics(1e6, 0.71)
-            sp.set_cavity_walls().init(perturbation(m, m, SEED_C2))
-            sp.step(10)
-            a_ms, _, _ = sp.profile_steps(200)
-            ach = 72.0 * m * m / (a_ms * 1e-3) / 1e9
-            out[key] = {"workload": f"{m}x{m} split cavity (LBM west half, FV east half), "
-                                    f"Ra 1e6, Pr 0.71, FP32, interface by {name}",
-                        "ms_per_step": round(a_ms, 5),
-                        "mlups": round(m * m / (a_ms * 1e-3) / 1e6, 1),
-                        "achieved_GBs_at_72B": round(ach, 1),
-                        "frac_of_8TBs": round(ach / HBM_PEAK_GBS, 4),
-                        "U_char": sp.params()["U_char"]}
-            sp.close()
-            del sp
+        split_closures(lf, ctx, m, out)
         # the horizontal division of the same cavity (Fig. 17b)
         sh = lf.Case(ctx, m, m, "f32", mode=lf.MODE_SPLIT_H).set_physics(1e6, 0.71)
         sh.set_cavity_walls().init(perturbation(m, m, SEED_C2))

@@ -51,8 +51,8 @@ struct ConvArgs {
 
 template <int MODE, int BM, int BN>
 __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[BM * LDK];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[BN * LDK];
+  __shared__ __attribute__((aligned(16))) uint16_t As[2 * BM * LDK];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2 * BN * LDK];
   const ConvGeom& g = a.g;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
@@ -108,7 +108,14 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
   const int wtap = bn8 / g.Cin, wci0 = bn8 - wtap * g.Cin;
   const int wky = wtap / 3, wkx = wtap - wky * 3;
 
-  for (int kc = kc0; kc < kc1; ++kc) {
+  // A chunk is staged in registers (ra, rb) from global memory, then stored
+  // to one of two LDS buffers: the loads of chunk k + 1 are in flight while
+  // the matrix cores work on chunk k, and one barrier per chunk suffices
+  // (the buffer a store overwrites was last read before the previous
+  // barrier).
+  constexpr int BV = MODE == BWD_WEIGHT ? 1 : (BN * 4 + 255) / 256;  // B vectors per thread
+  uint4 ra[AV], rb[BV];
+  auto load_chunk = [&](int kc) {
     if (MODE != BWD_WEIGHT) {
       const bool gok = gi < G;
       const int ky = tap >= 6 ? 2 : (tap >= 3 ? 1 : 0), kx = tap - 3 * ky, c0 = cgp << 3;
@@ -130,18 +137,19 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
             }
           }
         }
-        *(uint4*)&As[(rq + 64 * k) * LDK + q * 8] = val;
+        ra[k] = val;
       }
-      for (int v = tid; v < BN * 4; v += 256) {
-        const int r = v >> 2, nn = n0 + r;  // v & 3 == q
+#pragma unroll
+      for (int k = 0; k < BV; ++k) {
+        const int v = tid + 256 * k, r = v >> 2, nn = n0 + r;  // v & 3 == q
         uint4 val = {0u, 0u, 0u, 0u};
-        if (gok && nn < a.N) {
+        if (v < BN * 4 && gok && nn < a.N) {
           if (MODE == FWD)
             val = *(const uint4*)(a.w + ((size_t)nn * 9 + tap) * g.Cin + c0);
           else
             val = *(const uint4*)(a.w + ((size_t)tap * g.Cin + nn) * g.Cout + c0);
         }
-        *(uint4*)&Bs[r * LDK + q * 8] = val;
+        rb[k] = val;
       }
       gi += 4;
       cgp += 4;
@@ -150,7 +158,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
         ++tap;
       }
     } else {
-      // K = output pixels: 16-byte loads along channels, transposed into LDS
+      // K = output pixels: 16-byte loads along channels
       const bool pin = kc * BK + pl < P;
 #pragma unroll
       for (int k = 0; k < AV; ++k) {
@@ -158,25 +166,19 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
         uint4 val = {0u, 0u, 0u, 0u};
         if (pin && co0 < g.Cout)
           val = *(const uint4*)(a.dz + (size_t)(kc * BK + pl) * g.Cout + co0);
-        const uint16_t* e = (const uint16_t*)&val;
-#pragma unroll
-        for (int jj = 0; jj < 8; ++jj) As[(gk * 8 + jj) * LDK + pl] = e[jj];
+        ra[k] = val;
       }
-      if (tid < (BN / 8) * BK) {
-        uint4 val = {0u, 0u, 0u, 0u};
-        if (pin) {
-          if (bn8 < 9 * g.Cin) {
-            const int iy = p1[0] * g.stride + wky - 1, ix = p2[0] * g.stride + wkx - 1;
-            if (iy >= 0 && iy < g.H && ix >= 0 && ix < g.W)
-              val = *(const uint4*)(a.x + ((size_t)(pb[0] * g.H + iy) * g.W + ix) * g.Cin + wci0);
-          } else if (bn8 == 9 * g.Cin) {
-            val.x = 0x3F80u;  // bf16 1.0 in the first column: the bias gradient
-          }
+      uint4 val = {0u, 0u, 0u, 0u};
+      if (tid < (BN / 8) * BK && pin) {
+        if (bn8 < 9 * g.Cin) {
+          const int iy = p1[0] * g.stride + wky - 1, ix = p2[0] * g.stride + wkx - 1;
+          if (iy >= 0 && iy < g.H && ix >= 0 && ix < g.W)
+            val = *(const uint4*)(a.x + ((size_t)(pb[0] * g.H + iy) * g.W + ix) * g.Cin + wci0);
+        } else if (bn8 == 9 * g.Cin) {
+          val.x = 0x3F80u;  // bf16 1.0 in the first column: the bias gradient
         }
-        const uint16_t* e = (const uint16_t*)&val;
-#pragma unroll
-        for (int jj = 0; jj < 8; ++jj) Bs[(grp * 8 + jj) * LDK + pl] = e[jj];
       }
+      rb[0] = val;
       // next chunk's pixel
       p2[0] += BK;
       while (p2[0] >= g.Wo) {
@@ -187,19 +189,62 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
         }
       }
     }
-    __syncthreads();
-    const int lr = lane & 15, lk = (lane >> 4) * 8;
+  };
+  auto store_chunk = [&](int buf) {
+    uint16_t* A = As + buf * BM * LDK;
+    uint16_t* B = Bs + buf * BN * LDK;
+    if (MODE != BWD_WEIGHT) {
+#pragma unroll
+      for (int k = 0; k < AV; ++k) *(uint4*)&A[(rq + 64 * k) * LDK + q * 8] = ra[k];
+#pragma unroll
+      for (int k = 0; k < BV; ++k) {
+        const int v = tid + 256 * k;
+        if (v < BN * 4) *(uint4*)&B[(v >> 2) * LDK + q * 8] = rb[k];
+      }
+    } else {
+      // transposed into LDS (K = pixels along the rows' inner dimension)
+#pragma unroll
+      for (int k = 0; k < AV; ++k) {
+        const int gk = grp + (256 / BK) * k;
+        const uint16_t* e = (const uint16_t*)&ra[k];
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) A[(gk * 8 + jj) * LDK + pl] = e[jj];
+      }
+      if (tid < (BN / 8) * BK) {
+        const uint16_t* e = (const uint16_t*)&rb[0];
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) B[(grp * 8 + jj) * LDK + pl] = e[jj];
+      }
+    }
+  };
+  const int lr = lane & 15, lk = (lane >> 4) * 8;
+  auto compute = [&](int buf) {
+    const uint16_t* A = As + buf * BM * LDK;
+    const uint16_t* B = Bs + buf * BN * LDK;
     bf16x8 av[FM], bv[FN];
 #pragma unroll
-    for (int i = 0; i < FM; ++i) av[i] = *(const bf16x8*)&As[(wm0 + i * 16 + lr) * LDK + lk];
+    for (int i = 0; i < FM; ++i) av[i] = *(const bf16x8*)&A[(wm0 + i * 16 + lr) * LDK + lk];
 #pragma unroll
-    for (int j = 0; j < FN; ++j) bv[j] = *(const bf16x8*)&Bs[(wn0 + j * 16 + lr) * LDK + lk];
+    for (int j = 0; j < FN; ++j) bv[j] = *(const bf16x8*)&B[(wn0 + j * 16 + lr) * LDK + lk];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
       for (int j = 0; j < FN; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+  };
+  if (kc0 < kc1) {
+    load_chunk(kc0);
+    store_chunk(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int kc = kc0; kc < kc1; ++kc) {
+    const bool more = kc + 1 < kc1;
+    if (more) load_chunk(kc + 1);
+    compute(buf);
+    if (more) store_chunk(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
 
   // accumulator element r of block (i, j): row 4 * (lane / 16) + r, column lane % 16
@@ -230,14 +275,27 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
       }
 }
 
-// Sum of the split partials in split order; weights then bias.
-__global__ void k_wgrad_reduce(const float* __restrict__ part, int splits, int Cout, int K9,
-                               int N, float* __restrict__ grad) {
+// Sum of the split partials in split order; weights then bias.  The loads
+// of 16 splits are issued before their additions (which stay in split
+// order), so a thread waits for one round trip per 16 partials.
+__global__ __launch_bounds__(64) void k_wgrad_reduce(const float* __restrict__ part, int splits,
+                                                     int Cout, int K9, int N,
+                                                     float* __restrict__ grad) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= Cout * (K9 + 1)) return;
   const int co = i / (K9 + 1), col = i - co * (K9 + 1);
+  const size_t zs = (size_t)Cout * N;
+  const float* p = part + (size_t)co * N + col;
   float s = 0.f;
-  for (int z = 0; z < splits; ++z) s += part[((size_t)z * Cout + co) * N + col];
+  int z = 0;
+  for (; z + 16 <= splits; z += 16) {
+    float v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = p[(size_t)(z + k) * zs];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) s += v[k];
+  }
+  for (; z < splits; ++z) s += p[(size_t)z * zs];
   if (col < K9) grad[(size_t)co * K9 + col] = s;
   else grad[(size_t)Cout * K9 + co] = s;
 }
@@ -521,8 +579,8 @@ hipError_t launch_conv_bwd_weight(const ConvGeom& g, const uint16_t* x, const ui
   hipLaunchKernelGGL((k_conv<BWD_WEIGHT, 64, 64>), dim3(p.gx, p.gy, p.splits), dim3(256), 0, s,
                      a);
   const int K9 = 9 * g.Cin;
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblocks((long long)g.Cout * (K9 + 1))), dim3(256), 0,
-                     s, part, p.splits, g.Cout, K9, p.N, grad_wb);
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)(((long long)g.Cout * (K9 + 1) + 63) / 64)),
+                     dim3(64), 0, s, part, p.splits, g.Cout, K9, p.N, grad_wb);
   return hipGetLastError();
 }
 

@@ -10,11 +10,7 @@
 //              and the east wall face): u on x-faces [ny][pitch_F], v on
 //              y-faces [ny+1][pitch_F], p and T at centres [ny][pitch_F];
 //   shared columns c0, c0+1, c0+2 = ib.
-// One step is seven launches on one stream:
-//   k_dd_ghost_rows, k_dd_ghost_fold  ghost columns of the FV zone from the LBM moments of the
-//                 previous step (two-point averages; the mean of the inflow
-//                 face is removed: global continuity of the FV zone) and
-//                 rho0 = mean LBM density over the shared columns (Eq 91-93);
+// One step is three launches on one stream:
 //   k_dd_fv       the interior of the FV zone in one pass: u*, v* (QUICK
 //                 convection, central diffusion, pressure gradient,
 //                 buoyancy; Eq 74-75 explicit), then p <- p - c_s^2 div u*
@@ -22,25 +18,32 @@
 //                 the frame of faces and cells the walls' mirror and ghost
 //                 rules or the inflow face reach is formed by other blocks of
 //                 the same launch;
-//   k_dd_pbar_rows, k_dd_pbar_fold  mean FV pressure over the shared columns,
-//                 and the mass the LBM zone is about to gain through the
-//                 links to x_b (its running total is the zone's mass change
-//                 since init: the walls conserve mass);
 //   k_dd_lbm      pull-stream + bounce-back / anti-bounce-back walls,
 //                 moments, BGK collision with buoyancy from T = sum g
 //                 (Eq 5, 18, 19-23) for nodes 0 .. ib-1; the streamed state
-//                 of x_f = ib-1 is kept for the boundary node;
+//                 of x_f = ib-1 is kept for the boundary node; one more
+//                 column of blocks sums, per 256 rows, the new FV pressure
+//                 over the shared columns (p_bar) and the mass the LBM zone
+//                 gains through the links to x_b in this step (its running
+//                 total is the zone's mass change since init: the walls
+//                 conserve mass);
 //   k_dd_xb       x_b from the FV zone: rho_b by Eq 93 with its level
 //                 shifted to hold the LBM zone's mass, u_b, v_b, T_b by
 //                 face averages, populations by non-equilibrium
 //                 extrapolation (Eq 60 / Eq 94-95) or by the
 //                 finite-difference velocity-gradient closure (Eq 70-72);
-//                 then its collision.
+//                 then its collision; then the ghost columns of the next
+//                 step's FV zone from the LBM moments (two-point averages;
+//                 the mean of the inflow face is removed: global continuity
+//                 of the FV zone) and the sums for the next rho0 = mean LBM
+//                 density over the shared columns (Eq 91-93).
 // The north wall may slide along +x (the lid-driven cavity of Sec. 3.3):
 // moving-wall bounce-back in the LBM zone, ghost u = 2 u_lid - u_edge in the
 // FV zone.
 // The LBM zone is 112 B per node (FP32), the FV zone 32 B per cell (u, v, p,
-// T read and written once); the interface work is O(ny).
+// T read and written once); the interface work is O(ny).  The interface's
+// sums over all rows are per-block sums that each consumer adds in block
+// order itself, so no launch is spent on folding them.
 // The single-method cavities of the Sec. 4.2 comparison run the same zone
 // kernels on the whole box: FV only (momentum + pressure/energy, with the
 // west wall's mirror and ghost rules) or LBM only (k_dd_lbm with an east
@@ -92,7 +95,6 @@ __device__ __forceinline__ real feq_s(int q, real drho, real ux, real uy) {
   return w9<real>(q) * fmad(rho, P, drho);
 }
 
-constexpr int kIfacePart = 8;
 // gains of the level of Eq 93 on the LBM zone's mass deficit and on its
 // running sum over the steps
 constexpr double kLevelP = 0.25, kLevelI = 1.0 / 64.0;
@@ -117,9 +119,7 @@ struct SplitArgs {
   const real* __restrict__ pin;  // pressure of the last step
   real* __restrict__ p;          // pressure of this step
   int pF;
-  // interface scalars (double): [0] rho0, [1] p_bar, [2] the LBM zone's mass
-  // change since init, from [kIfacePart] the per-block sums of the ghost and
-  // p_bar kernels
+  // interface scalars and per-block sums (layout at kIfacePart)
   double* __restrict__ iface;
   int nx, ny, s, c0, ib;
   // grid setting 2: coarse planes (see SplitPtrs::gc), sizes and pitch
@@ -132,6 +132,12 @@ struct SplitArgs {
   int west_wall;  // FV zone closed by a wall at x = 0 (FV-only cavity)
   int east_wall;  // LBM zone closed by a wall at x = nx (LBM-only cavity)
   int kind, mom_all;
+  int par;       // parity of the step (the buffer set read), selects the interface's slots
+  int iface_on;  // the divided cavity (interface launches and sums)
+  // mean velocity of the inflow face over its rows, removed from the stored
+  // inflow face (column c0 of u) wherever the FV step reads it (global
+  // continuity of the FV zone); formed at the start of the FV launch
+  real umean;
   real omega, omegaT, tau, nu, alpha, gbeta, Tref;
   real ulid;  // north wall velocity along +x
   int tfix[4];
@@ -143,14 +149,16 @@ template <typename real>
 __device__ __forceinline__ int fidx(const SplitArgs<real>& a, int x) {
   return x - (a.c0 - 2);
 }
+// corr: subtracted from the stored inflow face (column c0), see umean
 template <typename real>
-__device__ __forceinline__ real U_at(const SplitArgs<real>& a, const real* u, int x, int j) {
+__device__ __forceinline__ real U_at(const SplitArgs<real>& a, const real* u, int x, int j,
+                                     real corr = real(0)) {
   real sg = real(1), lid = real(0);
   if (j < 0) { j = -1 - j; sg = -sg; }
   else if (j >= a.ny) { j = 2 * a.ny - 1 - j; sg = -sg; lid = real(2) * a.ulid; }
   if (x > a.nx) { x = 2 * a.nx - x; sg = -sg; }
   else if (x < 0 && a.west_wall) { x = -x; sg = -sg; }
-  return lid + sg * u[j * a.pF + fidx(a, x)];
+  return lid + sg * (u[j * a.pF + fidx(a, x)] - (x == a.c0 ? corr : real(0)));
 }
 template <typename real>
 __device__ __forceinline__ real V_at(const SplitArgs<real>& a, const real* v, int x, int jf) {
@@ -183,95 +191,59 @@ __device__ __forceinline__ real P_at(const SplitArgs<real>& a, int x, int j) {
   return a.pin[j * a.pF + fidx(a, x)];
 }
 
-// 1. ghost columns from the LBM moments of the previous step; rho0.
-//    (a) one thread per row (and per y-face): ghost values, plus per-block
-//        sums of the inflow face and of rho over the shared columns,
-//        reduced in a fixed order;
-//    (b) one block per 256 rows folds the block sums in order (every block
-//        the same sums in the same order, so the same bits), removes the
-//        inflow face's mean from its rows; the first block stores rho0.
-constexpr int kGhostBlock = 256;
+// Interface scalars and sums (FP64, one array):
+//   [2 + 2 p], [3 + 2 p]  the LBM zone's mass change since init and its
+//                         running sum, read by the step of parity p (the
+//                         step writes them for the next one into the other
+//                         pair, so no block reads what another one writes);
+//   from kIfacePart       per block of kIfBlock rows: the ghost sums of the
+//                         steps of parity 0 and of parity 1 (inflow face,
+//                         density over the shared columns), then the p_bar
+//                         sums (pressure over the shared columns, mass flux).
+// Every consumer adds the per-block sums in block order itself, so all of
+// them hold the same bits and no launch is spent on folding.
+constexpr int kIfacePart = 8;
+constexpr int kIfBlock = 256;  // rows per interface block (one thread per row)
 
-template <typename real>
-__global__ __launch_bounds__(kGhostBlock) void k_dd_ghost_rows(SplitArgs<real> a) {
-  __shared__ double sh[2][kGhostBlock];
-  real* u = const_cast<real*>(a.u);
-  real* v = const_cast<real*>(a.v);
-  real* T = const_cast<real*>(a.T);
-  const real* rho = a.mom;
-  const real* ux = a.mom + a.planeL;
-  const real* uy = a.mom + 2 * a.planeL;
-  const real* TL = a.mom + 3 * a.planeL;
-  const int c0 = a.c0, ny = a.ny;
-  const int j = blockIdx.x * kGhostBlock + threadIdx.x;
-  double su = 0.0, sr = 0.0;
-  if (j < ny) {
-    const int o = j * a.pL;
-    const real uf0 = real(0.5) * (ux[o + c0 - 2] + ux[o + c0 - 1]);
-    const real uf1 = real(0.5) * (ux[o + c0 - 1] + ux[o + c0]);
-    u[j * a.pF + fidx(a, c0 - 1)] = uf0;
-    u[j * a.pF + fidx(a, c0)] = uf1;
-    su = (double)uf1;
-    T[j * a.pF + fidx(a, c0 - 2)] = TL[o + c0 - 2];
-    T[j * a.pF + fidx(a, c0 - 1)] = TL[o + c0 - 1];
-    sr = (double)rho[o + c0] + (double)rho[o + c0 + 1] + (double)rho[o + c0 + 2];
+__host__ __device__ __forceinline__ int iface_blocks(int ny) {
+  return (ny + 1 + kIfBlock - 1) / kIfBlock;  // rows and y-faces 0 .. ny
+}
+__device__ __forceinline__ double* ghost_sums(double* iface, int ny, int parity) {
+  return iface + kIfacePart + 2 * iface_blocks(ny) * (parity & 1);
+}
+__device__ __forceinline__ double* pbar_sums(double* iface, int ny) {
+  return iface + kIfacePart + 4 * iface_blocks(ny);
+}
+
+// Sums of two per-row terms over the block's rows in a fixed order: a
+// butterfly over each wave (every lane ends with the same bits: IEEE
+// addition commutes), then the waves' sums in order.  Valid in thread 0.
+__device__ __forceinline__ void block_sum2(double t0, double t1, double (*sh)[kIfBlock / 64],
+                                           double& s0, double& s1) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    t0 += __shfl_xor(t0, off, 64);
+    t1 += __shfl_xor(t1, off, 64);
   }
-  if (j <= ny) {
-    const int jf = j;
-    for (int x = c0 - 2; x <= c0 - 1; ++x) {
-      real vv = real(0);
-      if (jf > 0 && jf < ny) vv = real(0.5) * (uy[(jf - 1) * a.pL + x] + uy[jf * a.pL + x]);
-      v[jf * a.pF + fidx(a, x)] = vv;
-    }
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = t0;
+    sh[1][threadIdx.x >> 6] = t1;
   }
-  sh[0][threadIdx.x] = su;
-  sh[1][threadIdx.x] = sr;
   __syncthreads();
-  for (int k = kGhostBlock / 2; k > 0; k >>= 1) {
-    if ((int)threadIdx.x < k) {
-      sh[0][threadIdx.x] += sh[0][threadIdx.x + k];
-      sh[1][threadIdx.x] += sh[1][threadIdx.x + k];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    a.iface[kIfacePart + 2 * blockIdx.x] = sh[0][0];
-    a.iface[kIfacePart + 2 * blockIdx.x + 1] = sh[1][0];
+  s0 = sh[0][0];
+  s1 = sh[1][0];
+#pragma unroll
+  for (int w = 1; w < kIfBlock / 64; ++w) {
+    s0 += sh[0][w];
+    s1 += sh[1][w];
   }
 }
 
-// In-order sum of n per-block partials spaced `stride` doubles apart, from
-// `base` on: the block stages up to 1024 of them at a time in LDS with
-// parallel loads, then thread 0 adds them in index order (the same order,
-// hence the same bits, as one thread reading them one by one).
-__device__ __forceinline__ double ordered_sum(const double* __restrict__ base, int n, int stride,
-                                              double* stage) {
+// In-order sum of the first (k = 0) or second (k = 1) of n per-block pairs.
+__device__ __forceinline__ double fold_pairs(const double* __restrict__ sums, int n, int k) {
   double t = 0.0;
-  for (int b0 = 0; b0 < n; b0 += 1024) {
-    const int m = n - b0 < 1024 ? n - b0 : 1024;
-    for (int k = threadIdx.x; k < m; k += blockDim.x) stage[k] = base[(size_t)(b0 + k) * stride];
-    __syncthreads();
-    if (threadIdx.x == 0)
-      for (int k = 0; k < m; ++k) t += stage[k];
-    __syncthreads();
-  }
-  return t;  // valid in thread 0
-}
-
-template <typename real>
-__global__ __launch_bounds__(kGhostBlock) void k_dd_ghost_fold(SplitArgs<real> a, int nblocks) {
-  __shared__ double stage[1024];
-  __shared__ real mean_sh;
-  const double tu = ordered_sum(a.iface + kIfacePart, nblocks, 2, stage);
-  if (threadIdx.x == 0) mean_sh = (real)(tu / a.ny);
-  if (blockIdx.x == 0) {
-    const double tr = ordered_sum(a.iface + kIfacePart + 1, nblocks, 2, stage);
-    if (threadIdx.x == 0) a.iface[0] = tr / (3.0 * a.ny);
-  }
-  __syncthreads();
-  real* u = const_cast<real*>(a.u);
-  const int j = blockIdx.x * kGhostBlock + threadIdx.x;
-  if (j < a.ny) u[j * a.pF + fidx(a, a.c0)] -= mean_sh;
+  for (int b = 0; b < n; ++b) t += sums[2 * b + k];
+  return t;
 }
 
 // ---- field access relative to a thread's face / cell (x, j) ------------
@@ -280,7 +252,7 @@ template <typename real>
 struct GenAcc {
   const SplitArgs<real>& a;
   int x, j;
-  __device__ real u(int dx, int dy) const { return U_at(a, a.u, x + dx, j + dy); }
+  __device__ real u(int dx, int dy) const { return U_at(a, a.u, x + dx, j + dy, a.umean); }
   __device__ real v(int dx, int dy) const { return V_at(a, a.v, x + dx, j + dy); }
   __device__ real us(int dx, int dy) const { return U_at(a, a.us, x + dx, j + dy); }
   __device__ real vs(int dx, int dy) const { return V_at(a, a.vs, x + dx, j + dy); }
@@ -506,7 +478,7 @@ struct FrameE {
 // the prescribed inflow face, the walls and their mirror and ghost rules
 template <typename real, int CONV>
 __device__ __forceinline__ real face_u(const SplitArgs<real>& a, int x, int j) {
-  if (x == a.c0) return a.u[j * a.pF + fidx(a, x)];
+  if (x == a.c0) return a.u[j * a.pF + fidx(a, x)] - a.umean;
   if (x == a.nx) return real(0);
   return ustar_val<real, CONV>(a, GenAcc<real>{a, x, j});
 }
@@ -565,8 +537,16 @@ __device__ __forceinline__ void fv_frame(const SplitArgs<real>& a, const FvRegio
   a.Tn[o] = Tn;
 }
 
-template <typename real, int CONV>
-__global__ __launch_bounds__(256) void k_dd_fv(SplitArgs<real> a, FvRegion R) {
+// IFACE: the divided cavity, whose inflow face carries its mean; the FV-only
+// cavity has none (a separate instance, without the corrections' registers)
+template <typename real, int CONV, bool IFACE>
+__global__ __launch_bounds__(256) void k_dd_fv(SplitArgs<real> a0, FvRegion R) {
+  // the mean of the inflow face the boundary-node launch stored, from its
+  // per-block sums in block order (the same bits in every wave)
+  SplitArgs<real> a = a0;
+  a.umean = IFACE ? (real)(fold_pairs(ghost_sums(a.iface, a.ny, a.par), iface_blocks(a.ny), 0) /
+                           a.ny)
+                  : real(0);
   // blocks renumbered so that each XCD works on a contiguous range
   const int nb = gridDim.x, b = blockIdx.x;
   const int per = nb / 8, rem = nb % 8, xcd = b % 8;
@@ -590,9 +570,11 @@ __global__ __launch_bounds__(256) void k_dd_fv(SplitArgs<real> a, FvRegion R) {
                                rP = fv_rsrc(a.pin, bytes), rT = fv_rsrc(a.T, bytes);
   const int vo = fidx(a, x) * (int)sizeof(real), rowb = a.pF * (int)sizeof(real);
   real u[5], v[5], p[2], T[5];
+  // the lane on the inflow face reads it less its mean
+  const real ucorr = x == a.c0 ? a.umean : real(0);
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    u[k] = fv_load<real>(rU, vo, (j0 - 2 + k) * rowb);
+    u[k] = fv_load<real>(rU, vo, (j0 - 2 + k) * rowb) - ucorr;
     v[k] = fv_load<real>(rV, vo, (j0 - 1 + k) * rowb);
     T[k] = fv_load<real>(rT, vo, (j0 - 2 + k) * rowb);
   }
@@ -629,7 +611,7 @@ __global__ __launch_bounds__(256) void k_dd_fv(SplitArgs<real> a, FvRegion R) {
   const int rmax = a.ny - 3;
   auto issue = [&](real (&q)[4], int r) {
     r = min(r, rmax);
-    q[0] = fv_load<real>(rU, vo, (r + 2) * rowb);
+    q[0] = fv_load<real>(rU, vo, (r + 2) * rowb) - ucorr;
     q[1] = fv_load<real>(rV, vo, (r + 3) * rowb);
     q[2] = fv_load<real>(rP, vo, (r + 1) * rowb);
     q[3] = fv_load<real>(rT, vo, (r + 2) * rowb);
@@ -678,24 +660,27 @@ __global__ __launch_bounds__(256) void k_dd_fv(SplitArgs<real> a, FvRegion R) {
   }
 }
 
-// 4. p_bar: mean new FV pressure over the shared columns; and the net mass
-//    the coming stream moves into the LBM zone through the links to x_b:
-//    the post-collision populations x_b sends west (W, NW, SW) less those
-//    x_f sends east (E, NE, SE), each only where its target row exists (a
+// 4. p_bar sums of block b of the interface's rows (b < iface_blocks): the
+//    new FV pressure over the shared columns, and the net mass this step's
+//    stream moves into the LBM zone through the links to x_b: the
+//    post-collision populations x_b sent west (W, NW, SW) less those x_f
+//    sent east (E, NE, SE), each only where its target row exists (a
 //    diagonal leaving through a wall returns to its own node).  Both sets
-//    carry the same weights, so the shifted values give the same sum.
-//    Per-block sums (one thread per row), then an in-order fold by one
-//    thread; the fold adds the flux to the running mass change.
+//    carry the same weights, so the shifted values give the same sum.  Run
+//    by extra blocks of the LBM launch (they read only what that launch
+//    does not write).
 template <typename real>
-__global__ __launch_bounds__(kGhostBlock) void k_dd_pbar_rows(SplitArgs<real> a) {
-  __shared__ double sh[2][kGhostBlock];
-  const int j = blockIdx.x * kGhostBlock + threadIdx.x;
-  double s = 0.0, fl = 0.0;
-  if (j < a.ny) {
-    for (int x = a.c0; x <= a.ib; ++x) s += (double)a.p[j * a.pF + fidx(a, x)];
-    const int PL = a.planeL, ob = j * a.pL + a.ib, of = ob - 1;
+__device__ void pbar_block(const SplitArgs<real>& a, int b) {
+  __shared__ double sh[2][kIfBlock / 64];
+  const int ny = a.ny, ib = a.ib;
+  if (b >= iface_blocks(ny)) return;  // uniform per block
+  const int j = b * kIfBlock + (int)threadIdx.x;
+  double ps = 0.0, fl = 0.0;
+  if (j < ny) {
+    for (int x = a.c0; x <= ib; ++x) ps += (double)a.p[j * a.pF + fidx(a, x)];
+    const int PL = a.planeL, ob = j * a.pL + ib, of = ob - 1;
     double in = (double)a.fin[3 * PL + ob], out = (double)a.fin[1 * PL + of];
-    if (j + 1 < a.ny) {
+    if (j + 1 < ny) {
       in += (double)a.fin[6 * PL + ob];
       out += (double)a.fin[5 * PL + of];
     }
@@ -705,31 +690,12 @@ __global__ __launch_bounds__(kGhostBlock) void k_dd_pbar_rows(SplitArgs<real> a)
     }
     fl = in - out;
   }
-  sh[0][threadIdx.x] = s;
-  sh[1][threadIdx.x] = fl;
-  __syncthreads();
-  for (int k = kGhostBlock / 2; k > 0; k >>= 1) {
-    if ((int)threadIdx.x < k) {
-      sh[0][threadIdx.x] += sh[0][threadIdx.x + k];
-      sh[1][threadIdx.x] += sh[1][threadIdx.x + k];
-    }
-    __syncthreads();
-  }
+  double bs, bf;
+  block_sum2(ps, fl, sh, bs, bf);
   if (threadIdx.x == 0) {
-    a.iface[kIfacePart + 2 * blockIdx.x] = sh[0][0];
-    a.iface[kIfacePart + 2 * blockIdx.x + 1] = sh[1][0];
-  }
-}
-
-template <typename real>
-__global__ __launch_bounds__(256) void k_dd_pbar_fold(SplitArgs<real> a, int nblocks) {
-  __shared__ double stage[1024];
-  const double t = ordered_sum(a.iface + kIfacePart, nblocks, 2, stage);
-  const double tf = ordered_sum(a.iface + kIfacePart + 1, nblocks, 2, stage);
-  if (threadIdx.x == 0) {
-    a.iface[1] = t / (3.0 * a.ny);
-    a.iface[2] += tf;
-    a.iface[3] -= a.iface[2];  // running sum of the zone's mass deficit
+    double* out = pbar_sums(a.iface, ny);
+    out[2 * b] = bs;
+    out[2 * b + 1] = bf;
   }
 }
 
@@ -808,9 +774,14 @@ __device__ __forceinline__ void moments9(const real f[9], real& drho, real& ux, 
 }
 
 template <typename real>
-__global__ __launch_bounds__(256) void k_dd_lbm(SplitArgs<real> a) {
+__global__ __launch_bounds__(256) void k_dd_lbm(SplitArgs<real> a, int pbar_rows) {
+  // the first pbar_rows rows of blocks (dispatched first) form the p_bar sums
+  if ((int)blockIdx.y < pbar_rows) {
+    pbar_block(a, blockIdx.y * gridDim.x + blockIdx.x);
+    return;
+  }
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int j = (blockIdx.y - pbar_rows) * 4 + (threadIdx.x >> 6);
   if (i >= a.ib || j >= a.ny) return;
   const int pL = a.pL, PL = a.planeL;
   real f[9], g[5];
@@ -861,29 +832,31 @@ __global__ __launch_bounds__(256) void k_dd_lbm(SplitArgs<real> a) {
   for (int q = 0; q < 5; ++q) a.gout[q * PL + o] = g[q];
 }
 
-// 6. the artificial boundary node x_b = ib, one thread per row
+// 6. the artificial boundary node x_b = ib of row j: rho_b by Eq 93 with
+//    its level, u_b, v_b, T_b by face averages of the new FV state,
+//    populations by non-equilibrium extrapolation or the finite-difference
+//    closure, then its collision.  mchange: the LBM zone's mass change since
+//    init after this step's stream; msum: the running sum of its deficit.
 template <typename real>
-__global__ __launch_bounds__(256) void k_dd_xb(SplitArgs<real> a) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= a.ny) return;
+__device__ __forceinline__ void xb_row(const SplitArgs<real>& a, int j, double rho0, double pbar,
+                                       double mchange, double msum) {
   const int ib = a.ib, ny = a.ny;
   // FV state at the new time level (u*, v*, p, T_new)
   const real ub = real(0.5) * (a.us[j * a.pF + fidx(a, ib)] + a.us[j * a.pF + fidx(a, ib + 1)]);
   const real vb = real(0.5) * (a.vs[j * a.pF + fidx(a, ib)] + a.vs[(j + 1) * a.pF + fidx(a, ib)]);
   const real Tb = a.Tn[j * a.pF + fidx(a, ib)];
-  const double rho0 = a.iface[0], pbar = a.iface[1];
   // Eq 93: rho_b = rho0 ((p_S - p_bar) / (rho0 c_s^2) + 1), its level shifted
   // uniformly over the rows by kLevelP times the amount that, carried by the
   // rest weights of the populations x_b sends into the zone (W, NW, SW; one
   // diagonal fewer on the wall rows), would return the zone to its mass at
-  // init, plus kLevelI times the running sum of that deficit over the steps
-  // (iface[3]).  The sum holds the zone's mass at its value at init in any
-  // steady state, whatever the two gains; the partial correction keeps the
+  // init, plus kLevelI times the running sum of that deficit over the steps.
+  // The sum holds the zone's mass at its value at init in any steady state,
+  // whatever the two gains; the partial correction keeps the
   // finite-difference closure stable (its populations answer the FV
   // pressure one step later, and a whole correction per step overshoots).
   const double wsum = a.ny * ((1.0 / 9.0 + 1.0 / 36.0) + 1.0 / 36.0) - 1.0 / 36.0 - 1.0 / 36.0;
-  const double e = -a.iface[2];
-  const double delta = (kLevelP * e + kLevelI * a.iface[3]) / wsum;
+  const double e = -mchange;
+  const double delta = (kLevelP * e + kLevelI * msum) / wsum;
   const double rb =
       rho0 * (((double)a.p[j * a.pF + fidx(a, ib)] - pbar) / (rho0 / 3.0) + 1.0) + delta;
   const real drb = (real)(rb - 1.0);
@@ -938,6 +911,92 @@ __global__ __launch_bounds__(256) void k_dd_xb(SplitArgs<real> a) {
   for (int q = 0; q < 5; ++q) a.gout[q * a.planeL + o] = g[q];
 }
 
+// 7. ghost columns of the next step's FV zone (its input buffers: this
+//    step's output set us, vs, Tn) from the LBM moments of this step, for
+//    row j (j < ny) and y-face j (j <= ny): two-point averages of the LBM
+//    velocities on the faces c0 - 1 and c0 (the inflow face, whose mean over
+//    the rows the FV step removes where it reads it: global continuity of
+//    the FV zone), the
+//    LBM temperatures on the ghost cells.  Returns the row's inflow velocity
+//    and density over the shared columns c0 .. ib (for rho0, Eq 91-93).
+template <typename real>
+__device__ __forceinline__ void ghost_row(const SplitArgs<real>& a, int j, double& su,
+                                          double& sr) {
+  const int c0 = a.c0, ny = a.ny;
+  const real* rho = a.mom;
+  const real* ux = a.mom + a.planeL;
+  const real* uy = a.mom + 2 * a.planeL;
+  const real* TL = a.mom + 3 * a.planeL;
+  su = 0.0;
+  sr = 0.0;
+  if (j < ny) {
+    const int o = j * a.pL;
+    const real uf1 = real(0.5) * (ux[o + c0 - 1] + ux[o + c0]);
+    a.us[j * a.pF + fidx(a, c0 - 1)] = real(0.5) * (ux[o + c0 - 2] + ux[o + c0 - 1]);
+    a.us[j * a.pF + fidx(a, c0)] = uf1;
+    a.Tn[j * a.pF + fidx(a, c0 - 2)] = TL[o + c0 - 2];
+    a.Tn[j * a.pF + fidx(a, c0 - 1)] = TL[o + c0 - 1];
+    su = (double)uf1;
+    sr = (double)rho[o + c0] + (double)rho[o + c0 + 1] + (double)rho[o + c0 + 2];
+  }
+  if (j <= ny) {
+    for (int x = c0 - 2; x <= c0 - 1; ++x) {
+      real vv = real(0);
+      if (j > 0 && j < ny) vv = real(0.5) * (uy[(j - 1) * a.pL + x] + uy[j * a.pL + x]);
+      a.vs[j * a.pF + fidx(a, x)] = vv;
+    }
+  }
+}
+
+// The interface's end of a step (one thread per row and y-face):
+//  (a) unless ghost_only: every block adds the per-block sums in order --
+//      p_bar, the mean new FV pressure over the shared columns (written by
+//      the LBM launch), the net mass this step's stream moved into the LBM
+//      zone through the links to x_b (same launch), and rho0, the mean LBM
+//      density over the shared columns at the start of the step (the ghost
+//      sums of this step's parity); block 0 stores the zone's new mass
+//      change and running sum for the next step; then x_b of its row;
+//  (b) the ghost values of the next step (ghost_row) and the block's sums
+//      of them (the ghost sums of the next parity); the next FV launch adds
+//      the inflow sums in order and removes their mean where it reads the
+//      inflow face (umean).
+// ghost_only (at init, with the arguments of parity 1, so that the values
+// land in the buffers and sums step 0 reads) runs (b) alone.
+template <typename real>
+__global__ __launch_bounds__(kIfBlock) void k_dd_xb(SplitArgs<real> a, int ghost_only) {
+  __shared__ double sh[2][kIfBlock / 64];
+  __shared__ double fold[3];
+  const int ny = a.ny, nb = (int)gridDim.x;
+  const int j = blockIdx.x * kIfBlock + threadIdx.x;
+  if (!ghost_only) {
+    if (threadIdx.x == 0) {
+      const double* ps = pbar_sums(a.iface, ny);
+      fold[0] = fold_pairs(ps, nb, 0);
+      fold[1] = fold_pairs(ps, nb, 1);
+      fold[2] = fold_pairs(ghost_sums(a.iface, ny, a.par), nb, 1);
+    }
+    __syncthreads();
+    const double pbar = fold[0] / (3.0 * ny), rho0 = fold[2] / (3.0 * ny);
+    const int sl = 2 + 2 * (a.par & 1), sn = 2 + 2 * ((a.par & 1) ^ 1);
+    const double mchange = a.iface[sl] + fold[1];  // the zone's mass change since init
+    const double msum = a.iface[sl + 1] - mchange;  // running sum of its deficit
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.iface[sn] = mchange;
+      a.iface[sn + 1] = msum;
+    }
+    if (j < ny) xb_row(a, j, rho0, pbar, mchange, msum);
+  }
+  double su, sr;
+  ghost_row(a, j, su, sr);
+  double bu, br;
+  block_sum2(su, sr, sh, bu, br);
+  if (threadIdx.x == 0) {
+    double* gn = ghost_sums(a.iface, ny, a.par ^ 1);
+    gn[2 * blockIdx.x] = bu;
+    gn[2 * blockIdx.x + 1] = br;
+  }
+}
+
 // dense output: LBM values for columns < s, FV (face-averaged) for >= s
 template <typename real>
 __global__ __launch_bounds__(256) void k_dd_output(SplitArgs<real> a, real* __restrict__ out) {
@@ -976,8 +1035,8 @@ __global__ __launch_bounds__(256) void k_dd_init(SplitArgs<real> a, const double
   const auto t0_at = [&](int xx) { return a.transposed ? T0[xx * a.ny + j] : T0[j * a.nx + xx]; };
   const double t0 = (x < a.nx && T0) ? t0_at(x) : 0.0;
   if (x == 0 && j == 0) {
-    a.iface[2] = 0.0;  // the LBM zone's mass change
-    a.iface[3] = 0.0;  // and its running sum
+    // the LBM zone's mass change and its running sum, both parities
+    for (int k = 2; k < 6; ++k) a.iface[k] = 0.0;
   }
   if (x < a.nl) {
     const int o = j * a.pL + x;
@@ -1399,6 +1458,9 @@ static SplitArgs<real> make_args(const SplitGeom& G, const SplitPtrs<real>& P, c
   a.east_wall = G.lbm_only;
   a.kind = S.kind;
   a.mom_all = mom_all;
+  a.par = cur;
+  a.iface_on = !G.fv_only && !G.lbm_only && !G.gs2 && !G.mcm;
+  a.umean = real(0);
   a.omega = real(1.0 / S.tau);
   a.omegaT = real(1.0 / S.tauT);
   a.tau = real(S.tau);
@@ -1444,14 +1506,17 @@ static FvRegion fv_region(const SplitGeom& G, int band) {
   return r;
 }
 
-// rows per wave of the march: the longest of 16, 8, 4 that still gives the
-// chip 2048 waves (a band's halo costs 4.5 row loads)
+// rows per wave of the march: the longest of 32, 24, 16, 12, 8, 4 that still
+// gives the chip 2048 waves (a band's halo costs 4.5 row loads; measured on
+// MI355X, us per step at 32 / 24 / 16 / 12 rows: FV-only 4096^2 148 / 153 /
+// 158 / -, 2048^2 37.3 / 33.2 / 38.4 / 40.7, 1024^2 24.0 / 19.3 / 14.3 /
+// 12.8; the 4096^2 divided cavity 319 / 327 / 328 / -)
 static FvRegion fv_region_auto(const SplitGeom& G) {
-  int band = 16;
-  FvRegion r = fv_region(G, band);
-  while (band > 4 && r.nwaves < 2048) {
-    band /= 2;
-    r = fv_region(G, band);
+  const int bands[6] = {32, 24, 16, 12, 8, 4};
+  FvRegion r{};
+  for (int k = 0; k < 6; ++k) {
+    r = fv_region(G, bands[k]);
+    if (r.nwaves >= 2048) break;
   }
   return r;
 }
@@ -1459,7 +1524,10 @@ static FvRegion fv_region_auto(const SplitGeom& G) {
 template <typename real, int CONV>
 static void launch_fv(const SplitArgs<real>& a, const FvRegion& R, hipStream_t s) {
   const int nb = R.nfrb + (R.nwaves + 3) / 4;
-  hipLaunchKernelGGL((k_dd_fv<real, CONV>), dim3(nb), dim3(256), 0, s, a, R);
+  if (a.iface_on)
+    hipLaunchKernelGGL((k_dd_fv<real, CONV, true>), dim3(nb), dim3(256), 0, s, a, R);
+  else
+    hipLaunchKernelGGL((k_dd_fv<real, CONV, false>), dim3(nb), dim3(256), 0, s, a, R);
 }
 
 template <typename real>
@@ -1470,26 +1538,19 @@ hipError_t launch_split_step(const SplitGeom& G, const SplitPtrs<real>& P, const
   if ((size_t)(G.ny + 1) * G.pF * sizeof(real) >= ((size_t)1 << 31)) return hipErrorInvalidValue;
   const dim3 gl((a.nl + 63) / 64, (G.ny + 3) / 4);
   if (G.lbm_only) {  // one zone kernel per step
-    hipLaunchKernelGGL(k_dd_lbm<real>, gl, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_dd_lbm<real>, gl, dim3(256), 0, s, a, 0);
     return hipGetLastError();
   }
   const bool split = !G.fv_only;
-  const int ngb = (G.ny + 1 + kGhostBlock - 1) / kGhostBlock;  // rows and y-faces 0 .. ny
-  if (split) {
-    hipLaunchKernelGGL(k_dd_ghost_rows<real>, dim3(ngb), dim3(kGhostBlock), 0, s, a);
-    hipLaunchKernelGGL(k_dd_ghost_fold<real>, dim3((G.ny + kGhostBlock - 1) / kGhostBlock),
-                       dim3(kGhostBlock), 0, s, a, ngb);
-  }
   const FvRegion R = fv_region_auto(G);
   if (S.conv == 1) launch_fv<real, 1>(a, R, s);
   else if (S.conv == 2) launch_fv<real, 2>(a, R, s);
   else launch_fv<real, 0>(a, R, s);
   if (split) {
-    const int npb = (G.ny + kGhostBlock - 1) / kGhostBlock;
-    hipLaunchKernelGGL(k_dd_pbar_rows<real>, dim3(npb), dim3(kGhostBlock), 0, s, a);
-    hipLaunchKernelGGL(k_dd_pbar_fold<real>, dim3(1), dim3(256), 0, s, a, npb);
-    hipLaunchKernelGGL(k_dd_lbm<real>, dim3((G.ib + 63) / 64, (G.ny + 3) / 4), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_dd_xb<real>, dim3((G.ny + 255) / 256), dim3(256), 0, s, a);
+    // the LBM zone, after rows of blocks for the p_bar sums
+    const int nbx = (G.ib + 63) / 64, pr = (iface_blocks(G.ny) + nbx - 1) / nbx;
+    hipLaunchKernelGGL(k_dd_lbm<real>, dim3(nbx, (G.ny + 3) / 4 + pr), dim3(256), 0, s, a, pr);
+    hipLaunchKernelGGL(k_dd_xb<real>, dim3(iface_blocks(G.ny)), dim3(kIfBlock), 0, s, a, 0);
   }
   return hipGetLastError();
 }
@@ -1505,6 +1566,9 @@ hipError_t launch_split_init(const SplitGeom& G, const SplitPtrs<real>& P, const
   // the second FV buffers start equal to the first (prescribed/wall faces)
   const SplitArgs<real> b = make_args<real>(G, P, S, 1, 1);
   hipLaunchKernelGGL(k_dd_init<real>, dim3((w + 255) / 256, G.ny), dim3(256), 0, s, b, T0);
+  // the ghost values and sums step 0 reads (written as by a step of parity 1)
+  if (b.iface_on)
+    hipLaunchKernelGGL(k_dd_xb<real>, dim3(iface_blocks(G.ny)), dim3(kIfBlock), 0, s, b, 1);
   return hipGetLastError();
 }
 
