@@ -65,7 +65,13 @@ struct lf_case {
   int mcm_S, mcm_N;
   unsigned long long mcm_seed;
   long long mcm_max;
+  // captured runs of kGraphSteps steps starting from buffer set 0 / 1, and
+  // the signature of the settings they were captured with
+  hipGraphExec_t gexec[2];
+  uint64_t gsig[2];
 };
+
+static void drop_graphs(lf_case* c);
 
 template <typename real>
 static real* fptr(lf_case* c, size_t off) { return (real*)(c->ws + off); }
@@ -165,8 +171,9 @@ static lf_status split_init(lf_case* c, const double* dT) {
   return LF_OK;
 }
 
+// n steps; the last writes every node's moments when mom_last is set
 template <typename real>
-static lf_status split_steps(lf_case* c, int64_t n) {
+static lf_status split_steps(lf_case* c, int64_t n, bool mom_last = true) {
   hipStream_t s = c->ctx->stream;
   const lf::SplitPtrs<real> P = split_ptrs<real>(c);
   if (c->sg.gs2 || c->sg.mcm) {
@@ -194,7 +201,8 @@ static lf_status split_steps(lf_case* c, int64_t n) {
     return LF_OK;
   }
   for (int64_t k = 0; k < n; ++k) {
-    HIP_TRY(lf::launch_split_step<real>(c->sg, P, c->sp, c->cur, k == n - 1 ? 1 : 0, s));
+    HIP_TRY(lf::launch_split_step<real>(c->sg, P, c->sp, c->cur,
+                                        (mom_last && k == n - 1) ? 1 : 0, s));
     c->cur ^= 1;
   }
   c->steps += n;
@@ -403,6 +411,7 @@ lf_status lf_case_create(lf_ctx* ctx, const lf_case_desc* d, lf_case** out) {
 }
 
 lf_status lf_case_destroy(lf_case* c) {
+  if (c) drop_graphs(c);
   delete c;
   return LF_OK;
 }
@@ -662,13 +671,14 @@ static int auto_band(const lf_case* c) {
 
 }  // extern "C"
 
+// n steps; the last writes the moment planes when mom_last is set
 template <typename real>
-static lf_status step_impl(lf_case* c, int64_t n) {
+static lf_status step_impl(lf_case* c, int64_t n, bool mom_last = true) {
   hipStream_t s = c->ctx->stream;
   const int band = auto_band(c);
   for (int64_t k = 0; k < n; ++k) {
     const int a = c->cur, b = a ^ 1;
-    real* mom = (k == n - 1) ? fptr<real>(c, c->off_mom) : nullptr;
+    real* mom = (mom_last && k == n - 1) ? fptr<real>(c, c->off_mom) : nullptr;
     HIP_TRY(lf::launch_hybrid_step<real>(
         c->g, c->w, c->p, fptr<real>(c, c->off_f[a]), fptr<real>(c, c->off_f[b]),
         fptr<real>(c, c->off_T[a]), fptr<real>(c, c->off_T[b]),
@@ -680,6 +690,94 @@ static lf_status step_impl(lf_case* c, int64_t n) {
   return LF_OK;
 }
 
+// Steps launched one call at a time (the last writing the moments when
+// mom_last is set).
+static lf_status eager_steps(lf_case* c, int64_t n, bool mom_last) {
+  if (c->split)
+    return c->desc.precision == LF_F32 ? split_steps<float>(c, n, mom_last)
+                                       : split_steps<double>(c, n, mom_last);
+  return c->desc.precision == LF_F32 ? step_impl<float>(c, n, mom_last)
+                                     : step_impl<double>(c, n, mom_last);
+}
+
+// Long step calls replay a captured hipGraph of kGraphSteps steps (an even
+// count, so a run starts and ends on the same buffer set) and launch the
+// remaining 1 .. kGraphSteps steps one by one, the last writing the
+// moments.  A run's kernel arguments hold the case's buffers and settings,
+// so it is captured again when the signature of those changes.  Grid
+// setting 2 and LBM-MCM launch an energy step every S lattice steps counted
+// since init (and MCM a new stream seed each time): launched one by one.
+constexpr int64_t kGraphSteps = 64;
+
+static uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+  const unsigned char* b = (const unsigned char*)p;
+  for (size_t k = 0; k < n; ++k) h = (h ^ b[k]) * 1099511628211ull;
+  return h;
+}
+
+static uint64_t graph_signature(const lf_case* c) {
+  uint64_t h = 14695981039346656037ull;
+  h = fnv1a(h, &c->ws, sizeof(c->ws));
+  h = fnv1a(h, &c->ctx->band, sizeof(c->ctx->band));
+  h = fnv1a(h, &c->g, sizeof(c->g));
+  h = fnv1a(h, &c->w, sizeof(c->w));
+  h = fnv1a(h, &c->p, sizeof(c->p));
+  h = fnv1a(h, &c->sg, sizeof(c->sg));
+  h = fnv1a(h, &c->sp, sizeof(c->sp));
+  return h;
+}
+
+static void drop_graphs(lf_case* c) {
+  for (int k = 0; k < 2; ++k) {
+    if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+    c->gexec[k] = nullptr;
+    c->gsig[k] = 0;
+  }
+}
+
+// the run of kGraphSteps steps from the current buffer set, captured if need be
+static lf_status ensure_run(lf_case* c, uint64_t sig) {
+  const int slot = c->cur;
+  if (c->gexec[slot] && c->gsig[slot] == sig) return LF_OK;
+  if (c->gexec[slot]) (void)hipGraphExecDestroy(c->gexec[slot]);
+  c->gexec[slot] = nullptr;
+  hipStream_t s = c->ctx->stream;
+  const int cur0 = c->cur;
+  const int64_t steps0 = c->steps;
+  HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  lf_status st = eager_steps(c, kGraphSteps, false);  // recorded, not run
+  c->cur = cur0;
+  c->steps = steps0;
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(s, &g);
+  if (st != LF_OK || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return st != LF_OK ? st : fail(LF_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+  }
+  const hipError_t ei = hipGraphInstantiate(&c->gexec[slot], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    c->gexec[slot] = nullptr;
+    return fail(LF_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+  }
+  c->gsig[slot] = sig;
+  return LF_OK;
+}
+
+static lf_status run_steps(lf_case* c, int64_t n) {
+  const bool cyclic = c->split && (c->sg.gs2 || c->sg.mcm);
+  if (cyclic || n <= kGraphSteps) return eager_steps(c, n, true);
+  const uint64_t sig = graph_signature(c);
+  for (int64_t reps = (n - 1) / kGraphSteps; reps > 0; --reps) {
+    lf_status st = ensure_run(c, sig);
+    if (st != LF_OK) return st;
+    HIP_TRY(hipGraphLaunch(c->gexec[c->cur], c->ctx->stream));
+    c->steps += kGraphSteps;
+    n -= kGraphSteps;
+  }
+  return eager_steps(c, n, true);
+}
+
 extern "C" {
 
 lf_status lf_case_step(lf_case* c, int64_t nsteps) {
@@ -688,9 +786,7 @@ lf_status lf_case_step(lf_case* c, int64_t nsteps) {
   if (!c->inited) return fail(LF_ESTATE, "init before step");
   if (!c->have_params) return fail(LF_ESTATE, "set_physics or set_lattice before step");
   if (nsteps == 0) return LF_OK;
-  if (c->split)
-    return c->desc.precision == LF_F32 ? split_steps<float>(c, nsteps) : split_steps<double>(c, nsteps);
-  return c->desc.precision == LF_F32 ? step_impl<float>(c, nsteps) : step_impl<double>(c, nsteps);
+  return run_steps(c, nsteps);
 }
 
 lf_status lf_case_profile_steps(lf_case* c, int64_t nsteps, double* avg_ms, double* min_ms,
