@@ -917,6 +917,9 @@ lf_status lf_case_run_to_steady(lf_case* c, double tol, int check_every, int64_t
   lf_status st = lf_case_residual(c, r);  // snapshot the current state
   if (st != LF_OK) return st;
   std::vector<double> hist;
+  // the slowest diffusive mode the FP32 floor rule waits for
+  const double lam_min = lf_slow_mode(c->params[3], c->params[1], c->desc.nx, c->desc.ny,
+                                      c->w.tfix, c->w.xper, c->w.yper, check_every);
   int64_t done = 0;
   int fired = 0;
   while (done < max_steps) {
@@ -929,7 +932,10 @@ lf_status lf_case_run_to_steady(lf_case* c, double tol, int check_every, int64_t
     const double m = fmax(r[0], fmax(r[1], r[2]));
     hist.push_back(m);
     if (m <= tol || (r[0] == 0.0 && r[1] == 0.0 && r[2] == 0.0)) { fired = LF_STOP_TOL; break; }
-    if (c->desc.precision == LF_F32 && lf_at_floor(hist)) { fired = LF_STOP_FLOOR; break; }
+    if (c->desc.precision == LF_F32 && lf_at_floor(hist, lam_min)) {
+      fired = LF_STOP_FLOOR;
+      break;
+    }
   }
   if (steps_taken) *steps_taken = done;
   if (r_final) memcpy(r_final, r, sizeof(r));

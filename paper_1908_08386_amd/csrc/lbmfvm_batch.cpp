@@ -551,7 +551,10 @@ lf_status lf_batch_run_to_steady(lf_batch* b, double tol, int check_every, int64
       }
       int fired = 0;
       if (m <= tol || (c.r[0] == 0.0 && c.r[1] == 0.0 && c.r[2] == 0.0)) fired = LF_STOP_TOL;
-      else if (b->precision == LF_F32 && lf_at_floor(c.hist)) fired = LF_STOP_FLOOR;
+      else if (b->precision == LF_F32 &&
+               lf_at_floor(c.hist, lf_slow_mode(c.prm[3], c.prm[1], c.nx, c.ny, c.tfix, 0, 0,
+                                                check_every)))
+        fired = LF_STOP_FLOOR;
       if (fired || c.steps >= max_steps) {
         c.active = false;
         c.rule = fired;

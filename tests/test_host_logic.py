@@ -92,11 +92,12 @@ def _floor_rule_driver(tmp_path):
     src = tmp_path / "floor.cpp"
     src.write_text(
         '#include "lf_stop.h"\n#include <cstdio>\n'
-        "int main() { int n; if (scanf(\"%d\", &n) != 1) return 1; std::vector<double> h(n);\n"
+        "int main() { int n; double lmin; if (scanf(\"%lf %d\", &lmin, &n) != 2) return 1;\n"
+        "  std::vector<double> h(n);\n"
         "  for (auto& x : h) if (scanf(\"%lf\", &x) != 1) return 1;\n"
         "  std::vector<double> p;\n"
         "  for (int k = 0; k < n; ++k) { p.push_back(h[k]);\n"
-        "    if (lf_at_floor(p)) { printf(\"%d\\n\", k + 1); return 0; } }\n"
+        "    if (lf_at_floor(p, lmin)) { printf(\"%d\\n\", k + 1); return 0; } }\n"
         "  printf(\"0\\n\"); return 0; }\n")
     exe = tmp_path / "floor"
     subprocess.run(["g++", "-O1", "-std=c++17", "-I",
@@ -105,8 +106,9 @@ def _floor_rule_driver(tmp_path):
     return exe
 
 
-def _fires(exe, h):
-    r = subprocess.run([str(exe)], input=f"{len(h)} " + " ".join(repr(float(x)) for x in h),
+def _fires(exe, h, lam_min=0.0):
+    r = subprocess.run([str(exe)], input=f"{lam_min!r} {len(h)} " +
+                       " ".join(repr(float(x)) for x in h),
                        capture_output=True, text=True, check=True)
     return int(r.stdout)
 
@@ -139,3 +141,64 @@ def test_fp32_floor_rule_waits_for_the_slow_mode(tmp_path):
     # above 1e-6: never; a clean decay that keeps setting minima: never
     assert _fires(exe, 2e-6 * (1.0 + 0.3 * rng.random(200))) == 0
     assert _fires(exe, 1e-3 * 0.9 ** np.arange(300)) == 0
+
+
+def test_fp32_floor_rule_without_a_measured_decay(tmp_path):
+    """A run that starts within 10x of the floor (a start from a nearly
+    steady field) shows no decay to measure a slow mode from: with the
+    cavity's slowest diffusive decay factor lam_min per check given, the rule
+    waits until that mode, extrapolated from the floor value, is <= 2e-6
+    from settled; without it, it stops at the floor.  A measured decay is
+    used as it is, whatever lam_min."""
+    exe = _floor_rule_driver(tmp_path)
+    rng = np.random.default_rng(5)
+    n = 3000
+    h = 3e-7 * 0.5 ** np.arange(n) + 1e-7 * (1.0 + 0.3 * rng.random(n))
+    onset = int(np.argmax(h <= 2 * h.min()))
+    free = _fires(exe, h)
+    assert 0 < free <= onset + 20  # four checks without a new minimum (noise sets a few)
+    lam = 0.997  # e.g. the temperature mode across a 2048-wide cavity, 1000 steps per check
+    fired = _fires(exe, h, lam)
+    rest = h[onset] * lam / (1 - lam) * lam ** (fired - 1 - onset)
+    assert fired > free and rest <= 2e-6 * 1.05 and rest * lam ** -2 > 2e-6, (fired, onset, rest)
+    # a measured decay (here faster than lam_min) is kept
+    h2 = 1e-3 * 0.5 ** np.arange(60) + 1e-7 * (1.0 + 0.3 * rng.random(60))
+    assert _fires(exe, h2, lam) == _fires(exe, h2)
+    k = np.arange(20000)
+    h3 = 1e-2 * 0.999 ** k + 1e-7 * (1.0 + 0.3 * rng.random(k.size))
+    assert _fires(exe, h3, 0.99) == _fires(exe, h3)
+
+
+def test_slow_mode_of_the_side_heated_cavity(tmp_path):
+    """lf_slow_mode: the temperature mode between the fixed-temperature west
+    and east walls (alpha pi^2 / nx^2 per step) when it is slower than the
+    no-slip velocity mode; K steps per check."""
+    src = tmp_path / "slow.cpp"
+    src.write_text(
+        '#include "lf_stop.h"\n#include <cstdio>\n'
+        "int main() { double a, nu; int nx, ny, w, e, s, n, xp, yp, K;\n"
+        "  if (scanf(\"%lf %lf %d %d %d %d %d %d %d %d %d\", &a, &nu, &nx, &ny, &w, &e, &s, &n,\n"
+        "            &xp, &yp, &K) != 11) return 1;\n"
+        "  const int t[4] = {w, e, s, n};\n"
+        "  printf(\"%.17g\\n\", lf_slow_mode(a, nu, nx, ny, t, xp, yp, K)); return 0; }\n")
+    exe = tmp_path / "slow"
+    subprocess.run(["g++", "-O1", "-std=c++17", "-I",
+                    os.path.join(ROOT, "paper_1908_08386_amd", "csrc"), str(src), "-o", str(exe)],
+                   check=True)
+
+    def lam(*args):
+        r = subprocess.run([str(exe)], input=" ".join(str(x) for x in args),
+                           capture_output=True, text=True, check=True)
+        return float(r.stdout)
+    pi2 = np.pi ** 2
+    # 2048 x 512, alpha 1.22, nu 0.87: the thermal mode across the width is slowest
+    got = lam(1.22, 0.87, 2048, 512, 1, 1, 0, 0, 0, 0, 1000)
+    assert abs(got - np.exp(-1000 * 1.22 * pi2 / 2048 ** 2)) < 1e-15
+    # a viscous mode slower than the thermal one (large Pr)
+    got = lam(1.0, 0.01, 256, 256, 1, 1, 0, 0, 0, 0, 1000)
+    assert abs(got - np.exp(-1000 * 0.01 * pi2 * 2 / 256 ** 2)) < 1e-15
+    # one fixed wall: a quarter wavelength; adiabatic box: the velocity mode only
+    got = lam(1.0, 5.0, 100, 100, 1, 0, 0, 0, 0, 0, 10)
+    assert abs(got - np.exp(-10 * 0.25 * pi2 / 100 ** 2)) < 1e-15
+    got = lam(1.0, 5.0, 100, 100, 0, 0, 0, 0, 0, 0, 10)
+    assert abs(got - np.exp(-10 * 5.0 * pi2 * 2 / 100 ** 2)) < 1e-15
