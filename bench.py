@@ -201,6 +201,34 @@ def split_closures(lf, ctx, m, out):
         del sp
 
 
+def net_training(lf, ctx, steps=100, batch=32):
+    """The warm-start network's training step (forward, both backward passes
+    and Adam on a mini-batch of `batch` canvases) on synthetic targets:
+    uniform fields in [0, 0.5) for 64 seeded cavity draws.  Timed on the
+    library's stream (HIP events around `steps` steps)."""
+    import numpy as np
+    import torch
+    from synth_inputs import SEED_TRAIN, cavity_sweep, uniform01
+    from paper_1908_08386_amd import warmstart as ws
+    net = lf.Net(ctx, max_batch=batch)
+    net.set_weights(net.he_uniform(uniform01(SEED_TRAIN * 7 + 1, net.nparam)))
+    cases = cavity_sweep(64, SEED_TRAIN)
+    dev = f"cuda:{ctx.device}"
+    feat = torch.tensor(ws.features(cases), device=dev)
+    tgt = torch.tensor(0.5 * uniform01(SEED_TRAIN + 5, 64 * 3 * 128 * 128).reshape(64, 3, 128, 128),
+                       dtype=torch.float32, device=dev)
+    idx = torch.arange(batch, dtype=torch.int32, device=dev)
+    net.train_step(feat, tgt, idx, 1e-4)
+    ms = net.profile_train(feat, tgt, idx, 1e-4, steps)
+    _, flop_train = net.flops()
+    tf = flop_train * batch / (ms * 1e-3) / 1e12
+    net.close()
+    return {"workload": f"warm-start network training step, batch {batch}, 128^2 canvas, "
+                        f"{net.nparam} parameters, synthetic targets",
+            "ms_per_step": round(ms, 4), "tflops_bf16": round(tf, 2),
+            "frac_of_bf16_dense_peak": round(tf / 2500.0, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,6 +240,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--oracle-timing", action="store_true",
                     help="only time the FP64 oracle on this host (one thread and all threads)")
+    ap.add_argument("--net-only", action="store_true",
+                    help="time only the warm-start network's training step")
     ap.add_argument("--split-only", action="store_true",
                     help="time only the divided cavity (both closures) at --split-point")
     ap.add_argument("--headline-only", action="store_true",
@@ -273,6 +303,10 @@ def main():
             torch.cuda.synchronize()
             c.close()
         print(json.dumps({"traffic_probe": "done"}), flush=True)
+        return
+
+    if args.net_only:
+        print(json.dumps({"net_training": net_training(lf, ctx)}), flush=True)
         return
 
     if args.split_only:
