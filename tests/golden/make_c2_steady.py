@@ -4,8 +4,10 @@ The 512 x 512 side-heated cavity at Ra 1e6, Pr 0.71 (U_char 0.1), seeded T0
 perturbation (uniform +-1e-6, splitmix64 seed 1908083860), run by the FP64
 oracle until the relative residual (K = 1000 steps) of u, v and T is <= 1e-8.
 Stored: the step count S_o, the final residuals, the Nusselt numbers, the
-full hot- and cold-wall temperature columns, and u, v, T sampled on every
-4th node in each direction plus their full-field maxima.
+full hot- and cold-wall temperature columns, u, v, T on every node rounded
+to FP32 (for the FP32 comparison at 1e-4 of the field maxima; the rounding
+is below 1e-7 of them), u, v, T in FP64 on every 4th node in each direction
+(for the FP64 comparison at 1e-9), and the full-field maxima.
 
     python tests/golden/make_c2_steady.py [threads]
 """
@@ -49,6 +51,7 @@ def main():
                                           "nu_cold_o2")]),
         T_west=T[:, 0].copy(), T_east=T[:, -1].copy(),
         u_s=u[::4, ::4].copy(), v_s=v[::4, ::4].copy(), T_s=T[::4, ::4].copy(),
+        u32=u.astype(np.float32), v32=v.astype(np.float32), T32=T.astype(np.float32),
         max_abs=np.array([np.abs(u).max(), np.abs(v).max(), np.abs(T).max()]))
     print(f"done: {c.steps} steps, r = {r}, Nu_hot = {nu['nu_hot']:.6f}, "
           f"{time.time() - t0:.0f} s -> {OUT}", flush=True)

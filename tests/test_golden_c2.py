@@ -38,3 +38,18 @@ def test_table1_table2_at_ra1e6(golden):
     assert abs(nu["nu_hot_max"] - ref_max) / ref_max < 0.03, (nu["nu_hot_max"], ref_max)
     assert abs(nu["y_hot_max"] - ref_y) * 512 <= 1.5 + 0.5, (nu["y_hot_max"], ref_y)
     assert abs(nu["nu_hot_o2"] - nu["nu_hot"]) / nu["nu_hot"] < 0.01
+
+
+def test_full_field_matches_the_fp64_samples(golden):
+    """The stored FP32 full fields are the FP64 steady state rounded: on every
+    4th node they equal the stored FP64 samples to FP32 rounding, their maxima
+    are the stored maxima, and T is centro-symmetric over the whole field."""
+    mx = golden["max_abs"]
+    for k, name in enumerate(("u", "v", "T")):
+        full = golden[name + "32"].astype(np.float64)
+        assert full.shape == (512, 512)
+        samp = golden[name + "_s"]
+        assert np.abs(full[::4, ::4] - samp).max() <= 2.0 ** -24 * np.abs(samp).max(), name
+        assert abs(np.abs(full).max() - mx[k]) <= 2.0 ** -24 * mx[k], name
+    T = golden["T32"].astype(np.float64)
+    assert np.abs(T + T[::-1, ::-1]).max() <= 1e-5

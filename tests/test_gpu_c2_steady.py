@@ -2,14 +2,16 @@
 oracle's steady state, stored by tests/golden/make_c2_steady.py.
 
 The GPU runs exactly the oracle's step count S_o from the same seeded T0 and
-is compared on every 4th node, on both wall columns and on the Nusselt
-numbers: the FP64 path to 1e-9; the FP32 path (shifted populations,
-compensated T) to 1e-4 on the Nusselt numbers and 5e-4 on the fields.  At
-this size the slowest modes decay by ~1e-5 per step, which amplifies FP32
-rounding noise in the fixed point (measured at S_o: u 4.3e-4, v 1.9e-4,
-T 1.4e-4, Nu 4.9e-5 of the field maxima; FP64: 5e-11).  Then the FP32 path
-runs to its own stop (residual 1e-8 or the FP32 floor rule) and its
-Nusselt number is compared with the oracle's."""
+is compared with it: the FP64 path on every 4th node (the stored FP64
+samples) and on the wall columns to 1e-9 of the field maxima; the FP32 path
+(shifted populations, compensated T) on every node (the stored field rounded
+to FP32, which moves it by less than 1e-7 of the maxima) to 1e-4; the
+Nusselt numbers to 1e-9 / 1e-4.  At this size the slowest modes decay by
+only ~1e-5 per step, which amplifies FP32 rounding that is coherent over
+regions of nodes into the fixed point; the collision's equilibrium is formed
+so that it carries none (measured at S_o over every node: u 3.7e-6, v 2.0e-6, T 8.4e-7 of
+the maxima).  Then the FP32 path runs to its own stop (residual 1e-8 or the
+FP32 floor rule) and its Nusselt number is compared with the oracle's."""
 import os
 
 import numpy as np
@@ -31,7 +33,7 @@ def golden():
     return np.load(GOLDEN)
 
 
-TOL = {"f64": (1e-9, 1e-9), "f32": (5e-4, 1e-4)}  # (fields, Nusselt numbers)
+TOL = {"f64": (1e-9, 1e-9), "f32": (1e-4, 1e-4)}  # (fields, Nusselt numbers)
 
 
 @pytest.fixture(scope="module", params=["f64", "f32"])
@@ -50,9 +52,12 @@ def test_fields_at_oracle_step_count(golden, case):
     tol = TOL[prec][0]
     u, v, T = c.fetch("u"), c.fetch("v"), c.fetch("T")
     mx = golden["max_abs"]
-    for name, a, ref, m in (("u", u, golden["u_s"], mx[0]), ("v", v, golden["v_s"], mx[1]),
-                            ("T", T, golden["T_s"], mx[2])):
-        e = np.abs(a[::4, ::4] - ref).max() / m
+    for name, a, m in (("u", u, mx[0]), ("v", v, mx[1]), ("T", T, mx[2])):
+        if prec == "f64":
+            e = np.abs(a[::4, ::4] - golden[name + "_s"]).max() / m
+        else:
+            e = np.abs(a - golden[name + "32"].astype(np.float64)).max() / m
+        print(f"{prec} {name}: max error {e:.2e} of the field maximum", flush=True)
         assert e <= tol, (prec, name, e)
     for name, a, ref in (("T_west", T[:, 0], golden["T_west"]), ("T_east", T[:, -1], golden["T_east"])):
         assert np.abs(a - ref).max() <= tol * mx[2], (prec, name)
