@@ -717,8 +717,9 @@ template <typename real, int CONV, bool ROW1>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LF_BATCH_WAVES(real, ROW1))))
 void k_batch_step(const TileDesc* __restrict__ tiles, const int* __restrict__ ntiles,
                   const CavDesc<real>* __restrict__ cavs, int parity, int write_mom) {
-  // The grid is sized for the largest tile table (band 1, all cavities
-  // live); only the first ceil(live / waves-per-block) blocks have work.
+  // The grid covers the live tile table (between one and two times its
+  // size, so a graph captured for it serves a shrinking set); only the
+  // first ceil(live / waves-per-block) blocks have work.
   // Those are spread round-robin over the 8 XCDs, so the XCD-contiguous
   // renumbering is taken over them alone: taken over the whole grid it
   // would hand every live tile to the first XCDs.

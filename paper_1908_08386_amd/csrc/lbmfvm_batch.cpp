@@ -76,8 +76,13 @@ struct lf_batch {
   int counts[3];
   std::vector<unsigned char> cavdesc;
   int row1;  // every live tile is a single row (the step kernel's 5-wave form)
+  // tiles the step launches are sized for: at least the live table, and
+  // re-sized when the table outgrows it or falls below half of it, so a
+  // shrinking live set is recaptured O(log) times while blocks with no tile
+  // stay under half of the grid
+  int grid_tiles;
   hipGraphExec_t gexec;
-  int graph_K, graph_row1;
+  int graph_K, graph_row1, graph_tiles;
   bool inited;
 };
 
@@ -212,6 +217,8 @@ static lf_status upload_tables(lf_batch* b) {
   for (const auto& t : b->tiles)
     if (t.j1 - t.j0 != 1) b->row1 = 0;
   b->counts[0] = (int)b->tiles.size();
+  if (b->counts[0] > b->grid_tiles || 2 * b->counts[0] < b->grid_tiles)
+    b->grid_tiles = b->counts[0] > 0 ? b->counts[0] : 1;
   b->counts[1] = (int)b->rts.size();
   b->counts[2] = (int)b->folds.size();
   if (b->precision == LF_F32) fill_desc<float>(b);
@@ -245,7 +252,7 @@ static hipError_t enqueue_steps(lf_batch* b, int64_t k0, int64_t n, bool write_m
   for (int64_t k = 0; k < n; ++k) {
     hipError_t e = lf::launch_batch_step<real>(
         (const lf::TileDesc*)(b->ws + b->off_tiles), (const int*)(b->ws + b->off_ntiles),
-        b->max_tiles, d, (int)((k0 + k) & 1), (write_mom_last && k == n - 1) ? 1 : 0, 0,
+        b->grid_tiles, d, (int)((k0 + k) & 1), (write_mom_last && k == n - 1) ? 1 : 0, 0,
         b->row1, b->ctx->stream);
     if (e != hipSuccess) return e;
   }
@@ -275,10 +282,11 @@ static void drop_graph(lf_batch* b) {
   b->graph_K = 0;
 }
 
-// K steps (K even) followed by the batched residual, captured once per K and
-// per form of the step kernel
+// K steps (K even) followed by the batched residual, captured once per K,
+// per form of the step kernel and per grid size
 static lf_status ensure_graph(lf_batch* b, int K) {
-  if (b->gexec && b->graph_K == K && b->graph_row1 == b->row1) return LF_OK;
+  if (b->gexec && b->graph_K == K && b->graph_row1 == b->row1 && b->graph_tiles == b->grid_tiles)
+    return LF_OK;
   drop_graph(b);
   hipStream_t s = b->ctx->stream;
   LF_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -298,6 +306,7 @@ static lf_status ensure_graph(lf_batch* b, int K) {
   }
   b->graph_K = K;
   b->graph_row1 = b->row1;
+  b->graph_tiles = b->grid_tiles;
   return LF_OK;
 }
 
