@@ -229,6 +229,52 @@ def net_training(lf, ctx, steps=100, batch=32):
             "frac_of_bf16_dense_peak": round(tf / 2500.0, 4)}
 
 
+def sweep_to_steady(lf, ctx, cases, T0s, budget_s, chunk=20000, max_steps=3_000_000):
+    """The sweep's cavities in one batch, each run to steady state (residual
+    1e-8 per 1000 steps or the FP32 floor rule) from the cold start, in calls
+    of `chunk` more steps: per call the cavities still live, their nodes and
+    the aggregate node-update rate (the throughput as cavities retire), then
+    each cavity's steps and stop rule.  Stops after `budget_s` seconds of
+    stepping with the cavities still live reported as such."""
+    import numpy as np
+    n = len(cases)
+    nodes = np.array([c["nx"] * c["ny"] for c in cases], dtype=np.int64)
+    bt = lf.Batch(ctx, cases, "f32").init(T0s)
+    steps = np.zeros(n, dtype=np.int64)
+    rules = np.zeros(n, dtype=np.int64)
+    curve, spent, limit = [], 0.0, 0
+    while limit < max_steps and spent < budget_s:
+        live = (rules == 0) & (steps < max_steps)
+        if not live.any():
+            break
+        limit += chunk
+        t0 = time.perf_counter()
+        st, ru, _ = bt.run_to_steady(1e-8, 1000, limit, raise_on_notconv=False)
+        dt = time.perf_counter() - t0
+        spent += dt
+        lu = float(((st - steps) * nodes).sum())
+        steps, rules = np.asarray(st, dtype=np.int64), np.asarray(ru, dtype=np.int64)
+        point = {"t_s": round(spent, 2), "steps_limit": limit, "live_at_start": int(live.sum()),
+                 "live_mnodes_at_start": round(float(nodes[live].sum()) / 1e6, 2),
+                 "stopped": int((rules != 0).sum()), "mlups": round(lu / dt / 1e6, 1)}
+        curve.append(point)
+        print(json.dumps({"sweep_to_steady_progress": point}), flush=True)
+    bt.close()
+    done = rules != 0
+    return {
+        "workload": f"{n} sweep cavities (the headline's), FP32 Mode H, cold start (T0 = 1e-6 noise), "
+                    f"to residual 1e-8 per 1000 steps or the FP32 floor rule, one batch, calls of "
+                    f"{chunk} steps, step limit {max_steps}",
+        "seconds": round(spent, 2), "node_updates": float((steps * nodes).sum()),
+        "mean_mlups": round(float((steps * nodes).sum()) / spent / 1e6, 1) if spent > 0 else None,
+        "stopped": int(done.sum()), "by_tolerance": int((rules == lf.STOP_TOL).sum()),
+        "by_floor_rule": int((rules == lf.STOP_FLOOR).sum()), "diverged": int((rules < 0).sum()),
+        "steps_median_stopped": int(np.median(steps[done])) if done.any() else None,
+        "steps_max_stopped": int(steps[done].max()) if done.any() else None,
+        "curve": curve, "steps_each": steps.tolist(), "rule_each": rules.tolist(),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -260,6 +306,9 @@ def main():
                          "(0 = skip)")
     ap.add_argument("--time-to-steady", type=int, default=1,
                     help="also time cold and learned (warm) starts to steady state (0 = skip)")
+    ap.add_argument("--sweep-to-steady", type=float, default=0.0, metavar="SECONDS",
+                    help="only run the sweep's cavities to steady state for at most SECONDS of "
+                         "stepping, printing the throughput as cavities retire (0 = skip)")
     ap.add_argument("--heldout", type=int, default=16,
                     help="held-out cavities (ny <= 128) in the batched warm/cold comparison")
     args = ap.parse_args()
@@ -307,6 +356,11 @@ def main():
 
     if args.net_only:
         print(json.dumps({"net_training": net_training(lf, ctx)}), flush=True)
+        return
+
+    if args.sweep_to_steady > 0:
+        print(json.dumps({"sweep_to_steady": sweep_to_steady(lf, ctx, cases, T0s,
+                                                             args.sweep_to_steady)}), flush=True)
         return
 
     if args.split_only:
