@@ -34,12 +34,18 @@ METRIC = "coupled LBM-FVM MLUPS + %HBM peak; time-to-steady (warm vs cold) at Nu
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 BYTES_PER_LU_F32 = 80.0        # 9 f read + 9 f write + T read + T write, 4 B each
 PROFILES = os.path.join(ROOT, "profiles")
-KERNEL_SRC = os.path.join(ROOT, "paper_1908_08386_amd", "csrc", "k_hybrid.hip")
+# the step kernels and the host rules that shape their launches and layout
+# (rows per wave, plane stride): counters taken on other sources are stale
+KERNEL_SRC = [os.path.join(ROOT, "paper_1908_08386_amd", "csrc", f)
+              for f in ("k_hybrid.hip", "lf_host.h")]
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for p in KERNEL_SRC:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(name, key):

@@ -184,7 +184,10 @@ lf_status lf_ctx_set_band(lf_ctx* ctx, int rows);
  * T = +1/2, east T = -1/2, south/north adiabatic, all no-slip at rest).
  * LF_EINVAL for an unknown mode, nx or ny < 8, an odd or < 12 divided
  * extent (nx for LF_MODE_SPLIT, ny for LF_MODE_SPLIT_H), odd nx or ny for
- * LF_MODE_HYBRID_GS2, or a grid too large for 32-bit plane indexing.      */
+ * LF_MODE_HYBRID_GS2, or a grid whose nine population planes (each
+ * pitch x ny elements plus a small pad, pitch = nx rounded up to 64) reach
+ * 2^31 elements or 4 GiB (32-bit element and byte offsets): FP32 up to about
+ * 119 M nodes, FP64 up to about 59 M.                                     */
 lf_status lf_case_create(lf_ctx* ctx, const lf_case_desc* desc, lf_case** out);
 lf_status lf_case_destroy(lf_case* c);
 lf_status lf_case_workspace_bytes(const lf_case* c, size_t* bytes);

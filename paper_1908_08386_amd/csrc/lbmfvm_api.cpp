@@ -331,8 +331,9 @@ lf_status lf_case_create(lf_ctx* ctx, const lf_case_desc* d, lf_case** out) {
       return fail(LF_EINVAL, "bad iface %d", d->iface);
   }
   const long long pitch = (d->nx + 63) / 64 * 64;
-  const long long plane = pitch * d->ny;
-  if (9 * plane >= (1LL << 31)) return fail(LF_EINVAL, "grid too large for 32-bit plane indexing");
+  const long long plane = lf_plane_elems(pitch, d->ny);
+  if (!lf_planes_fit(plane, d->precision == LF_F64 ? 8 : 4))
+    return fail(LF_EINVAL, "grid too large: nine planes must stay under 4 GiB and 2^31 elements");
   lf_case* c = new (std::nothrow) lf_case;
   if (!c) return fail(LF_ENOMEM, "case allocation");
   memset(c, 0, sizeof(*c));

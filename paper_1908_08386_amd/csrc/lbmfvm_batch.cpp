@@ -343,10 +343,10 @@ lf_status lf_batch_create(lf_ctx* ctx, int n, const lf_case_desc* descs, const l
     c.nx = d.nx;
     c.ny = d.ny;
     c.pitch = (d.nx + 63) / 64 * 64;
-    c.plane = (long long)c.pitch * d.ny;
-    if (9 * c.plane >= (1LL << 31)) {
+    c.plane = lf_plane_elems(c.pitch, d.ny);
+    if (!lf_planes_fit(c.plane, b->es)) {
       delete b;
-      return lf_fail(LF_EINVAL, "cavity %d too large", k);
+      return lf_fail(LF_EINVAL, "cavity %d too large: nine planes must stay under 4 GiB", k);
     }
     lf_status st = lf_derive_params(&phys[k], d.ny, 0, c.prm);
     if (st != LF_OK) {

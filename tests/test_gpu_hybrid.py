@@ -302,6 +302,10 @@ def test_errors(lf, ctx):
     with pytest.raises(lf.LFError) as e:
         lf.Case(ctx, 4, 16)
     assert e.value.status == lf.LF_EINVAL
+    # nine FP64 planes of 8192^2 exceed the step kernels' 32-bit byte range
+    with pytest.raises(lf.LFError) as e:
+        lf.Case(ctx, 8192, 8192, "f64")
+    assert e.value.status == lf.LF_EINVAL
     # NaN input is reported by the residual
     g.set_lattice(0.1, 0.1).set_cavity_walls()
     T0 = np.zeros((16, 16))
