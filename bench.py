@@ -207,6 +207,26 @@ def split_closures(lf, ctx, m, out):
         del sp
 
 
+def gs2_point(lf, ctx, m):
+    """Mode H on grid setting 2: lattice on all m x m nodes, temperature on
+    2 x 2 control volumes, one implicit energy step per 2NX = m lattice steps,
+    timed over whole cycles (so the energy step is included)."""
+    from synth_inputs import SEED_C2, perturbation
+    g2 = lf.Case(ctx, m, m, "f32", mode=lf.MODE_HYBRID_GS2).set_physics(1e6, 0.71)
+    g2.set_cavity_walls().init(perturbation(m, m, SEED_C2))
+    g2.step(m)
+    a_ms, _, _ = g2.profile_steps(m)
+    g2.close()
+    ach = 76.0 * m * m / (a_ms * 1e-3) / 1e9
+    return {"workload": f"{m}x{m} cavity, grid setting 2 ({m // 2}x{m // 2} control volumes), "
+                        f"Ra 1e6, Pr 0.71, FP32, one energy step (4 line sweeps) per {m} "
+                        f"lattice steps",
+            "ms_per_step": round(a_ms, 5),
+            "mlups": round(m * m / (a_ms * 1e-3) / 1e6, 1),
+            "achieved_GBs_at_76B": round(ach, 1),
+            "frac_of_8TBs": round(ach / HBM_PEAK_GBS, 4)}
+
+
 def net_training(lf, ctx, steps=100, batch=32):
     """The warm-start network's training step (forward, both backward passes
     and Adam on a mini-batch of `batch` canvases) on synthetic targets:
@@ -296,6 +316,8 @@ def main():
                     help="time only the warm-start network's training step")
     ap.add_argument("--split-only", action="store_true",
                     help="time only the divided cavity (both closures) at --split-point")
+    ap.add_argument("--gs2-only", action="store_true",
+                    help="time only grid setting 2 at --split-point")
     ap.add_argument("--headline-only", action="store_true",
                     help="time the headline workload only (for profiler runs)")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -367,6 +389,11 @@ def main():
     if args.sweep_to_steady > 0:
         print(json.dumps({"sweep_to_steady": sweep_to_steady(lf, ctx, cases, T0s,
                                                              args.sweep_to_steady)}), flush=True)
+        return
+
+    if args.gs2_only:
+        print(json.dumps({"gs2_point": gs2_point(lf, ctx, args.split_point or 4096)}),
+              flush=True)
         return
 
     if args.split_only:
@@ -505,23 +532,7 @@ def main():
                         "frac_of_8TBs": round(ach / HBM_PEAK_GBS, 4)}
             pc.close()
             del pc
-        # Mode H on grid setting 2: lattice on all nodes, temperature on 2 x 2
-        # control volumes, one implicit energy step per 2NX = m lattice steps
-        # (timed over whole cycles, so the energy step is included)
-        g2 = lf.Case(ctx, m, m, "f32", mode=lf.MODE_HYBRID_GS2).set_physics(1e6, 0.71)
-        g2.set_cavity_walls().init(perturbation(m, m, SEED_C2))
-        g2.step(m)
-        a_ms, _, _ = g2.profile_steps(m)
-        ach = 76.0 * m * m / (a_ms * 1e-3) / 1e9
-        out["gs2_point"] = {"workload": f"{m}x{m} cavity, grid setting 2 ({m // 2}x{m // 2} "
-                                        f"control volumes), Ra 1e6, Pr 0.71, FP32, one energy "
-                                        f"step (4 line sweeps) per {m} lattice steps",
-                            "ms_per_step": round(a_ms, 5),
-                            "mlups": round(m * m / (a_ms * 1e-3) / 1e6, 1),
-                            "achieved_GBs_at_76B": round(ach, 1),
-                            "frac_of_8TBs": round(ach / HBM_PEAK_GBS, 4)}
-        g2.close()
-        del g2
+        out["gs2_point"] = gs2_point(lf, ctx, m)
         # LBM-MCM (Sec. 6): 128^2, one Monte Carlo solve of 1024 walkers per
         # node after every 100 lattice steps, timed over whole cycles
         mm, S, N = 128, 100, 1024

@@ -1429,7 +1429,7 @@ static SplitArgs<real> make_args(const SplitGeom& G, const SplitPtrs<real>& P, c
   a.mom = P.mom;
   a.xf = P.xf;
   a.pL = G.pL;
-  a.planeL = G.pL * G.ny;
+  a.planeL = G.planeL;
   a.nl = G.fv_only ? 0 : (G.lbm_only || G.gs2 || G.mcm) ? G.nx : G.ib + 1;
   a.u = P.u[cur];
   a.v = P.v[cur];

@@ -32,7 +32,7 @@ struct HybridParams {
 // Geometry of one cavity's planes inside the workspace.
 struct Grid {
   int nx, ny, pitch;  // pitch: row stride in elements (multiple of 64)
-  long long plane;    // elements per plane = ny * pitch
+  long long plane;    // elements between successive planes: ny * pitch plus a pad
 };
 
 // ---- batched Mode H -------------------------------------------------------
@@ -139,6 +139,7 @@ namespace lf {
 // pitch pC), with s = ib = nx like lbm_only.
 struct SplitGeom {
   int nx, ny, s, c0, ib, pL, pF;
+  int planeL;  // elements between successive LBM-zone planes (ny * pL plus a pad)
   int fv_only, lbm_only;
   int gs2, NXc, NYc, pC;
   // horizontally divided cavity: stored transposed (the caller's x is the
@@ -151,7 +152,7 @@ struct SplitGeom {
 
 template <typename real>
 struct SplitPtrs {
-  real* f[2];   // 9 planes of ny * pL each (shifted populations)
+  real* f[2];   // 9 planes, planeL apart (shifted populations)
   real* g[2];   // 5 planes
   real* mom;    // rho, u, v, T planes of the LBM zone
   real* xf;     // 18 values per row: streamed state of column ib - 1
