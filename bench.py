@@ -227,6 +227,24 @@ def gs2_point(lf, ctx, m):
             "frac_of_8TBs": round(ach / HBM_PEAK_GBS, 4)}
 
 
+def mcm_point(lf, ctx, mm=128, S=100, N=1024):
+    """LBM-MCM (Sec. 6): an mm x mm cavity, one Monte Carlo solve of N
+    walkers per node after every S lattice steps, timed over whole cycles."""
+    from synth_inputs import SEED_C2, perturbation
+    mc = lf.Case(ctx, mm, mm, "f32", mode=lf.MODE_LBM_MCM).set_physics(1e4, 0.71)
+    mc.set_cavity_walls().set_mcm(S, N).init(perturbation(mm, mm, SEED_C2))
+    mc.step(S)
+    a_ms, _, _ = mc.profile_steps(S)
+    capped = mc.mcm_capped()
+    mc.close()
+    return {"workload": f"{mm}x{mm} cavity, LBM-MCM, Ra 1e4, Pr 0.71, FP32 lattice, {N} walkers "
+                        f"per node, one solve per {S} lattice steps",
+            "ms_per_cycle": round(a_ms * S, 3),
+            "ms_per_step": round(a_ms, 5),
+            "mlups": round(mm * mm / (a_ms * 1e-3) / 1e6, 1),
+            "capped_walkers": capped}
+
+
 def net_training(lf, ctx, steps=100, batch=32):
     """The warm-start network's training step (forward, both backward passes
     and Adam on a mini-batch of `batch` canvases) on synthetic targets:
@@ -318,6 +336,8 @@ def main():
                     help="time only the divided cavity (both closures) at --split-point")
     ap.add_argument("--gs2-only", action="store_true",
                     help="time only grid setting 2 at --split-point")
+    ap.add_argument("--mcm-only", action="store_true",
+                    help="time only the LBM-MCM cavity (128^2, 1024 walkers per node)")
     ap.add_argument("--headline-only", action="store_true",
                     help="time the headline workload only (for profiler runs)")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -389,6 +409,10 @@ def main():
     if args.sweep_to_steady > 0:
         print(json.dumps({"sweep_to_steady": sweep_to_steady(lf, ctx, cases, T0s,
                                                              args.sweep_to_steady)}), flush=True)
+        return
+
+    if args.mcm_only:
+        print(json.dumps({"mcm_point": mcm_point(lf, ctx)}), flush=True)
         return
 
     if args.gs2_only:
@@ -533,22 +557,7 @@ def main():
             pc.close()
             del pc
         out["gs2_point"] = gs2_point(lf, ctx, m)
-        # LBM-MCM (Sec. 6): 128^2, one Monte Carlo solve of 1024 walkers per
-        # node after every 100 lattice steps, timed over whole cycles
-        mm, S, N = 128, 100, 1024
-        mc = lf.Case(ctx, mm, mm, "f32", mode=lf.MODE_LBM_MCM).set_physics(1e4, 0.71)
-        mc.set_cavity_walls().set_mcm(S, N).init(perturbation(mm, mm, SEED_C2))
-        mc.step(S)
-        a_ms, _, _ = mc.profile_steps(S)
-        out["mcm_point"] = {"workload": f"{mm}x{mm} cavity, LBM-MCM, Ra 1e4, Pr 0.71, FP32 "
-                                        f"lattice, {N} walkers per node, one solve per {S} "
-                                        "lattice steps",
-                            "ms_per_cycle": round(a_ms * S, 3),
-                            "ms_per_step": round(a_ms, 5),
-                            "mlups": round(mm * mm / (a_ms * 1e-3) / 1e6, 1),
-                            "capped_walkers": mc.mcm_capped()}
-        mc.close()
-        del mc
+        out["mcm_point"] = mcm_point(lf, ctx)
 
     if args.lid_point:
         # lid-driven cavity (Sec. 3.3; the paper's grid is 160 x 160), hybrid
