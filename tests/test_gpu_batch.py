@@ -149,6 +149,11 @@ def test_batch_errors(lf, ctx):
     with pytest.raises(lf.LFError) as e:
         b.run_to_steady(check_every=999)
     assert e.value.status == lf.LF_EINVAL
+    # a cavity whose nine FP64 planes exceed the step kernel's 32-bit byte range
+    big = {"nx": 8192, "ny": 8192, "Ra": 1e6, "Pr": 0.71}
+    with pytest.raises(lf.LFError) as e:
+        lf.Batch(ctx, [CASES[0], big], "f64")
+    assert e.value.status == lf.LF_EINVAL
 
 
 def first_of_each_class(sweep):
