@@ -196,14 +196,17 @@ __device__ __forceinline__ real P_at(const SplitArgs<real>& a, int x, int j) {
 //                         running sum, read by the step of parity p (the
 //                         step writes them for the next one into the other
 //                         pair, so no block reads what another one writes);
-//   from kIfacePart       per block of kIfBlock rows: the ghost sums of the
+//   from kIfacePart       per unit of kIfBlock rows: the ghost sums of the
 //                         steps of parity 0 and of parity 1 (inflow face,
 //                         density over the shared columns), then the p_bar
 //                         sums (pressure over the shared columns, mass flux).
-// Every consumer adds the per-block sums in block order itself, so all of
-// them hold the same bits and no launch is spent on folding.
+// Every consumer folds the per-unit sums itself, in one fixed order (fold_units),
+// so all of them hold the same bits and no launch is spent on folding.  A
+// unit is one wave, a thread per row: every access of the interface's
+// kernels is row-strided (a cache line per value), so small units spread
+// those lines over many CUs.
 constexpr int kIfacePart = 8;
-constexpr int kIfBlock = 256;  // rows per interface block (one thread per row)
+constexpr int kIfBlock = 64;  // rows per interface unit (one wave, one thread per row)
 
 __host__ __device__ __forceinline__ int iface_blocks(int ny) {
   return (ny + 1 + kIfBlock - 1) / kIfBlock;  // rows and y-faces 0 .. ny
@@ -215,34 +218,28 @@ __device__ __forceinline__ double* pbar_sums(double* iface, int ny) {
   return iface + kIfacePart + 4 * iface_blocks(ny);
 }
 
-// Sums of two per-row terms over the block's rows in a fixed order: a
-// butterfly over each wave (every lane ends with the same bits: IEEE
-// addition commutes), then the waves' sums in order.  Valid in thread 0.
-__device__ __forceinline__ void block_sum2(double t0, double t1, double (*sh)[kIfBlock / 64],
-                                           double& s0, double& s1) {
+// Sums of two per-row terms over a unit's rows (one wave) in a fixed order:
+// a butterfly, after which every lane holds the same bits (IEEE addition
+// commutes).
+static_assert(kIfBlock == 64, "an interface unit is one wave");
+__device__ __forceinline__ void wave_sum2(double& t0, double& t1) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     t0 += __shfl_xor(t0, off, 64);
     t1 += __shfl_xor(t1, off, 64);
   }
-  if ((threadIdx.x & 63) == 0) {
-    sh[0][threadIdx.x >> 6] = t0;
-    sh[1][threadIdx.x >> 6] = t1;
-  }
-  __syncthreads();
-  s0 = sh[0][0];
-  s1 = sh[1][0];
-#pragma unroll
-  for (int w = 1; w < kIfBlock / 64; ++w) {
-    s0 += sh[0][w];
-    s1 += sh[1][w];
-  }
 }
 
-// In-order sum of the first (k = 0) or second (k = 1) of n per-block pairs.
-__device__ __forceinline__ double fold_pairs(const double* __restrict__ sums, int n, int k) {
+// Sum of the first (k = 0) or second (k = 1) of n per-unit pairs, in one
+// fixed order: lane l adds pairs l, l + 64, ... in turn, then the lanes'
+// partials are added by a butterfly.  Called by all 64 lanes of a wave; every
+// lane of every caller gets the same bits.
+__device__ __forceinline__ double fold_units(const double* __restrict__ sums, int n, int k) {
+  const int lane = (int)(threadIdx.x & 63);
   double t = 0.0;
-  for (int b = 0; b < n; ++b) t += sums[2 * b + k];
+  for (int b = lane; b < n; b += 64) t += sums[2 * b + k];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
   return t;
 }
 
@@ -544,7 +541,7 @@ __global__ __launch_bounds__(256) void k_dd_fv(SplitArgs<real> a0, FvRegion R) {
   // the mean of the inflow face the boundary-node launch stored, from its
   // per-block sums in block order (the same bits in every wave)
   SplitArgs<real> a = a0;
-  a.umean = IFACE ? (real)(fold_pairs(ghost_sums(a.iface, a.ny, a.par), iface_blocks(a.ny), 0) /
+  a.umean = IFACE ? (real)(fold_units(ghost_sums(a.iface, a.ny, a.par), iface_blocks(a.ny), 0) /
                            a.ny)
                   : real(0);
   // blocks renumbered so that each XCD works on a contiguous range
@@ -660,7 +657,8 @@ __global__ __launch_bounds__(256) void k_dd_fv(SplitArgs<real> a0, FvRegion R) {
   }
 }
 
-// 4. p_bar sums of block b of the interface's rows (b < iface_blocks): the
+// 4. p_bar sums of unit b of the interface's rows (b < iface_blocks; one
+//    wave): the
 //    new FV pressure over the shared columns, and the net mass this step's
 //    stream moves into the LBM zone through the links to x_b: the
 //    post-collision populations x_b sent west (W, NW, SW) less those x_f
@@ -671,10 +669,9 @@ __global__ __launch_bounds__(256) void k_dd_fv(SplitArgs<real> a0, FvRegion R) {
 //    does not write).
 template <typename real>
 __device__ void pbar_block(const SplitArgs<real>& a, int b) {
-  __shared__ double sh[2][kIfBlock / 64];
   const int ny = a.ny, ib = a.ib;
-  if (b >= iface_blocks(ny)) return;  // uniform per block
-  const int j = b * kIfBlock + (int)threadIdx.x;
+  if (b >= iface_blocks(ny)) return;  // uniform per wave
+  const int j = b * kIfBlock + (int)(threadIdx.x & 63);
   double ps = 0.0, fl = 0.0;
   if (j < ny) {
     for (int x = a.c0; x <= ib; ++x) ps += (double)a.p[j * a.pF + fidx(a, x)];
@@ -690,12 +687,11 @@ __device__ void pbar_block(const SplitArgs<real>& a, int b) {
     }
     fl = in - out;
   }
-  double bs, bf;
-  block_sum2(ps, fl, sh, bs, bf);
-  if (threadIdx.x == 0) {
+  wave_sum2(ps, fl);
+  if ((threadIdx.x & 63) == 0) {
     double* out = pbar_sums(a.iface, ny);
-    out[2 * b] = bs;
-    out[2 * b + 1] = bf;
+    out[2 * b] = ps;
+    out[2 * b + 1] = fl;
   }
 }
 
@@ -775,9 +771,10 @@ __device__ __forceinline__ void moments9(const real f[9], real& drho, real& ux, 
 
 template <typename real>
 __global__ __launch_bounds__(256) void k_dd_lbm(SplitArgs<real> a, int pbar_rows) {
-  // the first pbar_rows rows of blocks (dispatched first) form the p_bar sums
+  // the first pbar_rows rows of blocks (dispatched first) form the p_bar
+  // sums, one unit per wave
   if ((int)blockIdx.y < pbar_rows) {
-    pbar_block(a, blockIdx.y * gridDim.x + blockIdx.x);
+    pbar_block(a, (int)(blockIdx.y * gridDim.x + blockIdx.x) * 4 + (int)(threadIdx.x >> 6));
     return;
   }
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
@@ -949,33 +946,27 @@ __device__ __forceinline__ void ghost_row(const SplitArgs<real>& a, int j, doubl
 }
 
 // The interface's end of a step (one thread per row and y-face):
-//  (a) unless ghost_only: every block adds the per-block sums in order --
+//  (a) unless ghost_only: every unit folds the per-unit sums (fold_units) --
 //      p_bar, the mean new FV pressure over the shared columns (written by
 //      the LBM launch), the net mass this step's stream moved into the LBM
 //      zone through the links to x_b (same launch), and rho0, the mean LBM
 //      density over the shared columns at the start of the step (the ghost
-//      sums of this step's parity); block 0 stores the zone's new mass
+//      sums of this step's parity); unit 0 stores the zone's new mass
 //      change and running sum for the next step; then x_b of its row;
-//  (b) the ghost values of the next step (ghost_row) and the block's sums
-//      of them (the ghost sums of the next parity); the next FV launch adds
-//      the inflow sums in order and removes their mean where it reads the
-//      inflow face (umean).
+//  (b) the ghost values of the next step (ghost_row) and the unit's sums
+//      of them (the ghost sums of the next parity); the next FV launch folds
+//      the inflow sums and removes their mean where it reads the inflow face
+//      (umean).
 // ghost_only (at init, with the arguments of parity 1, so that the values
 // land in the buffers and sums step 0 reads) runs (b) alone.
 template <typename real>
 __global__ __launch_bounds__(kIfBlock) void k_dd_xb(SplitArgs<real> a, int ghost_only) {
-  __shared__ double sh[2][kIfBlock / 64];
-  __shared__ double fold[3];
   const int ny = a.ny, nb = (int)gridDim.x;
   const int j = blockIdx.x * kIfBlock + threadIdx.x;
   if (!ghost_only) {
-    if (threadIdx.x == 0) {
-      const double* ps = pbar_sums(a.iface, ny);
-      fold[0] = fold_pairs(ps, nb, 0);
-      fold[1] = fold_pairs(ps, nb, 1);
-      fold[2] = fold_pairs(ghost_sums(a.iface, ny, a.par), nb, 1);
-    }
-    __syncthreads();
+    const double* ps = pbar_sums(a.iface, ny);
+    const double fold[3] = {fold_units(ps, nb, 0), fold_units(ps, nb, 1),
+                            fold_units(ghost_sums(a.iface, ny, a.par), nb, 1)};
     const double pbar = fold[0] / (3.0 * ny), rho0 = fold[2] / (3.0 * ny);
     const int sl = 2 + 2 * (a.par & 1), sn = 2 + 2 * ((a.par & 1) ^ 1);
     const double mchange = a.iface[sl] + fold[1];  // the zone's mass change since init
@@ -988,12 +979,11 @@ __global__ __launch_bounds__(kIfBlock) void k_dd_xb(SplitArgs<real> a, int ghost
   }
   double su, sr;
   ghost_row(a, j, su, sr);
-  double bu, br;
-  block_sum2(su, sr, sh, bu, br);
+  wave_sum2(su, sr);
   if (threadIdx.x == 0) {
     double* gn = ghost_sums(a.iface, ny, a.par ^ 1);
-    gn[2 * blockIdx.x] = bu;
-    gn[2 * blockIdx.x + 1] = br;
+    gn[2 * blockIdx.x] = su;
+    gn[2 * blockIdx.x + 1] = sr;
   }
 }
 
@@ -1417,6 +1407,10 @@ __global__ __launch_bounds__(256) void k_mcm_finish(SplitArgs<real> a) {
 
 }  // namespace
 
+// doubles of the interface record for ny rows: the scalars, then per unit
+// the ghost sums of both parities and the p_bar sums
+int split_iface_doubles(int ny) { return kIfacePart + 6 * iface_blocks(ny); }
+
 template <typename real>
 static SplitArgs<real> make_args(const SplitGeom& G, const SplitPtrs<real>& P, const SplitParams& S,
                                  int cur, int mom_all) {
@@ -1548,7 +1542,7 @@ hipError_t launch_split_step(const SplitGeom& G, const SplitPtrs<real>& P, const
   else launch_fv<real, 0>(a, R, s);
   if (split) {
     // the LBM zone, after rows of blocks for the p_bar sums
-    const int nbx = (G.ib + 63) / 64, pr = (iface_blocks(G.ny) + nbx - 1) / nbx;
+    const int nbx = (G.ib + 63) / 64, pr = (iface_blocks(G.ny) + 4 * nbx - 1) / (4 * nbx);
     hipLaunchKernelGGL(k_dd_lbm<real>, dim3(nbx, (G.ny + 3) / 4 + pr), dim3(256), 0, s, a, pr);
     hipLaunchKernelGGL(k_dd_xb<real>, dim3(iface_blocks(G.ny)), dim3(kIfBlock), 0, s, a, 0);
   }

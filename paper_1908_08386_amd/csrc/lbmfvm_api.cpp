@@ -95,11 +95,10 @@ static void layout_split(lf_case* c) {
   for (int k = 0; k < 2; ++k) { c->off_sT[k] = o; o += pbF; }
   c->off_sp[0] = o; o += pbF;
   c->off_sp[1] = o; o += pbF;
-  // interface scalars, then two sums per 256-row block of the ghost kernel
-  // interface scalars, then per 256 rows two ghost sums of each parity and
-  // two p_bar sums
+  // interface scalars, then per unit of rows two ghost sums of each parity
+  // and two p_bar sums
   c->off_siface = o;
-  o += align_up((size_t)(8 + 6 * ((G.ny + 1 + 255) / 256)) * sizeof(double), 256);
+  o += align_up((size_t)lf::split_iface_doubles(G.ny) * sizeof(double), 256);
   for (int k = 0; k < 10; ++k) {
     c->off_gs2[k] = o;
     if (G.gs2) o += align_up((size_t)G.pC * G.NYc * c->es, 256);

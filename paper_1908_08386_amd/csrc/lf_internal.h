@@ -161,8 +161,9 @@ struct SplitPtrs {
   real* T[2];   // centres
   real* p[2];   // centres (ping-pong: each FV step reads one and writes the other)
   double* iface;  // interface scalars (the LBM zone's mass change since init
-                  // and its running sum), from [8] per 256 rows the ghost sums
+                  // and its running sum), from [8] per 64 rows the ghost sums
                   // of both step parities and the p_bar sums
+                  // (split_iface_doubles(ny) doubles in all)
   // grid setting 2, NYc rows * pC each: T (iterate A), T (iterate B),
   // a_P, a_W, a_E, a_S, a_N, b, and the Thomas sweep's c', r'
   real* gc[10];
@@ -181,6 +182,9 @@ struct SplitParams {
   double Tw[4];
   double ulid;  // tangential velocity of the north wall (split, FV-only, LBM-only)
 };
+
+// doubles of the split mode's interface record (SplitPtrs::iface) for ny rows
+int split_iface_doubles(int ny);
 
 // One step; the state is read from buffers [cur] and written to [cur ^ 1].
 // mom_all: write the moments of every LBM node (else only the shared and
