@@ -35,16 +35,25 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 BYTES_PER_LU_F32 = 80.0        # 9 f read + 9 f write + T read + T write, 4 B each
 PROFILES = os.path.join(ROOT, "profiles")
 # the step kernels and the host rules that shape their launches and layout
-# (rows per wave, plane stride): counters taken on other sources are stale
+# (rows per wave, plane stride): counters taken on other code are stale
 KERNEL_SRC = [os.path.join(ROOT, "paper_1908_08386_amd", "csrc", f)
               for f in ("k_hybrid.hip", "lf_host.h")]
 
 
-def kernel_hash() -> str:
+def _code_only(text: str) -> str:
+    """C/C++ source with comments and whitespace removed (string literals in
+    these files hold no comment markers)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return "".join(text.split())
+
+
+def kernel_hash(paths=None) -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SRC:
-        with open(p, "rb") as f:
-            h.update(f.read())
+    for p in paths or KERNEL_SRC:
+        with open(p, encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -29,12 +29,14 @@ static inline int lf_rows_per_wave(long long row_waves) {
   return row_waves <= 24576 ? 1 : 4;
 }
 
-// Elements between successive planes of a Mode H cavity (row pitch = nx
-// rounded up to 64): the plane plus 2112 elements (33 x 256 B in FP32).
-// Planes a power of two apart put a node's nine populations on the same
-// DRAM address bits; an odd number of 256-byte units between them measured
-// 1.6-2.1 % faster on the 256-cavity sweep and 0.5-1.8 % on 2048^2 and
-// 4096^2 (the pad's size mattered little: 320 to 4160 elements).
+// Elements between successive planes of a cavity's populations (row pitch
+// = nx rounded up to 64): the plane plus 2112 elements (33 x 256 B in FP32).
+// The usual 2^k-sized cavities otherwise have planes a power of two apart,
+// which puts a node's nine populations on the same DRAM address bits; the
+// pad moves them off it (a stride can still land on a power of two for a
+// rare shape, e.g. 64 x 223 in FP32).  Measured 1.6-2.1 % faster on the
+// 256-cavity sweep and 0.5-1.8 % on 2048^2 and 4096^2 (the pad's size
+// mattered little: 320 to 4160 elements).
 static inline long long lf_plane_elems(long long pitch, int ny) {
   return pitch * ny + 2112;
 }

@@ -202,3 +202,26 @@ def test_slow_mode_of_the_side_heated_cavity(tmp_path):
     assert abs(got - np.exp(-10 * 0.25 * pi2 / 100 ** 2)) < 1e-15
     got = lam(1.0, 5.0, 100, 100, 0, 0, 0, 0, 0, 0, 10)
     assert abs(got - np.exp(-10 * 5.0 * pi2 * 2 / 100 ** 2)) < 1e-15
+
+
+def test_counter_summaries_follow_the_code_not_its_comments(tmp_path):
+    """bench.py uses a committed counter summary only while the step kernels'
+    code is what the counters were taken on: a comment or layout edit keeps
+    the hash, any code change moves it; the committed summaries match."""
+    sys.path.insert(0, ROOT)
+    import bench
+    paths = []
+    for p in bench.KERNEL_SRC:
+        q = tmp_path / os.path.basename(p)
+        with open(p, encoding="utf-8") as f:
+            q.write_text(f.read())
+        paths.append(str(q))
+    base = bench.kernel_hash(paths)
+    assert base == bench.kernel_hash()
+    src = open(paths[1], encoding="utf-8").read()
+    open(paths[1], "w", encoding="utf-8").write("// a note\n/* and\n another */\n" +
+                                                src.replace("\n", "\n\n", 3))
+    assert bench.kernel_hash(paths) == base
+    open(paths[1], "w", encoding="utf-8").write(src.replace("pitch * ny + 2112;", "pitch * ny + 2176;"))
+    assert bench.kernel_hash(paths) != base
+    assert bench.measured_traffic("k_batch_step_traffic.json", "sweep256") is not None
