@@ -657,11 +657,12 @@ __device__ void march_interior(const StepArgs<real>& a, int lane, int i, int j0,
 // stay in one L2: below kXcdChunkFrom blocks each XCD takes one contiguous
 // eighth of the grid, from it on the XCDs take turns in chunks of
 // kXcdChunk blocks.  Measured (contiguous eighths / chunks of 64 / the plain
-// order): the 256-cavity sweep (51 k blocks) 0.957 / 0.935 / 1.016 ms,
-// 4096^2 (17 k) 321 / 313 / 336 us, 2048^2 (4.4 k) 85.6 / 90.7 / 94.6 us,
-// 512^2 (1.2 k) 6.7 / 7.4 / 9.7 us.
+// order): the 256-cavity sweep (53 k blocks) 0.957 / 0.935 / 1.016 ms,
+// 4096^2 (17 k) 321 / 313 / 336 us, 3072^2 (9.6 k) 185.7 / 182.3 us, 2560^2
+// (6.7 k) 131.3 / 132.9 us, 2048^2 (4.4 k) 85.6 / 90.7 / 94.6 us, 512^2
+// (1.2 k) 6.7 / 7.4 / 9.7 us.
 constexpr int kXcdChunk = 64;
-constexpr int kXcdChunkFrom = 16384;
+constexpr int kXcdChunkFrom = 8192;
 __device__ __forceinline__ int xcd_order(int b, int nb) {
   if (nb >= kXcdChunkFrom) {
     const int full = nb / (8 * kXcdChunk) * (8 * kXcdChunk);
